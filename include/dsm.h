@@ -1,0 +1,175 @@
+/*
+ * dsm.h -- C ABI of libdsm: GPU (gfx950) evaluation of the objectives and
+ * constraints of multi-objective dual simplex-mesh deformable registration
+ * (Andreadis, Bosman, Alderliesten, "Multi-Objective Dual Simplex-Mesh Based
+ * Deformable Image Registration for 3D Medical Images -- Proof of Concept").
+ *
+ * A problem holds a source ("moving") and a target ("fixed") image of equal
+ * dimensions and two coupled tetrahedral meshes of the same topology, one per
+ * image (Sec. 2.1: dual-dynamic grid model; each cube of 8 grid points split
+ * into 6 tetrahedra, cubes mirrored in 2x2x2 groups).  A solution is the
+ * coordinates of all points of both meshes; a population of S solutions is
+ * evaluated at once, in full or partially per FOS element (Sec. 2.2, 2.3).
+ *
+ * Conventions shared by every entry point
+ *   - Images are float32 [Dz][Dy][Dx], x fastest.  Voxel (i,j,k) has its centre
+ *     at (i,j,k) in voxel units; each mesh spans the box [-0.5, D-0.5].
+ *   - Grid point (i,j,k) has index i + nx*(j + ny*k).  Grid 0 is the source
+ *     (moving) grid, grid 1 the target (fixed) grid.
+ *   - Coordinates are float32 voxel units on the 1/128-voxel lattice:
+ *     (x + 0.5) * 128 must be an integer in [0, 128*D].  Off-lattice,
+ *     out-of-box or non-finite values are reported as flag bits, never read as
+ *     addresses.
+ *   - A population X is float32 [S][2][P][3] (solution, grid, point, xyz).
+ *   - "dev" pointers are device memory of the current HIP device, owned by the
+ *     caller and kept alive until the work enqueued on `stream` has finished;
+ *     "host" pointers are read during the call only.  The library never frees
+ *     caller memory.
+ *   - Every evaluation call only enqueues work on `stream` (a hipStream_t;
+ *     NULL = the null stream) and returns: no host synchronisation, no
+ *     allocation after dsm_problem_create, so the calls can be captured in a
+ *     HIP graph.  Calls on one problem must not run concurrently on different
+ *     streams (they share the problem's workspace).
+ *   - Errors: every function returns a dsm_status; nothing throws across the
+ *     ABI.  Host-detectable errors (null pointers, sizes, capacities) are
+ *     returned before anything is enqueued.  Errors in device-resident values
+ *     become flag bits of the affected solution; objectives of flagged entries
+ *     are unspecified.  dsm_last_error() gives a thread-local message.
+ */
+#ifndef DSM_H
+#define DSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dsm_status;
+#define DSM_OK 0
+#define DSM_ERR_ARG 1         /* null pointer, bad shape or size */
+#define DSM_ERR_CAPACITY 2    /* S / F / FOS size above the create-time maximum */
+#define DSM_ERR_DOMAIN 3      /* geometry outside what the exact predicates support */
+#define DSM_ERR_DEVICE 4      /* HIP runtime error (no device, launch failure) */
+#define DSM_ERR_NOMEM 5       /* device allocation failed at create */
+#define DSM_ERR_UNSUPPORTED 6
+
+/* Constraint flag bits of a solution or candidate (Sec. 2.3.4: no grid
+ * folding; border points stay on their border).  Folding is tested exactly:
+ * a tetrahedron is folded iff its orientation determinant is <= 0. */
+#define DSM_FLAG_INV_MOVING 1u  /* a tetrahedron of the source grid is inverted or flat */
+#define DSM_FLAG_INV_FIXED 2u   /* a tetrahedron of the target grid is inverted or flat */
+#define DSM_FLAG_BORDER 4u      /* a border point left its border plane */
+#define DSM_FLAG_DOMAIN 8u      /* a coordinate lies outside the image box */
+#define DSM_FLAG_LATTICE 16u    /* a coordinate is not on the 1/128-voxel lattice */
+#define DSM_FLAG_NONFINITE 32u  /* a coordinate is NaN or infinite */
+#define DSM_FLAG_BAD_FOS 64u    /* FOS element malformed (point index, size) */
+
+const char* dsm_status_string(dsm_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* dsm_last_error(void);
+
+typedef struct dsm_problem dsm_problem;
+
+typedef struct {
+  int32_t dims[3];          /* Dx, Dy, Dz: 2 <= D <= 512 */
+  float spacing_mm[3];      /* voxel spacing, > 0 */
+  const float* moving;      /* host [Dz][Dy][Dx] source image (copied) */
+  const float* fixed;       /* host [Dz][Dy][Dx] target image (copied) */
+  int32_t mesh[3];          /* points per axis nx, ny, nz: 2 <= n <= 129 */
+  float empty_tau;          /* a voxel is empty (black) iff its value <= tau (Sec. 2.3.1) */
+  int32_t n_guid_moving;    /* guidance points on the source image (Sec. 2.3.3), may be 0 */
+  int32_t n_guid_fixed;     /* guidance points on the target image */
+  const float* guid_moving; /* host [n][3] voxel units, on the lattice, within [0, D-1] */
+  const float* guid_fixed;
+  const int32_t* corr_moving; /* host [n] correspondence id of each point */
+  const int32_t* corr_fixed;
+  int32_t max_solutions;    /* largest S any later call passes */
+  int32_t max_fos;          /* largest F */
+  int32_t max_fos_points;   /* largest number of points in one FOS element */
+} dsm_problem_desc;
+
+typedef struct {
+  int32_t P, T, E;      /* points per grid, tetrahedra (6 per cube), unique edges */
+  int32_t max_star;     /* most tetrahedra incident to one point */
+  int64_t V;            /* voxels per image */
+  int32_t max_affected; /* capacity of one FOS element's affected set */
+  double norm[3];       /* normalisers: 1/(V_fixed+V_moving), 1/(E+4T), 1/(n_guid_moving+n_guid_fixed) or 0 */
+} dsm_problem_info;
+
+/* Copies the images and guidance to the current device, builds the topology
+ * (Sec. 2.1), the per-point stars (Sec. 2.2) and the workspace for the given
+ * capacities.  Errors: DSM_ERR_ARG for null/invalid fields, DSM_ERR_DOMAIN for
+ * dims/mesh outside the supported range or guidance off the lattice/box,
+ * DSM_ERR_DEVICE / DSM_ERR_NOMEM from the runtime.  *out is NULL on error. */
+dsm_status dsm_problem_create(const dsm_problem_desc* desc, dsm_problem** out);
+dsm_status dsm_problem_destroy(dsm_problem* p);
+dsm_status dsm_problem_query(const dsm_problem* p, dsm_problem_info* out);
+
+/* Host copies of the topology: tets host [T][4] (positively oriented on the
+ * undeformed grid), star_off host [P+1] and star host [4T] (tetrahedra incident
+ * to each point, ascending), identity host [P][3] (undeformed grid on the
+ * lattice).  Any output may be NULL. */
+dsm_status dsm_problem_topology(const dsm_problem* p, int32_t* tets, int32_t* star_off, int32_t* star,
+                                float* identity);
+
+/* Host-only variant of the above for a mesh without a problem (no device
+ * needed): counts host [4] = {P, T, E, max_star}; tets host [T][4];
+ * star_off host [P+1]; star host [4T]; identity host [P][3] for an image of
+ * dims (Dx, Dy, Dz).  Any output may be NULL; query counts first to size them. */
+dsm_status dsm_mesh_topology(const int32_t mesh[3], const int32_t dims[3], int32_t* counts, int32_t* tets,
+                             int32_t* star_off, int32_t* star, float* identity);
+
+/* Sec. 2.3.4 constraint check of whole solutions.
+ * X dev [S][2][P][3]; flags dev [S] (OR of DSM_FLAG_* over all points and all
+ * tetrahedra of both grids); first_bad_tet dev [S] or NULL: lowest folded
+ * tetrahedron id, -1 if none. */
+dsm_status dsm_fold_check(dsm_problem* p, int32_t S, const float* X, uint32_t* flags, int32_t* first_bad_tet,
+                          void* stream);
+
+/* Sec. 2.3: full evaluation of S solutions.
+ * obj dev [S][3] float64: dissimilarity (Sec. 2.3.1, forward + backward, divided
+ * by V_fixed + V_moving), deformation (Sec. 2.3.2, divided by E + 4T),
+ * guidance (Sec. 2.3.3, divided by the number of guidance points).
+ * flags dev [S] as dsm_fold_check.  tet_terms dev [S][T][3] float64 or NULL:
+ * the un-normalised per-tetrahedron terms (the decomposition of Sec. 2.3 that
+ * partial evaluation relies on); pass it to dsm_eval_partial as the cache. */
+dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj, uint32_t* flags, double* tet_terms,
+                         void* stream);
+
+/* Sec. 2.2-2.3: partial evaluation of every (solution, FOS element) pair.
+ * FOS element f holds points fos_pts[fos_off[f] .. fos_off[f+1]) (dev int32,
+ * fos_off dev [F+1]); its candidate coordinates, in both grids, are
+ * cand dev [S][fos_off[F]][2][3].  The affected tetrahedra are the union of the
+ * stars of the element's points.  Outputs, all dev:
+ *   part_new [S][F][3] float64: normalised objective sums over the affected
+ *     tetrahedra with the candidate coordinates;
+ *   part_old [S][F][3] float64: the same sums for the current coordinates, from
+ *     tet_terms_in [S][T][3] (as written by dsm_eval_full) if non-NULL, else
+ *     recomputed; so full(new) = full(old) - part_old + part_new;
+ *   flags [S][F]: constraint bits over the affected tetrahedra and their
+ *     vertices with the candidate applied;
+ *   tet_terms_new [S][T][3] or NULL: candidate terms of the affected
+ *     tetrahedra written in place (other entries untouched); only meaningful
+ *     when the elements' affected sets are pairwise disjoint;
+ *   voxel_count [S][F] uint32 or NULL: voxel samples taken for the candidate.
+ * Errors: DSM_ERR_CAPACITY if S or F exceeds the create-time maximum; a
+ * malformed element (point out of range, more than max_fos_points points)
+ * sets DSM_FLAG_BAD_FOS for that element. */
+dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                            const int32_t* fos_pts, const float* cand, const double* tet_terms_in, double* part_old,
+                            double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
+                            void* stream);
+
+/* Test hook for Sec. 2.3.1 rasterisation: owner dev [Dz][Dy][Dx] int32 receives
+ * the id of the tetrahedron of grid coordinates Xgrid dev [P][3] whose exact
+ * voxel set contains each voxel (-1 if none); overlap dev [1] int32 counts
+ * voxels claimed more than once.  With a feasible mesh every voxel is owned
+ * exactly once. */
+dsm_status dsm_rasterize_owner(dsm_problem* p, const float* Xgrid, int32_t* owner, int32_t* overlap, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSM_H */

@@ -1,0 +1,385 @@
+// C ABI of libdsm: argument validation, problem setup and launch sequencing.
+// Every evaluation entry point validates host-visible arguments, then only
+// enqueues kernels on the caller's stream (no synchronisation, no allocation).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dsm_internal.h"
+
+using namespace dsm;
+
+struct dsm_problem {
+  DevProblem dev{};
+  HostTopology topo;
+  int dims[3]{};
+  int mesh[3]{};
+  int64_t V = 0;
+  int max_S = 0, max_F = 0, max_pts = 0, maxA = 0;
+  int device = 0;
+  // device buffers owned by the problem
+  float* d_img = nullptr;       // [2][V]
+  int* d_tets = nullptr;
+  double* d_tet_w = nullptr;
+  int* d_star_off = nullptr;
+  int* d_star = nullptr;
+  double* d_gpt = nullptr;      // [n_m + n_f][3]
+  int* d_gcorr = nullptr;
+  int* d_aff = nullptr;         // [max_F][maxA]
+  int* d_aff_cnt = nullptr;     // [max_F]
+  double* d_terms = nullptr;    // [max_S][T][3] workspace for full evaluation
+  double* d_simws = nullptr;    // swept dissimilarity per (solution, group, version, tetrahedron)
+  size_t simws_len = 0;
+  std::vector<float> identity;  // [P][3]
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+dsm_status fail(dsm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+dsm_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? DSM_ERR_NOMEM : DSM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <class T>
+hipError_t dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, sizeof(T) * count);
+}
+
+void release(dsm_problem* p) {
+  if (!p) return;
+  void* bufs[] = {p->d_img, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
+                  p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+bool on_lattice(float x, int D, double& u) {
+  if (!isfinite(x)) return false;
+  u = ((double)x + 0.5) * kLat;
+  return u == floor(u) && u >= 0.0 && u <= kLat * D;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dsm_status_string(dsm_status s) {
+  switch (s) {
+    case DSM_OK: return "ok";
+    case DSM_ERR_ARG: return "invalid argument";
+    case DSM_ERR_CAPACITY: return "capacity exceeded";
+    case DSM_ERR_DOMAIN: return "geometry outside the supported domain";
+    case DSM_ERR_DEVICE: return "device error";
+    case DSM_ERR_NOMEM: return "out of device memory";
+    case DSM_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* dsm_last_error(void) { return g_err.c_str(); }
+
+dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
+  g_err.clear();
+  if (!out) return fail(DSM_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!d) return fail(DSM_ERR_ARG, "desc is null");
+  if (!d->moving || !d->fixed) return fail(DSM_ERR_ARG, "image pointer is null");
+  for (int a = 0; a < 3; ++a) {
+    if (d->dims[a] < 2 || d->dims[a] > 512)
+      return fail(DSM_ERR_DOMAIN, "dims[%d] = %d outside [2, 512] (exact lattice predicates need 128*D <= 2^16)", a,
+                  d->dims[a]);
+    if (d->mesh[a] < 2 || d->mesh[a] > 129) return fail(DSM_ERR_DOMAIN, "mesh[%d] = %d outside [2, 129]", a, d->mesh[a]);
+    if (!(d->spacing_mm[a] > 0.0f) || !isfinite(d->spacing_mm[a]))
+      return fail(DSM_ERR_ARG, "spacing_mm[%d] must be positive and finite", a);
+  }
+  if (!isfinite(d->empty_tau)) return fail(DSM_ERR_ARG, "empty_tau must be finite");
+  if (d->n_guid_moving < 0 || d->n_guid_fixed < 0) return fail(DSM_ERR_ARG, "negative guidance count");
+  if ((d->n_guid_moving > 0 && (!d->guid_moving || !d->corr_moving)) ||
+      (d->n_guid_fixed > 0 && (!d->guid_fixed || !d->corr_fixed)))
+    return fail(DSM_ERR_ARG, "guidance pointer is null");
+  if (d->max_solutions < 1 || d->max_fos < 0 || d->max_fos_points < 0)
+    return fail(DSM_ERR_ARG, "capacities must be max_solutions >= 1, max_fos >= 0, max_fos_points >= 0");
+  if (d->max_fos > 0 && d->max_fos_points < 1) return fail(DSM_ERR_ARG, "max_fos_points must be >= 1 when max_fos > 0");
+
+  auto* p = new dsm_problem();
+  for (int a = 0; a < 3; ++a) {
+    p->dims[a] = d->dims[a];
+    p->mesh[a] = d->mesh[a];
+  }
+  if (!build_topology(p->mesh, p->topo)) {
+    release(p);
+    return fail(DSM_ERR_ARG, "bad mesh");
+  }
+  p->V = (int64_t)d->dims[0] * d->dims[1] * d->dims[2];
+  p->max_S = d->max_solutions;
+  p->max_F = d->max_fos;
+  p->max_pts = d->max_fos_points;
+  p->maxA = std::max(1, std::min(p->topo.T, std::max(1, p->max_pts) * p->topo.max_star));
+  p->identity.resize(3 * (size_t)p->topo.P);
+  identity_grid(p->mesh, p->dims, p->identity.data());
+
+  // guidance points: lattice integers, within the voxel-centre range [0, D-1]
+  const int ng[2] = {d->n_guid_moving, d->n_guid_fixed};
+  const float* gsrc[2] = {d->guid_moving, d->guid_fixed};
+  const int32_t* csrc[2] = {d->corr_moving, d->corr_fixed};
+  std::vector<double> gl;
+  std::vector<int> gc;
+  for (int g = 0; g < 2; ++g)
+    for (int i = 0; i < ng[g]; ++i) {
+      for (int a = 0; a < 3; ++a) {
+        double u;
+        const float x = gsrc[g][3 * (size_t)i + a];
+        if (!on_lattice(x, d->dims[a], u) || x < 0.0f || x > (float)(d->dims[a] - 1)) {
+          release(p);
+          return fail(DSM_ERR_DOMAIN, "guidance point %d of image %d is off the lattice or outside [0, D-1]", i, g);
+        }
+        gl.push_back(u);
+      }
+      gc.push_back(csrc[g][i]);
+    }
+  // every correspondence must have a point on both images
+  for (int g = 0; g < 2; ++g)
+    for (int i = 0; i < ng[g]; ++i) {
+      const int c = csrc[g][i];
+      bool found = false;
+      for (int j = 0; j < ng[1 - g] && !found; ++j) found = csrc[1 - g][j] == c;
+      if (!found) {
+        release(p);
+        return fail(DSM_ERR_ARG, "correspondence %d has points on one image only", c);
+      }
+    }
+
+  hipError_t e;
+  if ((e = hipGetDevice(&p->device)) != hipSuccess) {
+    release(p);
+    return hip_fail(e, "hipGetDevice");
+  }
+  const HostTopology& tp = p->topo;
+#define DSM_TRY(expr, what)  \
+  if ((e = (expr)) != hipSuccess) { \
+    release(p);              \
+    return hip_fail(e, what); \
+  }
+  DSM_TRY(dev_alloc(&p->d_img, 2 * (size_t)p->V), "hipMalloc images");
+  DSM_TRY(hipMemcpy(p->d_img, d->moving, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy source image");
+  DSM_TRY(hipMemcpy(p->d_img + p->V, d->fixed, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy target image");
+  DSM_TRY(dev_alloc(&p->d_tets, tp.tets.size()), "hipMalloc tets");
+  DSM_TRY(hipMemcpy(p->d_tets, tp.tets.data(), sizeof(int) * tp.tets.size(), hipMemcpyHostToDevice), "copy tets");
+  DSM_TRY(dev_alloc(&p->d_tet_w, tp.tet_w.size()), "hipMalloc weights");
+  DSM_TRY(hipMemcpy(p->d_tet_w, tp.tet_w.data(), sizeof(double) * tp.tet_w.size(), hipMemcpyHostToDevice), "copy weights");
+  DSM_TRY(dev_alloc(&p->d_star_off, tp.star_off.size()), "hipMalloc star_off");
+  DSM_TRY(hipMemcpy(p->d_star_off, tp.star_off.data(), sizeof(int) * tp.star_off.size(), hipMemcpyHostToDevice),
+          "copy star_off");
+  DSM_TRY(dev_alloc(&p->d_star, tp.star.size()), "hipMalloc star");
+  DSM_TRY(hipMemcpy(p->d_star, tp.star.data(), sizeof(int) * tp.star.size(), hipMemcpyHostToDevice), "copy star");
+  DSM_TRY(dev_alloc(&p->d_gpt, gl.size()), "hipMalloc guidance");
+  if (!gl.empty())
+    DSM_TRY(hipMemcpy(p->d_gpt, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice), "copy guidance");
+  DSM_TRY(dev_alloc(&p->d_gcorr, gc.size()), "hipMalloc correspondences");
+  if (!gc.empty())
+    DSM_TRY(hipMemcpy(p->d_gcorr, gc.data(), sizeof(int) * gc.size(), hipMemcpyHostToDevice), "copy correspondences");
+  DSM_TRY(dev_alloc(&p->d_aff, (size_t)std::max(1, p->max_F) * p->maxA), "hipMalloc affected sets");
+  DSM_TRY(dev_alloc(&p->d_aff_cnt, (size_t)std::max(1, p->max_F)), "hipMalloc affected counts");
+  DSM_TRY(dev_alloc(&p->d_terms, (size_t)p->max_S * tp.T * 3), "hipMalloc term workspace");
+  {
+    const size_t full_groups = (size_t)(tp.T + kFullChunk - 1) / kFullChunk;
+    p->simws_len = std::max((size_t)p->max_S * std::max(1, p->max_F) * 2 * p->maxA,
+                            (size_t)p->max_S * full_groups * kFullChunk);
+  }
+  DSM_TRY(dev_alloc(&p->d_simws, p->simws_len), "hipMalloc sweep workspace");
+#undef DSM_TRY
+
+  DevProblem& dv = p->dev;
+  dv.img[0] = p->d_img;
+  dv.img[1] = p->d_img + p->V;
+  for (int a = 0; a < 3; ++a) {
+    dv.D[a] = p->dims[a];
+    dv.n[a] = p->mesh[a];
+    dv.sp[a] = d->spacing_mm[a];
+  }
+  dv.DxDy = p->dims[0] * p->dims[1];
+  dv.tau = d->empty_tau;
+  dv.P = tp.P;
+  dv.T = tp.T;
+  dv.tets = (const int4*)p->d_tets;
+  dv.tet_w = p->d_tet_w;
+  dv.star_off = p->d_star_off;
+  dv.star = p->d_star;
+  dv.ng[0] = ng[0];
+  dv.ng[1] = ng[1];
+  dv.gpt[0] = p->d_gpt;
+  dv.gpt[1] = p->d_gpt + 3 * (size_t)ng[0];
+  dv.gcorr[0] = p->d_gcorr;
+  dv.gcorr[1] = p->d_gcorr + ng[0];
+  dv.norm[0] = 1.0 / (2.0 * (double)p->V);
+  dv.norm[1] = 1.0 / (double)(tp.E + 4 * tp.T);
+  dv.norm[2] = (ng[0] + ng[1]) > 0 ? 1.0 / (double)(ng[0] + ng[1]) : 0.0;
+
+  // the evaluation kernel's dynamic LDS must fit one workgroup
+  const size_t lds = std::max(eval_lds_bytes(p->maxA, 2), eval_lds_bytes(kFullChunk, 1));
+  if (lds > 64 * 1024) {
+    release(p);
+    return fail(DSM_ERR_CAPACITY, "max_fos_points too large: affected set of %d tetrahedra needs %zu B of LDS", p->maxA,
+                lds);
+  }
+  *out = p;
+  return DSM_OK;
+}
+
+dsm_status dsm_problem_destroy(dsm_problem* p) {
+  g_err.clear();
+  if (!p) return fail(DSM_ERR_ARG, "problem is null");
+  release(p);
+  return DSM_OK;
+}
+
+dsm_status dsm_problem_query(const dsm_problem* p, dsm_problem_info* out) {
+  g_err.clear();
+  if (!p || !out) return fail(DSM_ERR_ARG, "null argument");
+  out->P = p->topo.P;
+  out->T = p->topo.T;
+  out->E = p->topo.E;
+  out->max_star = p->topo.max_star;
+  out->V = p->V;
+  out->max_affected = p->maxA;
+  for (int c = 0; c < 3; ++c) out->norm[c] = p->dev.norm[c];
+  return DSM_OK;
+}
+
+dsm_status dsm_problem_topology(const dsm_problem* p, int32_t* tets, int32_t* star_off, int32_t* star,
+                                float* identity) {
+  g_err.clear();
+  if (!p) return fail(DSM_ERR_ARG, "problem is null");
+  if (tets) memcpy(tets, p->topo.tets.data(), sizeof(int) * p->topo.tets.size());
+  if (star_off) memcpy(star_off, p->topo.star_off.data(), sizeof(int) * p->topo.star_off.size());
+  if (star) memcpy(star, p->topo.star.data(), sizeof(int) * p->topo.star.size());
+  if (identity) memcpy(identity, p->identity.data(), sizeof(float) * p->identity.size());
+  return DSM_OK;
+}
+
+dsm_status dsm_mesh_topology(const int32_t mesh[3], const int32_t dims[3], int32_t* counts, int32_t* tets,
+                             int32_t* star_off, int32_t* star, float* identity) {
+  g_err.clear();
+  if (!mesh) return fail(DSM_ERR_ARG, "mesh is null");
+  const int m[3] = {mesh[0], mesh[1], mesh[2]};
+  for (int a = 0; a < 3; ++a)
+    if (m[a] < 2 || m[a] > 129) return fail(DSM_ERR_DOMAIN, "mesh[%d] = %d outside [2, 129]", a, m[a]);
+  HostTopology tp;
+  if (!build_topology(m, tp)) return fail(DSM_ERR_ARG, "bad mesh");
+  if (counts) {
+    counts[0] = tp.P;
+    counts[1] = tp.T;
+    counts[2] = tp.E;
+    counts[3] = tp.max_star;
+  }
+  if (tets) memcpy(tets, tp.tets.data(), sizeof(int) * tp.tets.size());
+  if (star_off) memcpy(star_off, tp.star_off.data(), sizeof(int) * tp.star_off.size());
+  if (star) memcpy(star, tp.star.data(), sizeof(int) * tp.star.size());
+  if (identity) {
+    if (!dims) return fail(DSM_ERR_ARG, "dims is null");
+    const int d[3] = {dims[0], dims[1], dims[2]};
+    for (int a = 0; a < 3; ++a)
+      if (d[a] < 2 || d[a] > 512) return fail(DSM_ERR_DOMAIN, "dims[%d] = %d outside [2, 512]", a, d[a]);
+    identity_grid(m, d, identity);
+  }
+  return DSM_OK;
+}
+
+dsm_status dsm_fold_check(dsm_problem* p, int32_t S, const float* X, uint32_t* flags, int32_t* first_bad_tet,
+                          void* stream) {
+  g_err.clear();
+  if (!p || !X || !flags) return fail(DSM_ERR_ARG, "null argument");
+  if (S < 0) return fail(DSM_ERR_ARG, "S < 0");
+  if (S == 0) return DSM_OK;
+  const hipError_t e = launch_fold(p->dev, S, X, flags, first_bad_tet, (hipStream_t)stream);
+  return e == hipSuccess ? DSM_OK : hip_fail(e, "fold check launch");
+}
+
+dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj, uint32_t* flags, double* tet_terms,
+                         void* stream) {
+  g_err.clear();
+  if (!p || !X || !obj || !flags) return fail(DSM_ERR_ARG, "null argument");
+  if (S < 0) return fail(DSM_ERR_ARG, "S < 0");
+  if (S == 0) return DSM_OK;
+  if (S > p->max_S) return fail(DSM_ERR_CAPACITY, "S = %d exceeds max_solutions = %d", S, p->max_S);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_fold(p->dev, S, X, flags, nullptr, st);
+  if (e != hipSuccess) return hip_fail(e, "fold check launch");
+  EvalArgs a{};
+  a.pr = p->dev;
+  a.S = S;
+  a.G = (p->topo.T + kFullChunk - 1) / kFullChunk;
+  a.partial = 0;
+  a.X = X;
+  a.maxA = kFullChunk;
+  a.nver = 1;
+  a.terms_out = tet_terms ? tet_terms : p->d_terms;
+  if ((e = launch_eval(a, p->d_simws, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  if ((e = launch_full_reduce(p->dev, S, a.terms_out, obj, st)) != hipSuccess) return hip_fail(e, "reduce launch");
+  return DSM_OK;
+}
+
+dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                            const int32_t* fos_pts, const float* cand, const double* tet_terms_in, double* part_old,
+                            double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
+                            void* stream) {
+  g_err.clear();
+  if (!p || !X || !fos_off || !fos_pts || !cand || !part_old || !part_new || !flags)
+    return fail(DSM_ERR_ARG, "null argument");
+  if (S < 0 || F < 0) return fail(DSM_ERR_ARG, "negative S or F");
+  if (S > p->max_S) return fail(DSM_ERR_CAPACITY, "S = %d exceeds max_solutions = %d", S, p->max_S);
+  if (F > p->max_F) return fail(DSM_ERR_CAPACITY, "F = %d exceeds max_fos = %d", F, p->max_F);
+  if (S == 0 || F == 0) return DSM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_affected(p->dev, F, fos_off, fos_pts, p->max_pts, p->maxA, p->d_aff, p->d_aff_cnt, st);
+  if (e != hipSuccess) return hip_fail(e, "affected-set launch");
+  EvalArgs a{};
+  a.pr = p->dev;
+  a.S = S;
+  a.G = F;
+  a.partial = 1;
+  a.X = X;
+  a.fos_off = fos_off;
+  a.fos_pts = fos_pts;
+  a.cand = cand;
+  a.aff = p->d_aff;
+  a.aff_cnt = p->d_aff_cnt;
+  a.maxA = p->maxA;
+  a.nver = tet_terms_in ? 1 : 2;
+  a.terms_in = tet_terms_in;
+  a.part_old = part_old;
+  a.part_new = part_new;
+  a.flags = flags;
+  a.terms_out = tet_terms_new;
+  a.vcount = voxel_count;
+  if ((e = launch_eval(a, p->d_simws, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  return DSM_OK;
+}
+
+dsm_status dsm_rasterize_owner(dsm_problem* p, const float* Xgrid, int32_t* owner, int32_t* overlap, void* stream) {
+  g_err.clear();
+  if (!p || !Xgrid || !owner || !overlap) return fail(DSM_ERR_ARG, "null argument");
+  const hipError_t e = launch_owner(p->dev, Xgrid, owner, overlap, (hipStream_t)stream);
+  return e == hipSuccess ? DSM_OK : hip_fail(e, "owner launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/dsm.h"
+
+namespace dsm {
+
+constexpr int kWG = 256;          // threads per workgroup of the evaluation kernels
+constexpr int kWaves = kWG / 64;  // wave64 waves per workgroup
+constexpr double kLat = 128.0;    // lattice steps per voxel
+constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
+
+// Everything a kernel needs to know about one problem (passed by value).
+struct DevProblem {
+  const float* img[2];   // [0] source (moving), [1] target (fixed); [Dz][Dy][Dx]
+  int D[3];
+  int DxDy;
+  float tau;             // empty iff value <= tau
+  double sp[3];          // voxel spacing in mm
+  int n[3];              // points per axis
+  int P, T;
+  const int4* tets;      // [T] vertex ids, positively oriented on the undeformed grid
+  const double* tet_w;   // [T][6] 1/k_e of the edges 01 02 03 12 13 23
+  const int* star_off;   // [P+1]
+  const int* star;       // [4T]
+  int ng[2];             // guidance points per image
+  const double* gpt[2];  // [ng][3] lattice units
+  const int* gcorr[2];   // [ng] correspondence ids
+  double norm[3];        // objective normalisers
+};
+
+struct EvalArgs {
+  DevProblem pr;
+  int S;                 // solutions
+  int G;                 // groups: FOS elements (partial) or tetrahedron chunks (full)
+  int partial;           // 1: partial evaluation, 0: full evaluation
+  const float* X;        // [S][2][P][3]
+  const int* fos_off;    // partial only
+  const int* fos_pts;
+  const float* cand;     // [S][fos_off[G]][2][3]
+  const int* aff;        // [G][maxA] affected tetrahedra, ascending
+  const int* aff_cnt;    // [G], -1 = malformed element
+  int maxA;
+  int nver;              // 1: candidate only; 2: candidate and current recomputed
+  const double* terms_in;  // [S][T][3] cache of current terms or null
+  double* part_old;      // [S][G][3]
+  double* part_new;
+  uint32_t* flags;       // [S][G]
+  double* terms_out;     // [S][T][3] or null
+  uint32_t* vcount;      // [S][G] or null
+};
+
+// Host-side topology (topology.cpp).
+struct HostTopology {
+  int P = 0, C = 0, T = 0, E = 0, max_star = 0;
+  std::vector<int> tets;      // [T][4]
+  std::vector<double> tet_w;  // [T][6]
+  std::vector<int> star_off;  // [P+1]
+  std::vector<int> star;      // [4T]
+};
+bool build_topology(const int mesh[3], HostTopology& out);
+void identity_grid(const int mesh[3], const int dims[3], float* X);
+
+// Kernel launchers (kernels.hip).  All enqueue on `stream` and return the
+// launch status.
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* flags, int32_t* first_bad,
+                       hipStream_t stream);
+hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
+                           int maxA, int* aff, int* aff_cnt, hipStream_t stream);
+hipError_t launch_eval(const EvalArgs& a, double* simws, hipStream_t stream);
+hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
+hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
+size_t eval_lds_bytes(int maxA, int nver);
+
+}  // namespace dsm

@@ -1,0 +1,915 @@
+// gfx950 kernels of the dual simplex-mesh objective evaluator.
+//
+// Work decomposition (Sec. 2.2: the affected tetrahedra of a partial change
+// are re-evaluated; Sec. 2.3: every objective is a sum of per-cell terms):
+//   one workgroup per (FOS element, solution) in partial evaluation, or per
+//   (chunk of tetrahedra, solution) in full evaluation.  Its work units are
+//   (version, direction, tetrahedron, batch of 64 voxel rows); the 4 waves take
+//   the units round robin.  A wave computes the exact x-span of 64 rows (one
+//   row per lane), prefix-sums the span lengths, and then sweeps the voxels of
+//   those rows 64 at a time, adjacent lanes on adjacent voxels, so that both
+//   the streamed own-image reads and the trilinear gathers from the other
+//   image are coalesced.
+//
+// Exactness: coordinates are lattice integers (1/128 voxel, |u| <= 2^16), so
+// every orientation value and every face function evaluated at a voxel centre
+// is an integer below 2^53 and FP64 arithmetic on it is exact; the voxel set of
+// a tetrahedron is therefore decided bit-exactly.  Sampling and the
+// dissimilarity sum are FP32 (per-lane compensated sums, FP64 across lanes).
+#include <hip/hip_runtime.h>
+
+#include "dsm_internal.h"
+
+namespace dsm {
+
+namespace {
+
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Lattice value of one coordinate and its constraint bits.
+__device__ __forceinline__ unsigned lattice_of(float x, int D, double& u) {
+  if (!isfinite(x)) {
+    u = 0.0;
+    return DSM_FLAG_NONFINITE;
+  }
+  const double v = ((double)x + 0.5) * kLat;
+  u = v;
+  if (v != floor(v)) return DSM_FLAG_LATTICE;
+  if (v < 0.0 || v > kLat * D) return DSM_FLAG_DOMAIN;
+  return 0u;
+}
+
+// 6 x signed volume of (a, b, c, d); exact for lattice integers.
+__device__ __forceinline__ double orient(const double a[3], const double b[3], const double c[3], const double d[3]) {
+  const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  const double v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+  const double w[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
+  const double cx = v[1] * w[2] - v[2] * w[1];
+  const double cy = v[2] * w[0] - v[0] * w[2];
+  const double cz = v[0] * w[1] - v[1] * w[0];
+  return u[0] * cx + u[1] * cy + u[2] * cz;
+}
+
+// Face functions of a positively oriented tetrahedron: o_i(U) = G_i . U + K_i
+// is the orientation with vertex i replaced by U (zero on the face opposite i,
+// vol at vertex i).  U lies in the tetrahedron iff o_i(U) >= thr_i for all i,
+// where thr_i = 0 if the first non-zero component of G_i (x, then y, then z) is
+// positive and 1 otherwise: the top-left rule of Sec. 2.3.1 extended to 3-D by
+// perturbing U by (+e, +e^2, +e^3).
+struct Faces {
+  double G[4][3];
+  double K[4];
+  int thr[4];
+};
+
+__device__ __forceinline__ void make_faces(const double L[4][3], Faces& f) {
+  for (int i = 0; i < 4; ++i) {
+    const int j = i == 0 ? 1 : 0;
+    const int k = i <= 1 ? 2 : 1;
+    const int l = i <= 2 ? 3 : 2;
+    const double a[3] = {L[k][0] - L[j][0], L[k][1] - L[j][1], L[k][2] - L[j][2]};
+    const double b[3] = {L[l][0] - L[j][0], L[l][1] - L[j][1], L[l][2] - L[j][2]};
+    double g[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double d[3] = {L[i][0] - L[j][0], L[i][1] - L[j][1], L[i][2] - L[j][2]};
+    if (dot3(g, d) < 0.0) {
+      g[0] = -g[0];
+      g[1] = -g[1];
+      g[2] = -g[2];
+    }
+    for (int c = 0; c < 3; ++c) f.G[i][c] = g[c];
+    f.K[i] = -dot3(g, L[j]);
+    const bool pos = g[0] != 0.0 ? g[0] > 0.0 : (g[1] != 0.0 ? g[1] > 0.0 : g[2] > 0.0);
+    f.thr[i] = pos ? 0 : 1;
+  }
+}
+
+__device__ __forceinline__ bool inside(const Faces& f, const double U[3], double o[4]) {
+  bool in = true;
+  for (int i = 0; i < 4; ++i) {
+    o[i] = dot3(f.G[i], U) + f.K[i];
+    in = in && (o[i] >= (double)f.thr[i]);
+  }
+  return in;
+}
+
+// inclusive voxel index range of lattice interval [lo, hi] (voxel i centred at 128 i + 64)
+__device__ __forceinline__ void vox_range(double lo, double hi, int D, int& a, int& b) {
+  a = max(0, (int)ceil((lo - 64.0) / kLat));
+  b = min(D - 1, (int)floor((hi - 64.0) / kLat));
+}
+
+// Blockid -> logical index so that each of the 8 XCDs (which receive
+// workgroups round robin) processes one contiguous range of logical indices;
+// consecutive logical indices share a FOS element and hence an image region.
+__device__ __forceinline__ int xcd_logical(int bid, int n) {
+  const int x = bid & 7, k = bid >> 3;
+  const int q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
+// Makes LDS writes of some lanes visible to the other lanes of the same wave
+// (and keeps the compiler from moving LDS accesses across this point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// Parameters of one (tetrahedron, direction) for rasterising the own grid's
+// voxels and mapping them into the other grid.  Lives in wave-private LDS.
+struct RasterTet {
+  double A[4], C0[4], CY[4], CZ[4], rA[4];  // o_i(x,y,z) = A x + C0 + CY y + CZ z at voxel (x,y,z)
+  double J[3][3];  // own voxel coords -> other grid voxel coords: p' = P0 + J v
+  double P0[3];
+  int thr[4];
+  int zlo, ylo, ny, nrows;
+};
+
+// Fills rt for the tetrahedron with own-grid vertices xo[4][3] and other-grid
+// vertices xt[4][3] (voxel units, already validated on the lattice); the work
+// is spread over lanes so that no lane holds all of it in registers.
+__device__ void setup_raster(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
+  if (lane < 4) {
+    // face opposite vertex `lane`
+    const int i = lane;
+    const int j = i == 0 ? 1 : 0, k = i <= 1 ? 2 : 1, l = i <= 2 ? 3 : 2;
+    double Lj[3], a[3], b[3], d[3];
+    for (int c = 0; c < 3; ++c) {
+      Lj[c] = ((double)xo[3 * j + c] + 0.5) * kLat;
+      a[c] = ((double)xo[3 * k + c] + 0.5) * kLat - Lj[c];
+      b[c] = ((double)xo[3 * l + c] + 0.5) * kLat - Lj[c];
+      d[c] = ((double)xo[3 * i + c] + 0.5) * kLat - Lj[c];
+    }
+    double g[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    if (dot3(g, d) < 0.0) {
+      g[0] = -g[0];
+      g[1] = -g[1];
+      g[2] = -g[2];
+    }
+    const double K = -dot3(g, Lj);
+    rt.A[i] = kLat * g[0];
+    rt.CY[i] = kLat * g[1];
+    rt.CZ[i] = kLat * g[2];
+    rt.C0[i] = 64.0 * (g[0] + g[1] + g[2]) + K;
+    rt.rA[i] = g[0] != 0.0 ? 1.0 / (kLat * g[0]) : 0.0;
+    const bool pos = g[0] != 0.0 ? g[0] > 0.0 : (g[1] != 0.0 ? g[1] > 0.0 : g[2] > 0.0);
+    rt.thr[i] = pos ? 0 : 1;
+  } else if (lane < 13) {
+    // J[r][c] = sum_k Oedge[r][k] * 128 adj(M)[k][c] / vol, M = own edge matrix (lattice)
+    const int r = (lane - 4) / 3, c = (lane - 4) % 3;
+    double m[3][3];
+    for (int rr = 0; rr < 3; ++rr)
+      for (int cc = 0; cc < 3; ++cc) m[rr][cc] = ((double)xo[3 * (cc + 1) + rr] - (double)xo[rr]) * kLat;
+    const double vol = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                       m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+    // column c of adj(M): cofactors of row c of M
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    double adj[3];
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+      adj[k] = m[c1][k1] * m[c2][k2] - m[c1][k2] * m[c2][k1];
+    }
+    double acc = 0.0;
+    for (int k = 0; k < 3; ++k) acc += ((double)xt[3 * (k + 1) + r] - (double)xt[r]) * adj[k];
+    rt.J[r][c] = vol > 0.0 ? acc * kLat / vol : 0.0;
+  } else if (lane == 13) {
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = hi[c] = xo[c];
+      for (int q = 1; q < 4; ++q) {
+        lo[c] = fmin(lo[c], (double)xo[3 * q + c]);
+        hi[c] = fmax(hi[c], (double)xo[3 * q + c]);
+      }
+    }
+    int za, zb, ya, yb;
+    vox_range((lo[2] + 0.5) * kLat, (hi[2] + 0.5) * kLat, D[2], za, zb);
+    vox_range((lo[1] + 0.5) * kLat, (hi[1] + 0.5) * kLat, D[1], ya, yb);
+    rt.zlo = za;
+    rt.ylo = ya;
+    rt.ny = max(0, yb - ya + 1);
+    rt.nrows = rt.ny * max(0, zb - za + 1);
+  }
+  wave_sync();
+  if (lane < 3) {
+    const int r = lane;
+    rt.P0[r] = (double)xt[r] - (rt.J[r][0] * (double)xo[0] + rt.J[r][1] * (double)xo[1] + rt.J[r][2] * (double)xo[2]);
+  }
+  wave_sync();
+}
+
+// Exact x-span [x0, x1] (inclusive; empty if x0 > x1) of voxel row (y, z).
+__device__ __forceinline__ void row_span(const RasterTet& rt, int y, int z, int Dx, int& x0, int& x1) {
+  int lo = 0, hi = Dx - 1;
+  for (int i = 0; i < 4; ++i) {
+    const double A = rt.A[i];
+    // need A x + B >= thr  <=>  A x >= c
+    const double c = (double)rt.thr[i] - (rt.C0[i] + rt.CY[i] * y + rt.CZ[i] * z);
+    if (A > 0.0) {
+      const double q = fmin(fmax(c * rt.rA[i], -2.0), (double)Dx + 1.0);
+      int x = (int)ceil(q);
+      if (A * (x - 1) >= c)
+        x -= 1;
+      else if (A * x < c)
+        x += 1;
+      lo = max(lo, x);
+    } else if (A < 0.0) {
+      const double q = fmin(fmax(c * rt.rA[i], -2.0), (double)Dx + 1.0);
+      int x = (int)floor(q);
+      if (A * (x + 1) >= c)
+        x += 1;
+      else if (A * x < c)
+        x -= 1;
+      hi = min(hi, x);
+    } else if (c > 0.0) {
+      lo = Dx;
+      hi = -1;
+    }
+  }
+  x0 = lo;
+  x1 = hi;
+}
+
+struct WaveRows {
+  int start[64];  // exclusive prefix of span lengths
+  int lin[64];    // own-image linear index of the span's first voxel
+  float bx[64], by[64], bz[64];  // mapped position of the span's first voxel
+};
+
+// Computes the spans of rows [64 b, 64 b + 64) of rt into wr; returns the
+// number of voxels.  Row r = y-major within a slice: y = ylo + r % ny.
+__device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int DxDy,
+                                          WaveRows& wr) {
+  const int r = b * 64 + lane;
+  int len = 0, lin = 0;
+  float bx = 0.f, by = 0.f, bz = 0.f;
+  if (r < rt.nrows) {
+    const int y = rt.ylo + r % rt.ny;
+    const int z = rt.zlo + r / rt.ny;
+    int x0, x1;
+    row_span(rt, y, z, D[0], x0, x1);
+    if (x1 >= x0) {
+      len = x1 - x0 + 1;
+      lin = z * DxDy + y * D[0] + x0;
+      const double v[3] = {(double)x0, (double)y, (double)z};
+      bx = (float)(rt.P0[0] + rt.J[0][0] * v[0] + rt.J[0][1] * v[1] + rt.J[0][2] * v[2]);
+      by = (float)(rt.P0[1] + rt.J[1][0] * v[0] + rt.J[1][1] * v[1] + rt.J[1][2] * v[2]);
+      bz = (float)(rt.P0[2] + rt.J[2][0] * v[0] + rt.J[2][1] * v[1] + rt.J[2][2] * v[2]);
+    }
+  }
+  const int incl = wave_incl_scan(len, lane);
+  wave_sync();
+  wr.start[lane] = incl - len;
+  wr.lin[lane] = lin;
+  wr.bx[lane] = bx;
+  wr.by[lane] = by;
+  wr.bz[lane] = bz;
+  wave_sync();
+  return __shfl(incl, 63, 64);
+}
+
+// largest r with start[r] <= q
+__device__ __forceinline__ int find_row(const WaveRows& wr, int q) {
+  int r = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1)
+    if (wr.start[r + step] <= q) r += step;
+  return r;
+}
+
+// Sec. 2.3.1 contribution of a voxel pair: squared intensity difference, and
+// the maximal difference 1 where an empty voxel meets a non-empty one; the
+// empty indicator of the sampled position is interpolated like the intensity.
+__device__ __forceinline__ float sample_contrib(const float* __restrict__ oth, int Dx, int DxDy, float Dxm, float Dym,
+                                                float Dzm, int Dxm2, int Dym2, int Dzm2, float tau, float a, float px,
+                                                float py, float pz) {
+  px = fminf(fmaxf(px, 0.f), Dxm);
+  py = fminf(fmaxf(py, 0.f), Dym);
+  pz = fminf(fmaxf(pz, 0.f), Dzm);
+  const int ix = min((int)px, Dxm2), iy = min((int)py, Dym2), iz = min((int)pz, Dzm2);
+  const float fx = px - (float)ix, fy = py - (float)iy, fz = pz - (float)iz;
+  const float* p0 = oth + (iz * DxDy + iy * Dx + ix);
+  const float* p1 = p0 + DxDy;
+  const float v000 = p0[0], v100 = p0[1], v010 = p0[Dx], v110 = p0[Dx + 1];
+  const float v001 = p1[0], v101 = p1[1], v011 = p1[Dx], v111 = p1[Dx + 1];
+  const float e000 = v000 <= tau ? 1.f : 0.f, e100 = v100 <= tau ? 1.f : 0.f;
+  const float e010 = v010 <= tau ? 1.f : 0.f, e110 = v110 <= tau ? 1.f : 0.f;
+  const float e001 = v001 <= tau ? 1.f : 0.f, e101 = v101 <= tau ? 1.f : 0.f;
+  const float e011 = v011 <= tau ? 1.f : 0.f, e111 = v111 <= tau ? 1.f : 0.f;
+  const float i00 = fmaf(fx, v100 - v000, v000), i10 = fmaf(fx, v110 - v010, v010);
+  const float i01 = fmaf(fx, v101 - v001, v001), i11 = fmaf(fx, v111 - v011, v011);
+  const float i0 = fmaf(fy, i10 - i00, i00), i1 = fmaf(fy, i11 - i01, i01);
+  const float b = fmaf(fz, i1 - i0, i0);
+  const float m00 = fmaf(fx, e100 - e000, e000), m10 = fmaf(fx, e110 - e010, e010);
+  const float m01 = fmaf(fx, e101 - e001, e001), m11 = fmaf(fx, e111 - e011, e011);
+  const float m0 = fmaf(fy, m10 - m00, m00), m1 = fmaf(fy, m11 - m01, m01);
+  const float eb = fmaf(fz, m1 - m0, m0);
+  const float ea = a <= tau ? 1.f : 0.f;
+  const float m = fabsf(ea - eb);
+  const float d = a - b;
+  return fmaf(1.f - m, d * d, m);
+}
+
+__device__ __forceinline__ double len_mm(const double sp[3], const double a[3], const double b[3]) {
+  const double dx = (a[0] - b[0]) * sp[0], dy = (a[1] - b[1]) * sp[1], dz = (a[2] - b[2]) * sp[2];
+  return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// Sec. 2.3.2: deformation term of one tetrahedron (edges weighted 1/k_e, plus
+// the spoke from each vertex to the centroid of its opposite face); squared
+// length differences in mm between the two grids.
+__device__ double deformation_term(const DevProblem& pr, int t, const double S[4][3], const double Tg[4][3]) {
+  const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
+  double acc = 0.0;
+  for (int e = 0; e < 6; ++e) {
+    const double d = len_mm(pr.sp, S[pa[e]], S[pb[e]]) - len_mm(pr.sp, Tg[pa[e]], Tg[pb[e]]);
+    acc += pr.tet_w[6 * t + e] * d * d;
+  }
+  for (int q = 0; q < 4; ++q) {
+    double cs[3] = {0, 0, 0}, ct[3] = {0, 0, 0};
+    for (int r = 0; r < 4; ++r)
+      if (r != q)
+        for (int c = 0; c < 3; ++c) {
+          cs[c] += S[r][c];
+          ct[c] += Tg[r][c];
+        }
+    for (int c = 0; c < 3; ++c) {
+      cs[c] /= 3.0;
+      ct[c] /= 3.0;
+    }
+    const double d = len_mm(pr.sp, S[q], cs) - len_mm(pr.sp, Tg[q], ct);
+    acc += d * d;
+  }
+  return acc;
+}
+
+// Sec. 2.3.3: guidance points of image g inside tetrahedron (grid g) are mapped
+// into the other image and contribute the squared mm distance to the nearest
+// point of the same correspondence there.
+__device__ double guidance_term(const DevProblem& pr, const double L[2][4][3], const double V[2][4][3]) {
+  double acc = 0.0;
+  for (int g = 0; g < 2; ++g) {
+    if (pr.ng[g] == 0) continue;
+    const double vol = orient(L[g][0], L[g][1], L[g][2], L[g][3]);
+    if (!(vol > 0.0)) continue;
+    Faces f;
+    make_faces(L[g], f);
+    for (int i = 0; i < pr.ng[g]; ++i) {
+      const double U[3] = {pr.gpt[g][3 * i], pr.gpt[g][3 * i + 1], pr.gpt[g][3 * i + 2]};
+      double o[4];
+      if (!inside(f, U, o)) continue;
+      double x[3] = {0, 0, 0};
+      for (int q = 0; q < 4; ++q)
+        for (int c = 0; c < 3; ++c) x[c] += o[q] / vol * V[1 - g][q][c];
+      double best = INFINITY;
+      const int corr = pr.gcorr[g][i];
+      for (int j = 0; j < pr.ng[1 - g]; ++j) {
+        if (pr.gcorr[1 - g][j] != corr) continue;
+        double r[3];
+        for (int c = 0; c < 3; ++c) r[c] = pr.gpt[1 - g][3 * j + c] / kLat - 0.5;
+        best = fmin(best, len_mm(pr.sp, x, r));
+      }
+      if (best < INFINITY) acc += best * best;
+    }
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------ LDS layout
+
+struct EvalLayout {
+  size_t tet, xyz, units, part, waves, total;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ inline EvalLayout eval_layout(int maxA, int nver) {
+  EvalLayout L;
+  size_t o = 0;
+  L.tet = o;
+  o = align16(o + sizeof(int) * maxA);
+  L.xyz = o;  // [nver][maxA][2][4][3] float
+  o = align16(o + sizeof(float) * 24 * (size_t)nver * maxA);
+  L.units = o;  // [nver*2*maxA + 1] int (unit counts, then exclusive prefix)
+  o = align16(o + sizeof(int) * (2 * (size_t)nver * maxA + 1));
+  L.part = o;  // [nver*2*maxA][kWaves] double
+  o = align16(o + sizeof(double) * kWaves * 2 * (size_t)nver * maxA);
+  L.waves = o;  // [kWaves] WaveRows + RasterTet
+  o = align16(o + (sizeof(WaveRows) + sizeof(RasterTet)) * kWaves);
+  L.total = o;
+  return L;
+}
+
+// exclusive scan of n ints in LDS by wave 0 (n entries, writes n+1 with total)
+__device__ void lds_exclusive_scan(int* v, int n, int tid) {
+  if (tid < 64) {
+    int carry = 0;
+    for (int base = 0; base < n; base += 64) {
+      const int x = base + tid < n ? v[base + tid] : 0;
+      const int incl = wave_incl_scan(x, tid);
+      if (base + tid < n) v[base + tid] = carry + incl - x;
+      carry += __shfl(incl, 63, 64);
+    }
+    if (tid == 0) v[n] = carry;
+  }
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniformf(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Source of vertex vid's coordinates in grid gr for version v (0 = candidate,
+// 1 = current) of solution s, group g.
+__device__ __forceinline__ const float* vertex_src(const EvalArgs& a, int s, int g, int v, int vid, int gr) {
+  const float* src = a.X + (((size_t)s * 2 + gr) * a.pr.P + vid) * 3;
+  if (v == 0 && a.partial) {
+    const int pb = a.fos_off[g], pe = a.fos_off[g + 1], ncand = a.fos_off[a.G];
+    for (int k = pb; k < pe; ++k)
+      if (a.fos_pts[k] == vid) src = a.cand + (((size_t)s * ncand + k) * 2 + gr) * 3;
+  }
+  return src;
+}
+
+__device__ __forceinline__ int group_size(const EvalArgs& a, int g) {
+  return a.partial ? a.aff_cnt[g] : min(kFullChunk, a.pr.T - g * kFullChunk);
+}
+
+__device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
+  return a.partial ? a.aff[(size_t)g * a.maxA + i] : g * kFullChunk + i;
+}
+
+// ------------------------------------------------------------ voxel sweep kernel
+
+// Dissimilarity of every (version, tetrahedron) of one group of one solution:
+// writes simws[((s*G + g)*nver + v)*maxA + i]; partial mode also writes the
+// constraint flags and the voxel count of the candidate.
+__global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ simws) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const DevProblem& pr = a.pr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
+  const int nwg = a.S * a.G;
+  const int logical = xcd_logical(blockIdx.x, nwg);
+  const int g = logical / a.S, s = logical - g * a.S;
+  const int nver = a.nver;
+  const EvalLayout Lay = eval_layout(a.maxA, nver);
+  int* s_tet = (int*)(smem + Lay.tet);
+  float* s_xyz = (float*)(smem + Lay.xyz);
+  int* s_units = (int*)(smem + Lay.units);
+  double* s_part = (double*)(smem + Lay.part);
+  WaveRows* s_rows = (WaveRows*)(smem + Lay.waves);
+  RasterTet* s_rt = (RasterTet*)(smem + Lay.waves + sizeof(WaveRows) * kWaves);
+  __shared__ unsigned s_flags;
+  __shared__ unsigned s_count[kWaves];
+
+  const int na = group_size(a, g);
+  if (na < 0) {  // malformed FOS element
+    if (tid == 0) {
+      a.flags[(size_t)s * a.G + g] = DSM_FLAG_BAD_FOS;
+      if (a.vcount) a.vcount[(size_t)s * a.G + g] = 0;
+    }
+    return;
+  }
+  if (tid == 0) s_flags = 0u;
+  if (tid < kWaves) s_count[tid] = 0u;
+  for (int i = tid; i < na; i += kWG) s_tet[i] = group_tet(a, g, i);
+  __syncthreads();
+
+  // vertex coordinates of every (version, tetrahedron, grid, vertex) and the
+  // per-point constraint bits (lattice, box, border pins) of the candidate
+  for (int e = tid; e < nver * na * 8; e += kWG) {
+    const int v = e / (na * 8), r = e - v * na * 8;
+    const int i = r >> 3, gr = (r >> 2) & 1, q = r & 3;
+    const int vid = ((const int*)&pr.tets[s_tet[i]])[q];
+    const float* src = vertex_src(a, s, g, v, vid, gr);
+    float* dst = s_xyz + ((size_t)(v * na + i) * 8 + gr * 4 + q) * 3;
+    unsigned fl = 0u;
+    const int idx[3] = {vid % pr.n[0], (vid / pr.n[0]) % pr.n[1], vid / (pr.n[0] * pr.n[1])};
+    for (int c = 0; c < 3; ++c) {
+      const float x = src[c];
+      dst[c] = x;
+      double u;
+      const unsigned fc = lattice_of(x, pr.D[c], u);
+      fl |= fc;
+      if (!fc && ((idx[c] == 0 && u != 0.0) || (idx[c] == pr.n[c] - 1 && u != kLat * pr.D[c]))) fl |= DSM_FLAG_BORDER;
+    }
+    if (v == 0 && a.partial && fl) atomicOr(&s_flags, fl);
+  }
+  __syncthreads();
+
+  // unit counts per (version, direction, tetrahedron); direction 0 = target
+  // voxels mapped into the source (forward), 1 = source voxels into the target
+  const int nent = nver * 2 * na;
+  for (int e = tid; e < nent; e += kWG) {
+    const int v = e / (2 * na), r = e - v * 2 * na, dir = r / na, i = r - dir * na;
+    const int own = 1 - dir;
+    const float* xyz = s_xyz + (size_t)(v * na + i) * 24;
+    double L[4][3];
+    unsigned bad_own = 0u, bad_oth = 0u;
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 3; ++c) {
+        bad_own |= lattice_of(xyz[(own * 4 + q) * 3 + c], pr.D[c], L[q][c]);
+        double dummy;
+        bad_oth |= lattice_of(xyz[((1 - own) * 4 + q) * 3 + c], pr.D[c], dummy);
+      }
+    int nunits = 0;
+    if (!bad_own) {
+      const double vol = orient(L[0], L[1], L[2], L[3]);
+      if (vol > 0.0 && !bad_oth) {
+        double lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+          lo[c] = fmin(fmin(L[0][c], L[1][c]), fmin(L[2][c], L[3][c]));
+          hi[c] = fmax(fmax(L[0][c], L[1][c]), fmax(L[2][c], L[3][c]));
+        }
+        int za, zb, ya, yb;
+        vox_range(lo[2], hi[2], pr.D[2], za, zb);
+        vox_range(lo[1], hi[1], pr.D[1], ya, yb);
+        const int nrows = max(0, zb - za + 1) * max(0, yb - ya + 1);
+        nunits = (nrows + 63) >> 6;
+      } else if (!(vol > 0.0) && v == 0 && a.partial) {
+        atomicOr(&s_flags, own == 0 ? DSM_FLAG_INV_MOVING : DSM_FLAG_INV_FIXED);
+      }
+    }
+    s_units[e] = nunits;
+  }
+  for (int e = tid; e < nent * kWaves; e += kWG) s_part[e] = 0.0;
+  __syncthreads();
+  lds_exclusive_scan(s_units, nent, tid);
+  __syncthreads();
+  const int total_units = uniform(s_units[nent]);
+
+  // ---- voxel sweep
+  const int Dx = pr.D[0], DxDy = pr.DxDy;
+  const float Dxm = (float)(pr.D[0] - 1), Dym = (float)(pr.D[1] - 1), Dzm = (float)(pr.D[2] - 1);
+  const int Dxm2 = pr.D[0] - 2, Dym2 = pr.D[1] - 2, Dzm2 = pr.D[2] - 2;
+  const float tau = pr.tau;
+  WaveRows& wr = s_rows[wave];
+  RasterTet& rt = s_rt[wave];
+  int cur = -1, own = 0;
+  float jx = 0.f, jy = 0.f, jz = 0.f;
+  unsigned counted = 0u;
+  for (int u = wave; u < total_units; u += kWaves) {
+    int e = cur < 0 ? 0 : cur;
+    while (uniform(s_units[e + 1]) <= u) ++e;
+    e = uniform(e);
+    if (e != cur) {
+      cur = e;
+      const int v = e / (2 * na), r = e - v * 2 * na, dir = r / na, i = r - dir * na;
+      own = 1 - dir;
+      const float* xyz = s_xyz + (size_t)(v * na + i) * 24;
+      wave_sync();
+      setup_raster(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, rt);
+      jx = uniformf((float)rt.J[0][0]);
+      jy = uniformf((float)rt.J[1][0]);
+      jz = uniformf((float)rt.J[2][0]);
+    }
+    const float* __restrict__ own_img = pr.img[own];
+    const float* __restrict__ oth_img = pr.img[1 - own];
+    const int b = u - uniform(s_units[cur]);
+    const int nvox = uniform(build_rows(rt, b, lane, pr.D, DxDy, wr));
+    float sum = 0.f, comp = 0.f;
+    for (int q0 = 0; q0 < nvox; q0 += 64) {
+      const int q = q0 + lane;
+      if (q < nvox) {
+        const int r = find_row(wr, q);
+        const int off = q - wr.start[r];
+        const float fo = (float)off;
+        const float av = own_img[wr.lin[r] + off];
+        const float c = sample_contrib(oth_img, Dx, DxDy, Dxm, Dym, Dzm, Dxm2, Dym2, Dzm2, tau, av,
+                                       fmaf(jx, fo, wr.bx[r]), fmaf(jy, fo, wr.by[r]), fmaf(jz, fo, wr.bz[r]));
+        const float y = c - comp;
+        const float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+      }
+    }
+    const double tot = wave_sum((double)sum - (double)comp);
+    if (lane == 0) s_part[(size_t)cur * kWaves + wave] += tot;
+    if (cur < 2 * na) counted += (unsigned)nvox;  // version 0 (candidate) voxels
+  }
+  if (lane == 0) s_count[wave] = counted;
+  __syncthreads();
+
+  double* out = simws + ((size_t)s * a.G + g) * nver * a.maxA;
+  for (int e = tid; e < nver * na; e += kWG) {
+    const int v = e / na, i = e - v * na;
+    double sim = 0.0;
+    for (int dir = 0; dir < 2; ++dir)
+      for (int w = 0; w < kWaves; ++w) sim += s_part[((size_t)(v * 2 + dir) * na + i) * kWaves + w];
+    out[(size_t)v * a.maxA + i] = sim;
+  }
+  if (a.partial && tid == 0) {
+    const size_t oi = (size_t)s * a.G + g;
+    a.flags[oi] = s_flags;
+    if (a.vcount) {
+      unsigned tot = 0u;
+      for (int w = 0; w < kWaves; ++w) tot += s_count[w];
+      a.vcount[oi] = tot;
+    }
+  }
+}
+
+// ------------------------------------------------------------ finishing kernel
+
+// Adds the deformation and guidance terms (FP64, per tetrahedron) to the swept
+// dissimilarity, writes per-tetrahedron terms, and in partial mode the
+// normalised sums over each group in ascending tetrahedron order.
+__global__ __launch_bounds__(64) void k_finish(EvalArgs a, const double* __restrict__ simws) {
+  __shared__ double s_terms[2][3][64];
+  const DevProblem& pr = a.pr;
+  const int lane = threadIdx.x;
+  const int logical = blockIdx.x;
+  const int g = logical / a.S, s = logical - g * a.S;
+  const int na = group_size(a, g);
+  const size_t oi = (size_t)s * a.G + g;
+  if (na < 0) {
+    if (lane < 3) {
+      a.part_new[oi * 3 + lane] = 0.0;
+      a.part_old[oi * 3 + lane] = 0.0;
+    }
+    return;
+  }
+  const double* sims = simws + oi * a.nver * a.maxA;
+  double accn[3] = {0, 0, 0}, acco[3] = {0, 0, 0};
+  for (int base = 0; base < na; base += 64) {
+    const int i = base + lane;
+    for (int v = 0; v < a.nver; ++v) {
+      double term[3] = {0, 0, 0};
+      if (i < na) {
+        const int t = group_tet(a, g, i);
+        const int4 tv = pr.tets[t];
+        const int vid[4] = {tv.x, tv.y, tv.z, tv.w};
+        double L[2][4][3], V[2][4][3];
+        unsigned bad = 0u;
+        for (int gr = 0; gr < 2; ++gr)
+          for (int q = 0; q < 4; ++q) {
+            const float* src = vertex_src(a, s, g, v, vid[q], gr);
+            for (int c = 0; c < 3; ++c) {
+              V[gr][q][c] = src[c];
+              bad |= lattice_of(src[c], pr.D[c], L[gr][q][c]);
+            }
+          }
+        if (!bad) {
+          term[0] = sims[(size_t)v * a.maxA + i];
+          term[1] = deformation_term(pr, t, V[0], V[1]);
+          term[2] = guidance_term(pr, L, V);
+        }
+        if (v == 0 && a.terms_out) {
+          double* o = a.terms_out + ((size_t)s * pr.T + t) * 3;
+          o[0] = term[0];
+          o[1] = term[1];
+          o[2] = term[2];
+        }
+      }
+      for (int c = 0; c < 3; ++c) s_terms[v][c][lane] = term[c];
+    }
+    __syncthreads();
+    if (a.partial && lane < 6) {
+      const int c = lane % 3;
+      const bool old = lane >= 3;
+      const int n = min(64, na - base);
+      double acc = 0.0;
+      if (!old) {
+        for (int k = 0; k < n; ++k) acc += s_terms[0][c][k];
+        accn[c] += acc;
+      } else if (a.nver == 2) {
+        for (int k = 0; k < n; ++k) acc += s_terms[1][c][k];
+        acco[c] += acc;
+      } else {
+        for (int k = 0; k < n; ++k) acc += a.terms_in[((size_t)s * pr.T + group_tet(a, g, base + k)) * 3 + c];
+        acco[c] += acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (a.partial && lane < 6) {
+    const int c = lane % 3;
+    if (lane < 3)
+      a.part_new[oi * 3 + c] = accn[c] * pr.norm[c];
+    else
+      a.part_old[oi * 3 + c] = acco[c] * pr.norm[c];
+  }
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Sec. 2.3.4 per point: lattice, box and border pins, both grids.
+__global__ void k_fold_points(DevProblem pr, int S, const float* __restrict__ X, uint32_t* flags) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)S * pr.P) return;
+  const int s = (int)(e / pr.P), p = (int)(e - (int64_t)s * pr.P);
+  const int idx[3] = {p % pr.n[0], (p / pr.n[0]) % pr.n[1], p / (pr.n[0] * pr.n[1])};
+  unsigned fl = 0u;
+  for (int gr = 0; gr < 2; ++gr)
+    for (int c = 0; c < 3; ++c) {
+      double u;
+      const unsigned fc = lattice_of(X[(((size_t)s * 2 + gr) * pr.P + p) * 3 + c], pr.D[c], u);
+      fl |= fc;
+      if (!fc && ((idx[c] == 0 && u != 0.0) || (idx[c] == pr.n[c] - 1 && u != kLat * pr.D[c]))) fl |= DSM_FLAG_BORDER;
+    }
+  if (fl) atomicOr(&flags[s], fl);
+}
+
+// Sec. 2.3.4 per tetrahedron: exact orientation in both grids.
+__global__ void k_fold_tets(DevProblem pr, int S, const float* __restrict__ X, uint32_t* flags, int* first_bad) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)S * pr.T) return;
+  const int s = (int)(e / pr.T), t = (int)(e - (int64_t)s * pr.T);
+  const int4 tv = pr.tets[t];
+  const int vid[4] = {tv.x, tv.y, tv.z, tv.w};
+  unsigned fl = 0u;
+  for (int gr = 0; gr < 2; ++gr) {
+    double L[4][3];
+    unsigned bad = 0u;
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 3; ++c) bad |= lattice_of(X[(((size_t)s * 2 + gr) * pr.P + vid[q]) * 3 + c], pr.D[c], L[q][c]);
+    if (bad) continue;
+    if (!(orient(L[0], L[1], L[2], L[3]) > 0.0)) fl |= gr == 0 ? DSM_FLAG_INV_MOVING : DSM_FLAG_INV_FIXED;
+  }
+  if (fl) {
+    atomicOr(&flags[s], fl);
+    if (first_bad) atomicMin(&first_bad[s], t);
+  }
+}
+
+__global__ void k_first_bad_fix(int S, int* first_bad) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S && first_bad[s] == 0x7fffffff) first_bad[s] = -1;
+}
+
+// Affected tetrahedra of each FOS element: ascending union of its points' stars.
+__global__ void k_affected(DevProblem pr, int F, const int* __restrict__ fos_off, const int* __restrict__ fos_pts,
+                           int max_pts, int maxA, int* aff, int* aff_cnt) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int b = fos_off[f], e = fos_off[f + 1];
+  int* out = aff + (size_t)f * maxA;
+  if (b < 0 || e < b || e - b > max_pts) {
+    aff_cnt[f] = -1;
+    return;
+  }
+  int n = 0;
+  for (int k = b; k < e; ++k) {
+    const int p = fos_pts[k];
+    if (p < 0 || p >= pr.P) {
+      aff_cnt[f] = -1;
+      return;
+    }
+    for (int j = pr.star_off[p]; j < pr.star_off[p + 1]; ++j) {
+      const int t = pr.star[j];
+      // insertion into the sorted list, skipping duplicates
+      int pos = n;
+      while (pos > 0 && out[pos - 1] > t) --pos;
+      if (pos > 0 && out[pos - 1] == t) continue;
+      if (n >= maxA) {
+        aff_cnt[f] = -1;
+        return;
+      }
+      for (int m = n; m > pos; --m) out[m] = out[m - 1];
+      out[pos] = t;
+      ++n;
+    }
+  }
+  aff_cnt[f] = n;
+}
+
+// Full evaluation: fixed-order sum of the per-tetrahedron terms of each solution.
+__global__ __launch_bounds__(kWG) void k_full_reduce(DevProblem pr, const double* __restrict__ terms, double* obj) {
+  __shared__ double red[3][kWG];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  double acc[3] = {0, 0, 0};
+  for (int t = tid; t < pr.T; t += kWG)
+    for (int c = 0; c < 3; ++c) acc[c] += terms[((size_t)s * pr.T + t) * 3 + c];
+  for (int c = 0; c < 3; ++c) red[c][tid] = acc[c];
+  __syncthreads();
+  for (int w = kWG / 2; w >= 1; w >>= 1) {
+    if (tid < w)
+      for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + w];
+    __syncthreads();
+  }
+  if (tid < 3) obj[(size_t)s * 3 + tid] = red[tid][0] * pr.norm[tid];
+}
+
+// Owner map of one grid (test hook): every voxel of every tetrahedron's exact
+// voxel set claims its owner entry.
+__global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __restrict__ Xg, int* owner, int* overlap) {
+  __shared__ WaveRows rows[kWaves];
+  __shared__ RasterTet rts[kWaves];
+  __shared__ float xo[12];
+  const int t = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int4 tv = pr.tets[t];
+  const int vid[4] = {tv.x, tv.y, tv.z, tv.w};
+  double L[4][3];
+  unsigned bad = 0u;
+  for (int q = 0; q < 4; ++q)
+    for (int c = 0; c < 3; ++c) bad |= lattice_of(Xg[(size_t)vid[q] * 3 + c], pr.D[c], L[q][c]);
+  if (bad || !(orient(L[0], L[1], L[2], L[3]) > 0.0)) return;
+  if (threadIdx.x < 12) xo[threadIdx.x] = Xg[(size_t)vid[threadIdx.x / 3] * 3 + threadIdx.x % 3];
+  __syncthreads();
+  RasterTet& rt = rts[wave];
+  setup_raster(xo, xo, pr.D, lane, rt);
+  const int nb = (rt.nrows + 63) >> 6;
+  for (int b = wave; b < nb; b += kWaves) {
+    WaveRows& wr = rows[wave];
+    const int nvox = build_rows(rt, b, lane, pr.D, pr.DxDy, wr);
+    for (int q0 = 0; q0 < nvox; q0 += 64) {
+      const int q = q0 + lane;
+      if (q < nvox) {
+        const int r = find_row(wr, q);
+        const int idx = wr.lin[r] + (q - wr.start[r]);
+        const int prev = atomicCAS(&owner[idx], -1, t);
+        if (prev != -1) atomicAdd(overlap, 1);
+      }
+    }
+  }
+}
+
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+
+size_t eval_lds_bytes(int maxA, int nver) { return eval_layout(maxA, nver).total; }
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  k_fill_u32<<<blocks, 256, 0, stream>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* flags, int32_t* first_bad,
+                       hipStream_t stream) {
+  hipError_t e = launch_fill_u32(flags, S, 0u, stream);
+  if (e != hipSuccess) return e;
+  if (first_bad) {
+    k_fill_i32<<<(S + 255) / 256, 256, 0, stream>>>(first_bad, S, 0x7fffffff);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int64_t np = (int64_t)S * pr.P, nt = (int64_t)S * pr.T;
+  k_fold_points<<<(unsigned)((np + 255) / 256), 256, 0, stream>>>(pr, S, X, flags);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_fold_tets<<<(unsigned)((nt + 255) / 256), 256, 0, stream>>>(pr, S, X, flags, first_bad);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (first_bad) {
+    k_first_bad_fix<<<(S + 255) / 256, 256, 0, stream>>>(S, first_bad);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
+                           int maxA, int* aff, int* aff_cnt, hipStream_t stream) {
+  k_affected<<<(F + 63) / 64, 64, 0, stream>>>(pr, F, fos_off, fos_pts, max_pts, maxA, aff, aff_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const EvalArgs& a, double* simws, hipStream_t stream) {
+  const int64_t nwg = (int64_t)a.S * a.G;
+  if (nwg <= 0) return hipSuccess;
+  const size_t lds = eval_lds_bytes(a.maxA, a.nver);
+  k_sweep<<<(unsigned)nwg, kWG, lds, stream>>>(a, simws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_finish<<<(unsigned)nwg, 64, 0, stream>>>(a, simws);
+  return hipGetLastError();
+}
+
+hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream) {
+  k_full_reduce<<<S, kWG, 0, stream>>>(pr, terms, obj);
+  return hipGetLastError();
+}
+
+hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream) {
+  const int64_t V = (int64_t)pr.DxDy * pr.D[2];
+  k_fill_i32<<<(unsigned)std::min<int64_t>((V + 255) / 256, 4096), 256, 0, stream>>>(owner, V, -1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_fill_i32<<<1, 64, 0, stream>>>(overlap, 1, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_owner<<<pr.T, kWG, 0, stream>>>(pr, Xg, owner, overlap);
+  return hipGetLastError();
+}
+
+}  // namespace dsm

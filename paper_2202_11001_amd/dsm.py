@@ -1,0 +1,227 @@
+"""Python binding of libdsm (``include/dsm.h``): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; this module converts
+torch tensors to device pointers, allocates outputs with torch and passes the
+current torch stream.  There is no fallback: if ``libdsm.so`` is missing the
+import of the library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dsm.h")
+
+OK, ERR_ARG, ERR_CAPACITY, ERR_DOMAIN, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = range(7)
+FLAG_INV_MOVING, FLAG_INV_FIXED, FLAG_BORDER, FLAG_DOMAIN, FLAG_LATTICE, FLAG_NONFINITE, FLAG_BAD_FOS = (
+    1, 2, 4, 8, 16, 32, 64)
+
+
+class DsmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dsm status {status}: {msg}")
+        self.status = status
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("spacing_mm", C.c_float * 3), ("moving", C.c_void_p),
+                ("fixed", C.c_void_p), ("mesh", C.c_int32 * 3), ("empty_tau", C.c_float),
+                ("n_guid_moving", C.c_int32), ("n_guid_fixed", C.c_int32), ("guid_moving", C.c_void_p),
+                ("guid_fixed", C.c_void_p), ("corr_moving", C.c_void_p), ("corr_fixed", C.c_void_p),
+                ("max_solutions", C.c_int32), ("max_fos", C.c_int32), ("max_fos_points", C.c_int32)]
+
+
+class ProblemInfo(C.Structure):
+    _fields_ = [("P", C.c_int32), ("T", C.c_int32), ("E", C.c_int32), ("max_star", C.c_int32),
+                ("V", C.c_int64), ("max_affected", C.c_int32), ("norm", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libdsm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built: run __graft_entry__.build() (the HIP path has no fallback)")
+        L = C.CDLL(LIB_PATH)
+        V, I = C.c_void_p, C.c_int32
+        sig = {
+            "dsm_status_string": ([I], C.c_char_p),
+            "dsm_last_error": ([], C.c_char_p),
+            "dsm_problem_create": ([V, V], I),
+            "dsm_problem_destroy": ([V], I),
+            "dsm_problem_query": ([V, V], I),
+            "dsm_problem_topology": ([V, V, V, V, V], I),
+            "dsm_mesh_topology": ([V, V, V, V, V, V, V], I),
+            "dsm_fold_check": ([V, I, V, V, V, V], I),
+            "dsm_eval_full": ([V, I, V, V, V, V, V], I),
+            "dsm_eval_partial": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V], I),
+            "dsm_rasterize_owner": ([V, V, V, V, V], I),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names of the functions declared in include/dsm.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsm_[a-z_]+)\s*\(", txt)))
+
+
+def _check(st):
+    if st != OK:
+        L = lib()
+        raise DsmError(st, f"{L.dsm_status_string(st).decode()}: {L.dsm_last_error().decode()}")
+
+
+def _np_ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def mesh_topology(mesh, dims=None):
+    """Host-only topology: dict of counts, tets [T][4], star_off, star, identity [P][3]."""
+    L = lib()
+    m = np.ascontiguousarray(mesh, dtype=np.int32)
+    d = np.ascontiguousarray(dims, dtype=np.int32) if dims is not None else None
+    cnt = np.zeros(4, np.int32)
+    _check(L.dsm_mesh_topology(_np_ptr(m), _np_ptr(d), _np_ptr(cnt), None, None, None, None))
+    P, T, E, ms = (int(x) for x in cnt)
+    tets = np.zeros((T, 4), np.int32)
+    off = np.zeros(P + 1, np.int32)
+    st = np.zeros(4 * T, np.int32)
+    ident = np.zeros((P, 3), np.float32) if d is not None else None
+    _check(L.dsm_mesh_topology(_np_ptr(m), _np_ptr(d), None, _np_ptr(tets), _np_ptr(off), _np_ptr(st),
+                               _np_ptr(ident)))
+    return dict(P=P, T=T, E=E, max_star=ms, tets=tets, star_off=off, star=st, identity=ident)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """A registration problem resident on the current GPU (``dsm_problem``)."""
+
+    def __init__(self, moving, fixed, mesh, spacing=(1.0, 1.0, 1.0), tau=0.1, guid_moving=None, corr_moving=None,
+                 guid_fixed=None, corr_fixed=None, max_solutions=1, max_fos=0, max_fos_points=1):
+        L = lib()
+        moving = np.ascontiguousarray(moving, dtype=np.float32)
+        fixed = np.ascontiguousarray(fixed, dtype=np.float32)
+        if moving.shape != fixed.shape or moving.ndim != 3:
+            raise ValueError("moving and fixed must be equal-shape 3-D arrays")
+        gm = np.ascontiguousarray(guid_moving if guid_moving is not None else np.zeros((0, 3)), np.float32)
+        gf = np.ascontiguousarray(guid_fixed if guid_fixed is not None else np.zeros((0, 3)), np.float32)
+        cm = np.ascontiguousarray(corr_moving if corr_moving is not None else np.arange(len(gm)), np.int32)
+        cf = np.ascontiguousarray(corr_fixed if corr_fixed is not None else np.arange(len(gf)), np.int32)
+        d = ProblemDesc()
+        d.dims[:] = [moving.shape[2], moving.shape[1], moving.shape[0]]
+        d.spacing_mm[:] = [float(x) for x in spacing]
+        d.moving, d.fixed = moving.ctypes.data, fixed.ctypes.data
+        d.mesh[:] = [int(x) for x in mesh]
+        d.empty_tau = float(tau)
+        d.n_guid_moving, d.n_guid_fixed = len(gm), len(gf)
+        d.guid_moving, d.guid_fixed = _np_ptr(gm), _np_ptr(gf)
+        d.corr_moving, d.corr_fixed = _np_ptr(cm), _np_ptr(cf)
+        d.max_solutions, d.max_fos, d.max_fos_points = int(max_solutions), int(max_fos), int(max_fos_points)
+        h = C.c_void_p()
+        _check(L.dsm_problem_create(C.byref(d), C.byref(h)))
+        self._h = h
+        info = ProblemInfo()
+        _check(L.dsm_problem_query(self._h, C.byref(info)))
+        self.P, self.T, self.E, self.max_star = info.P, info.T, info.E, info.max_star
+        self.V, self.max_affected = info.V, info.max_affected
+        self.norm = tuple(info.norm)
+        self.dims = tuple(d.dims)
+        self.mesh = tuple(d.mesh)
+
+    @classmethod
+    def from_workload(cls, w, max_solutions=None, max_fos=None, max_fos_points=1):
+        return cls(w.moving, w.fixed, w.mesh, w.spacing, w.tau, w.guid_moving, w.corr_moving, w.guid_fixed,
+                   w.corr_fixed, max_solutions=max_solutions or w.S,
+                   max_fos=w.P if max_fos is None else max_fos, max_fos_points=max_fos_points)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dsm_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def topology(self):
+        tets = np.zeros((self.T, 4), np.int32)
+        off = np.zeros(self.P + 1, np.int32)
+        st = np.zeros(4 * self.T, np.int32)
+        ident = np.zeros((self.P, 3), np.float32)
+        _check(lib().dsm_problem_topology(self._h, _np_ptr(tets), _np_ptr(off), _np_ptr(st), _np_ptr(ident)))
+        return dict(tets=tets, star_off=off, star=st, identity=ident)
+
+    def fold_check(self, X, first_bad=False, stream=None):
+        torch = _torch()
+        S = X.shape[0]
+        flags = torch.empty(S, dtype=torch.int32, device=X.device)
+        fb = torch.empty(S, dtype=torch.int32, device=X.device) if first_bad else None
+        _check(lib().dsm_fold_check(self._h, S, _dptr(X), _dptr(flags), _dptr(fb), _stream(stream)))
+        return (flags, fb) if first_bad else flags
+
+    def eval_full(self, X, tet_terms=None, stream=None):
+        torch = _torch()
+        S = X.shape[0]
+        obj = torch.empty((S, 3), dtype=torch.float64, device=X.device)
+        flags = torch.empty(S, dtype=torch.int32, device=X.device)
+        _check(lib().dsm_eval_full(self._h, S, _dptr(X), _dptr(obj), _dptr(flags), _dptr(tet_terms),
+                                   _stream(stream)))
+        return obj, flags
+
+    def eval_partial(self, X, fos_off, fos_pts, cand, tet_terms_in=None, tet_terms_new=None, voxel_count=False,
+                     out=None, stream=None):
+        torch = _torch()
+        S, F = X.shape[0], fos_off.shape[0] - 1
+        if out is None:
+            out = (torch.empty((S, F, 3), dtype=torch.float64, device=X.device),
+                   torch.empty((S, F, 3), dtype=torch.float64, device=X.device),
+                   torch.empty((S, F), dtype=torch.int32, device=X.device),
+                   torch.empty((S, F), dtype=torch.int32, device=X.device) if voxel_count else None)
+        old, new, flags, vc = out
+        _check(lib().dsm_eval_partial(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                      _dptr(tet_terms_in), _dptr(old), _dptr(new), _dptr(flags),
+                                      _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
+        return out
+
+    def rasterize_owner(self, Xgrid, stream=None):
+        torch = _torch()
+        Dx, Dy, Dz = self.dims
+        owner = torch.empty((Dz, Dy, Dx), dtype=torch.int32, device=Xgrid.device)
+        overlap = torch.empty(1, dtype=torch.int32, device=Xgrid.device)
+        _check(lib().dsm_rasterize_owner(self._h, _dptr(Xgrid), _dptr(owner), _dptr(overlap), _stream(stream)))
+        return owner, overlap

@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.  Voxel sets and constraint flags bit-exact; every
+objective within 1e-5 relative (absolute floor 1e-7); deltas of partial
+changes within 1e-5 (|old| + |new|)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2202_11001_amd import workloads as W
+from tests._common import (assert_delta_close, assert_objectives_close, feasible_population,
+                           oracle_problem)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_11001_amd import dsm  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", file=sys.stderr, flush=True)
+
+
+def _gpu_problem(w, S, F=None, max_fos_points=1):
+    return dsm.Problem.from_workload(w, max_solutions=S, max_fos=w.P if F is None else F,
+                                     max_fos_points=max_fos_points)
+
+
+def _t(a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _small_workload(dims=(20, 18, 14), mesh=(4, 3, 3), seed=0, spacing=(1.0, 1.2, 2.0), tau=0.15, S=6):
+    rng = np.random.default_rng(seed)
+    shp = dims[::-1]
+    fixed = W._blur(rng.uniform(0, 1, shp) * (rng.uniform(0, 1, shp) > 0.3), 1.0).astype(np.float32)
+    moving = W._blur(rng.uniform(0, 1, shp) * (rng.uniform(0, 1, shp) > 0.3), 1.0).astype(np.float32)
+    hi = np.array(dims) - 1.0
+    gm = W.snap(rng.uniform(0, 1, (5, 3)) * hi)
+    gf = W.snap(rng.uniform(0, 1, (6, 3)) * hi)
+    return W.Workload(f"random-{dims}", moving, fixed, mesh, spacing, tau, S, 1.2, 1.0, seed + 1, seed + 2,
+                      gm, gf, np.array([0, 1, 2, 2, 3], np.int32), np.array([0, 1, 1, 2, 3, 3], np.int32))
+
+
+# ---------------------------------------------------------------- rasterisation
+
+@pytest.mark.parametrize("dims,mesh,sigma", [((33, 33, 33), (3, 3, 3), 0.0), ((33, 33, 33), (3, 3, 3), 3.0),
+                                             ((37, 23, 19), (5, 4, 3), 1.5), ((2, 2, 2), (2, 2, 2), 0.0),
+                                             ((64, 64, 64), (5, 5, 5), 1.0), ((17, 9, 25), (3, 2, 4), 0.0)])
+def test_owner_map_bitexact(dims, mesh, sigma):
+    _say(f"owner map dims={dims} mesh={mesh} sigma={sigma}")
+    z = np.zeros(dims[::-1], np.float32)
+    rp = ref.Problem(z, z, mesh)
+    if sigma > 0:
+        X = W.population(dims, mesh, 2, sigma, 5, reject=lambda X: rp.fold_check(X)[0] != 0)
+    else:
+        X = np.stack([rp.identity(), rp.identity()])[None]
+    gp = dsm.Problem(z, z, mesh, max_solutions=1)
+    for g in range(2):
+        owner, overlap = gp.rasterize_owner(_t(X[0, g]))
+        torch.cuda.synchronize()
+        ro, rc = rp.owner_bruteforce(X[0, g])
+        assert int(overlap.item()) == 0
+        np.testing.assert_array_equal(owner.cpu().numpy(), ro)
+
+
+# ---------------------------------------------------------------- fold check
+
+def test_fold_flags_bitexact():
+    w = _small_workload(dims=(24, 24, 24), mesh=(4, 4, 4))
+    rp = oracle_problem(w)
+    I = rp.identity()
+    base = np.stack([I, I])
+    cases = [base.copy()]
+    v = 1 + 4 * (1 + 4 * 1)
+    for (g, p, a, val) in [(0, v, 0, None), (1, v, 0, None), (0, 4 * (1 + 4 * 1), 0, 0.5),
+                           (1, 3 + 4 * (2 + 4 * 1), 0, 22.0), (1, v, 2, -3.0), (1, v, 1, 1.0 / 256), (0, v, 1, np.nan),
+                           (0, v, 1, np.inf)]:
+        Y = base.copy()
+        if val is None:
+            Y[g, p, a] = Y[g, p + 1, a] + 1.0
+        elif val == 1.0 / 256:
+            Y[g, p, a] += val
+        else:
+            Y[g, p, a] = val
+        cases.append(Y)
+    rng = np.random.default_rng(3)
+    for k in range(20):  # random large perturbations: many folds
+        cases.append(W.population(w.dims, w.mesh, 1, 4.0, 100 + k)[0])
+    X = np.stack(cases).astype(np.float32)
+    _say(f"fold flags S={len(X)}")
+    gp = _gpu_problem(w, len(X))
+    flags, fb = gp.fold_check(_t(X), first_bad=True)
+    torch.cuda.synchronize()
+    rf, rfb = rp.fold_check(X)
+    np.testing.assert_array_equal(flags.cpu().numpy().astype(np.uint32), rf)
+    np.testing.assert_array_equal(fb.cpu().numpy(), rfb)
+    assert (rf != 0).sum() > 10
+
+
+# ---------------------------------------------------------------- full evaluation
+
+@pytest.mark.parametrize("which", ["tiny", "random", "random_aniso"])
+def test_full_eval(which):
+    if which == "tiny":
+        w = W.tiny()
+    elif which == "random":
+        w = _small_workload()
+    else:
+        w = _small_workload(dims=(37, 23, 19), mesh=(5, 4, 3), spacing=(0.7, 1.1, 2.5), seed=4)
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    X[0] = np.stack([rp.identity(), rp.identity()])
+    _say(f"full eval {w.name} S={len(X)}")
+    gp = _gpu_problem(w, len(X))
+    terms = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+    obj, flags = gp.eval_full(_t(X), tet_terms=terms)
+    torch.cuda.synchronize()
+    robj, rflags, rterms, _ = rp.eval_full(X, want_terms=True)
+    np.testing.assert_array_equal(flags.cpu().numpy().astype(np.uint32), rflags)
+    assert_objectives_close(obj.cpu().numpy(), robj, what="full objectives")
+    # per-tetrahedron terms: absolute tolerance relative to the solution total
+    tt = terms.cpu().numpy()
+    tol = 1e-5 * np.abs(rterms).sum(axis=1, keepdims=True) / gp.T + 1e-9
+    assert np.all(np.abs(tt - rterms) <= tol + 1e-5 * np.abs(rterms))
+
+
+def test_identity_closed_forms_gpu():
+    """Identity mesh and identical images: every objective 0 (GPU floor 1e-7)."""
+    img = W._blur(np.random.default_rng(1).uniform(0, 1, (12, 14, 16)), 1.0).astype(np.float32)
+    gp = dsm.Problem(img, img, (3, 4, 3), tau=0.2, max_solutions=1)
+    I = gp.topology()["identity"]
+    obj, flags = gp.eval_full(_t(np.stack([I, I])[None]))
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0
+    assert np.all(np.abs(obj.cpu().numpy()) <= 1e-7)
+
+
+# ---------------------------------------------------------------- partial evaluation
+
+@pytest.mark.parametrize("use_cache", [True, False])
+@pytest.mark.parametrize("which", ["tiny", "random"])
+def test_partial_single_point(which, use_cache):
+    w = W.tiny() if which == "tiny" else _small_workload()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    _say(f"partial {w.name} S={len(X)} F={len(off) - 1} cache={use_cache}")
+    robj, rflags, rterms, _ = rp.eval_full(X, want_terms=True)
+    rold, rnew, rfl, rnv = rp.eval_partial(X, off, pts, cand, tet_terms=rterms if use_cache else None)
+    gp = _gpu_problem(w, len(X))
+    Xd = _t(X)
+    cache = None
+    if use_cache:
+        cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+        gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    fl = fl.cpu().numpy().astype(np.uint32)
+    np.testing.assert_array_equal(fl, rfl)
+    np.testing.assert_array_equal(vc.cpu().numpy()[fl == 0], rnv[fl == 0])
+    assert_objectives_close(new.cpu().numpy(), rnew, flags=fl, what="part_new")
+    assert_objectives_close(old.cpu().numpy(), rold, what="part_old")
+    assert_delta_close(old.cpu().numpy(), new.cpu().numpy(), rold, rnew, fl)
+
+
+def test_partial_multi_point_fos_and_edge_cases():
+    """FOS elements of several points (one tetrahedron per cube, Sec. 2.2),
+    an empty element, a malformed element, and candidates that fold or leave
+    the lattice."""
+    w = _small_workload(dims=(26, 22, 18), mesh=(4, 4, 3), seed=7)
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    tets = rp.tets()
+    rng = np.random.default_rng(9)
+    elems = [list(tets[6 * c + rng.integers(6)]) for c in range(0, (w.mesh[0] - 1) * (w.mesh[1] - 1) * (w.mesh[2] - 1), 2)]
+    elems.append([])              # empty element
+    elems.append([0, 1, 2, 3, 5, 6, 7])
+    good = len(elems)
+    off = np.zeros(good + 1, np.int32)
+    for i, e in enumerate(elems):
+        off[i + 1] = off[i] + len(e)
+    pts = np.concatenate([np.asarray(e, np.int32) for e in elems]).astype(np.int32)
+    cand = W.candidates(X, off, pts, w.mesh, w.dims, 2.5, 77)
+    # plant infeasible candidates: a NaN, an off-lattice value, a far jump
+    cand[0, 0, 0, 0] = np.nan
+    cand[1, 1, 1, 2] += 1.0 / 1024
+    cand[2, 2, 0, 1] = cand[2, 2, 0, 1] + 15.0
+    _say(f"partial multi-point S={len(X)} F={good}")
+    rterms = rp.eval_full(X, want_terms=True)[2]
+    rold, rnew, rfl, rnv = rp.eval_partial(X, off, pts, cand, tet_terms=rterms)
+    gp = _gpu_problem(w, len(X), F=good + 1, max_fos_points=7)
+    Xd = _t(X)
+    cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+    gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    fl = fl.cpu().numpy().astype(np.uint32)
+    np.testing.assert_array_equal(fl, rfl)
+    assert (fl != 0).sum() >= 3
+    np.testing.assert_array_equal(vc.cpu().numpy()[fl == 0], rnv[fl == 0])
+    assert_objectives_close(new.cpu().numpy(), rnew, flags=fl, what="part_new")
+    assert_objectives_close(old.cpu().numpy(), rold, what="part_old")
+    # malformed element: point index out of range, and one above max_fos_points
+    off2 = np.array([0, 1, 9], np.int32)
+    pts2 = np.array([rp.P + 3, 0, 1, 2, 3, 4, 5, 6, 7], np.int32)
+    cand2 = np.repeat(X[:, :, :1].transpose(0, 2, 1, 3), 9, axis=1).copy()
+    old2, new2, fl2, _ = gp.eval_partial(Xd, _t(off2), _t(pts2), _t(cand2), tet_terms_in=cache)
+    torch.cuda.synchronize()
+    assert np.all(fl2.cpu().numpy() == dsm.FLAG_BAD_FOS)
+
+
+def test_partial_full_consistency_gpu():
+    """full(new) = full(old) - part_old + part_new on the GPU, and the written
+    candidate terms equal a full evaluation of the changed solution."""
+    w = W.tiny()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    gp = _gpu_problem(w, len(X))
+    Xd = _t(X)
+    cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+    obj, _ = gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, _ = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache)
+    f = 13  # the centre point: its star is every tetrahedron
+    Y = X.copy()
+    Y[:, :, f] = cand[:, f]
+    obj2, fl2 = gp.eval_full(_t(Y))
+    torch.cuda.synchronize()
+    ok = (fl.cpu().numpy()[:, f] == 0)
+    lhs = obj2.cpu().numpy()[ok]
+    rhs = (obj.cpu().numpy() - old.cpu().numpy()[:, f] + new.cpu().numpy()[:, f])[ok]
+    assert ok.sum() > 5
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-5, atol=1e-7)
+
+
+def test_determinism():
+    w = _small_workload(seed=11)
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    gp = _gpu_problem(w, len(X))
+    Xd, od, pd, cd = _t(X), _t(off), _t(pts), _t(cand)
+    r1 = [t.cpu().numpy() for t in gp.eval_partial(Xd, od, pd, cd)[:3]]
+    r2 = [t.cpu().numpy() for t in gp.eval_partial(Xd, od, pd, cd)[:3]]
+    for a, b in zip(r1, r2):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_batched_sampled():
+    """64^3 blurred-ellipsoid pair, 5^3 meshes, 96 solutions x 125 single-point
+    elements in one launch; the oracle checks a sample of solutions."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    _say(f"batched {w.name} S={len(X)} F={len(off) - 1}")
+    gp = _gpu_problem(w, len(X))
+    Xd = _t(X)
+    cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+    obj, flags = gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    sample = [0, 17, 58, 95]
+    robj, rflags = rp.eval_full(X[sample])
+    assert_objectives_close(obj.cpu().numpy()[sample], robj, what="full objectives")
+    rold, rnew, rfl, rnv = rp.eval_partial(X[sample], off, pts, cand[sample])
+    flg = fl.cpu().numpy().astype(np.uint32)[sample]
+    np.testing.assert_array_equal(flg, rfl)
+    np.testing.assert_array_equal(vc.cpu().numpy()[sample][flg == 0], rnv[flg == 0])
+    assert_objectives_close(new.cpu().numpy()[sample], rnew, flags=flg, what="part_new")
+    assert_objectives_close(old.cpu().numpy()[sample], rold, what="part_old")
+    # exactly-once coverage: every single-point element's samples add up to 8 V per solution
+    vcs = vc.cpu().numpy().astype(np.int64)
+    allok = (fl.cpu().numpy() == 0).all(axis=1)
+    assert np.all(vcs[allok].sum(axis=1) == 8 * gp.V)
