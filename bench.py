@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_SAMPLE = 8   # one streamed own voxel + one (amortised) gathered voxel, float32
+KERNEL_SRC = os.path.join(ROOT, "paper_2202_11001_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_partial_clinical_traffic.txt")
 
 
 def log(msg):
@@ -57,6 +59,42 @@ def cpu_baseline(w, X, off, pts, cand, budget_s=20.0):
                       f"{dt:.1f} s wall"}
 
 
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings to bytes."""
+    import torch
+    n = 256 * 1024 * 1024  # float32 elements = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,7 +102,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--small", action="store_true", help="64^3 workload (quick check)")
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: 2 steps, no warmup, no CPU leg")
+    ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.profile:
+        args.steps, args.warmup, args.no_cpu = 2, 0, True
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} not supported: this evaluator runs on one GPU "
               f"(solutions shard across GPUs without exchange, see the design notes)", file=sys.stderr)
@@ -105,6 +150,7 @@ def main():
         gp.eval_partial(Xd, offd, ptsd, candd, tet_terms_in=cache, out=out)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    gp.timing(args.steps)
     t_start = time.perf_counter()
     ev[0].record(stream)
     for k in range(args.steps):
@@ -113,12 +159,17 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    sweep_ms = gp.timing_read()
+    gp.timing(0)
     ms = float(np.mean(step_ms))
-    log(f"step ms: {['%.2f' % x for x in step_ms]} wall {wall:.3f} s")
+    kms = float(np.mean(sweep_ms))
+    log(f"step ms: {['%.2f' % x for x in step_ms]}; sweep kernel ms: {['%.2f' % x for x in sweep_ms]}; "
+        f"wall {wall:.3f} s")
 
     evals_per_s = S * F / (ms / 1e3)
     samples_per_s = samples / (ms / 1e3)
-    achieved = samples * BYTES_PER_SAMPLE / (ms / 1e3) / 1e9
+    achieved = samples * BYTES_PER_SAMPLE / (kms / 1e3) / 1e9
+    traffic = measured_traffic()
     res = {
         "metric": "partial solution evals/s @512^2x100 (plain, batched)",
         "value": evals_per_s,
@@ -136,7 +187,10 @@ def main():
                    "partial_evals_per_step": S * F, "voxel_samples_per_step": samples},
         "voxel_samples_per_s": samples_per_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep<1> (partial-evaluation voxel sweep)", "kernel_ms": kms,
+                     "algorithmic_bytes_per_launch": samples * BYTES_PER_SAMPLE,
+                     "kernel_source_sha256_16": kernel_source_hash()},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)...")

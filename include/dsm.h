@@ -168,6 +168,18 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
  * exactly once. */
 dsm_status dsm_rasterize_owner(dsm_problem* p, const float* Xgrid, int32_t* owner, int32_t* overlap, void* stream);
 
+/* Measurement support.  dsm_problem_timing(p, capacity) with capacity > 0
+ * creates `capacity` pairs of HIP events; each following dsm_eval_full /
+ * dsm_eval_partial call records one pair around its voxel-sweep kernel on the
+ * call's stream (until the pairs run out).  capacity 0 disables timing and
+ * frees the events.  Not for use inside HIP graph capture.
+ * dsm_problem_timing_read waits for the recorded events, writes the sweep
+ * durations in milliseconds to ms host [max_n] in call order, their number to
+ * *n, and rewinds the pairs for reuse.  Errors: DSM_ERR_ARG (null, negative),
+ * DSM_ERR_DEVICE. */
+dsm_status dsm_problem_timing(dsm_problem* p, int32_t capacity);
+dsm_status dsm_problem_timing_read(dsm_problem* p, float* ms, int32_t max_n, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,8 @@ struct dsm_problem {
   int max_S = 0, max_F = 0, max_pts = 0, maxA = 0;
   int device = 0;
   // device buffers owned by the problem
-  float* d_img = nullptr;       // [2][V]
+  float* d_img = nullptr;       // [2][V + padding]
+  size_t img_stride = 0;
   int* d_tets = nullptr;
   double* d_tet_w = nullptr;
   int* d_star_off = nullptr;
@@ -36,6 +37,8 @@ struct dsm_problem {
   double* d_simws = nullptr;    // swept dissimilarity per (solution, group, version, tetrahedron)
   size_t simws_len = 0;
   std::vector<float> identity;  // [P][3]
+  std::vector<hipEvent_t> ev;   // timing event pairs (begin, end)
+  int ev_used = 0;
 };
 
 namespace {
@@ -65,11 +68,22 @@ hipError_t dev_alloc(T** p, size_t count) {
 
 void release(dsm_problem* p) {
   if (!p) return;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   void* bufs[] = {p->d_img, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
                   p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
+}
+
+// next free timing pair, or nulls
+void timing_pair(dsm_problem* p, hipEvent_t& b, hipEvent_t& e) {
+  b = e = nullptr;
+  if (p->ev_used * 2 + 1 < (int)p->ev.size()) {
+    b = p->ev[2 * p->ev_used];
+    e = p->ev[2 * p->ev_used + 1];
+    p->ev_used++;
+  }
 }
 
 bool on_lattice(float x, int D, double& u) {
@@ -179,9 +193,12 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
     release(p);              \
     return hip_fail(e, what); \
   }
-  DSM_TRY(dev_alloc(&p->d_img, 2 * (size_t)p->V), "hipMalloc images");
+  const size_t img_stride = (size_t)p->V + image_padding(d->dims[0], d->dims[1]);
+  DSM_TRY(dev_alloc(&p->d_img, 2 * img_stride), "hipMalloc images");
+  DSM_TRY(hipMemset(p->d_img, 0, sizeof(float) * 2 * img_stride), "clear images");
   DSM_TRY(hipMemcpy(p->d_img, d->moving, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy source image");
-  DSM_TRY(hipMemcpy(p->d_img + p->V, d->fixed, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy target image");
+  DSM_TRY(hipMemcpy(p->d_img + img_stride, d->fixed, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy target image");
+  p->img_stride = img_stride;
   DSM_TRY(dev_alloc(&p->d_tets, tp.tets.size()), "hipMalloc tets");
   DSM_TRY(hipMemcpy(p->d_tets, tp.tets.data(), sizeof(int) * tp.tets.size(), hipMemcpyHostToDevice), "copy tets");
   DSM_TRY(dev_alloc(&p->d_tet_w, tp.tet_w.size()), "hipMalloc weights");
@@ -210,7 +227,8 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
 
   DevProblem& dv = p->dev;
   dv.img[0] = p->d_img;
-  dv.img[1] = p->d_img + p->V;
+  dv.img[1] = p->d_img + p->img_stride;
+  dv.img_bytes = (int)(sizeof(float) * p->img_stride);
   for (int a = 0; a < 3; ++a) {
     dv.D[a] = p->dims[a];
     dv.n[a] = p->mesh[a];
@@ -333,7 +351,9 @@ dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj,
   a.maxA = kFullChunk;
   a.nver = 1;
   a.terms_out = tet_terms ? tet_terms : p->d_terms;
-  if ((e = launch_eval(a, p->d_simws, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  hipEvent_t eb, ee;
+  timing_pair(p, eb, ee);
+  if ((e = launch_eval(a, p->d_simws, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
   if ((e = launch_full_reduce(p->dev, S, a.terms_out, obj, st)) != hipSuccess) return hip_fail(e, "reduce launch");
   return DSM_OK;
 }
@@ -371,7 +391,38 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
   a.flags = flags;
   a.terms_out = tet_terms_new;
   a.vcount = voxel_count;
-  if ((e = launch_eval(a, p->d_simws, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  hipEvent_t eb, ee;
+  timing_pair(p, eb, ee);
+  if ((e = launch_eval(a, p->d_simws, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  return DSM_OK;
+}
+
+dsm_status dsm_problem_timing(dsm_problem* p, int32_t capacity) {
+  g_err.clear();
+  if (!p || capacity < 0) return fail(DSM_ERR_ARG, "null problem or negative capacity");
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->ev_used = 0;
+  for (int i = 0; i < 2 * capacity; ++i) {
+    hipEvent_t e;
+    const hipError_t st = hipEventCreate(&e);
+    if (st != hipSuccess) return hip_fail(st, "hipEventCreate");
+    p->ev.push_back(e);
+  }
+  return DSM_OK;
+}
+
+dsm_status dsm_problem_timing_read(dsm_problem* p, float* ms, int32_t max_n, int32_t* n) {
+  g_err.clear();
+  if (!p || !n || (max_n > 0 && !ms) || max_n < 0) return fail(DSM_ERR_ARG, "null argument");
+  const int k = std::min(p->ev_used, max_n);
+  for (int i = 0; i < k; ++i) {
+    hipError_t st = hipEventSynchronize(p->ev[2 * i + 1]);
+    if (st == hipSuccess) st = hipEventElapsedTime(&ms[i], p->ev[2 * i], p->ev[2 * i + 1]);
+    if (st != hipSuccess) return hip_fail(st, "timing events");
+  }
+  *n = k;
+  p->ev_used = 0;
   return DSM_OK;
 }
 

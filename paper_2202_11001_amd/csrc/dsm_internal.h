@@ -15,9 +15,15 @@ constexpr int kWaves = kWG / 64;  // wave64 waves per workgroup
 constexpr double kLat = 128.0;    // lattice steps per voxel
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
 
+// Zero floats after each image so that every trilinear tap of a position
+// clamped to [0, D-1] (including the weight-0 taps past the last voxel of a
+// row, column or slice) lies inside the allocation.
+inline int64_t image_padding(int Dx, int Dy) { return (int64_t)Dx * Dy + Dx + 64; }
+
 // Everything a kernel needs to know about one problem (passed by value).
 struct DevProblem {
-  const float* img[2];   // [0] source (moving), [1] target (fixed); [Dz][Dy][Dx]
+  const float* img[2];   // [0] source (moving), [1] target (fixed); [Dz][Dy][Dx], each followed by padding
+  int img_bytes;         // bytes of one image including its padding (buffer range)
   int D[3];
   int DxDy;
   float tau;             // empty iff value <= tau
@@ -73,7 +79,8 @@ hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* fl
                        hipStream_t stream);
 hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
                            int maxA, int* aff, int* aff_cnt, hipStream_t stream);
-hipError_t launch_eval(const EvalArgs& a, double* simws, hipStream_t stream);
+hipError_t launch_eval(const EvalArgs& a, double* simws, hipEvent_t ev_begin, hipEvent_t ev_end,
+                       hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
 size_t eval_lds_bytes(int maxA, int nver);

@@ -132,13 +132,70 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 
 // Parameters of one (tetrahedron, direction) for rasterising the own grid's
 // voxels and mapping them into the other grid.  Lives in wave-private LDS.
+constexpr int kMaxSlices = 64;  // slice-table capacity; taller tetrahedra enumerate bounding-box rows
+
 struct RasterTet {
   double A[4], C0[4], CY[4], CZ[4], rA[4];  // o_i(x,y,z) = A x + C0 + CY y + CZ z at voxel (x,y,z)
   double J[3][3];  // own voxel coords -> other grid voxel coords: p' = P0 + J v
   double P0[3];
   int thr[4];
-  int zlo, ylo, ny, nrows;
+  int zlo, nz, ylo, ny;  // bounding box (slices, rows)
+  int nrows;             // candidate rows
+  int sliced;            // 1: candidate rows from the slice table, 0: every bounding-box row
+  int y0[kMaxSlices];    // first candidate row of each slice
+  int rs[kMaxSlices + 1];  // exclusive prefix of candidate rows per slice
 };
+
+// Conservative row range [ya, yb] of the cross-section of the tetrahedron
+// (own-grid lattice vertices L) with voxel slice z: the y-extent of the
+// section polygon, whose vertices are the edge / plane intersections, widened
+// by one row on each side against rounding (the exact spans decide the voxels).
+__device__ __forceinline__ void slice_rows(const double L[4][3], int z, int Dy, int& ya, int& yb) {
+  const double Uz = kLat * z + 64.0;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int a = 0; a < 4; ++a) {
+    if (L[a][2] == Uz) {
+      lo = fmin(lo, L[a][1]);
+      hi = fmax(hi, L[a][1]);
+    }
+    for (int b = a + 1; b < 4; ++b) {
+      const double za = L[a][2], zb = L[b][2];
+      if ((za < Uz && zb > Uz) || (za > Uz && zb < Uz)) {
+        const double y = L[a][1] + (Uz - za) / (zb - za) * (L[b][1] - L[a][1]);
+        lo = fmin(lo, y);
+        hi = fmax(hi, y);
+      }
+    }
+  }
+  if (lo > hi) {
+    ya = 0;
+    yb = -1;
+    return;
+  }
+  ya = max(0, (int)ceil((lo - 64.0) / kLat) - 1);
+  yb = min(Dy - 1, (int)floor((hi - 64.0) / kLat) + 1);
+}
+
+// Number of candidate rows of a tetrahedron (same rule as the slice table).
+__device__ int candidate_rows(const double L[4][3], const int D[3]) {
+  double lo[3], hi[3];
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = fmin(fmin(L[0][c], L[1][c]), fmin(L[2][c], L[3][c]));
+    hi[c] = fmax(fmax(L[0][c], L[1][c]), fmax(L[2][c], L[3][c]));
+  }
+  int za, zb, ya, yb;
+  vox_range(lo[2], hi[2], D[2], za, zb);
+  vox_range(lo[1], hi[1], D[1], ya, yb);
+  const int nz = max(0, zb - za + 1), ny = max(0, yb - ya + 1);
+  if (nz > kMaxSlices) return nz * ny;
+  int rows = 0;
+  for (int k = 0; k < nz; ++k) {
+    int a, b;
+    slice_rows(L, za + k, D[1], a, b);
+    rows += max(0, b - a + 1);
+  }
+  return rows;
+}
 
 // Fills rt for the tetrahedron with own-grid vertices xo[4][3] and other-grid
 // vertices xt[4][3] (voxel units, already validated on the lattice); the work
@@ -200,11 +257,37 @@ __device__ void setup_raster(const float* xo, const float* xt, const int D[3], i
     vox_range((lo[2] + 0.5) * kLat, (hi[2] + 0.5) * kLat, D[2], za, zb);
     vox_range((lo[1] + 0.5) * kLat, (hi[1] + 0.5) * kLat, D[1], ya, yb);
     rt.zlo = za;
+    rt.nz = max(0, zb - za + 1);
     rt.ylo = ya;
     rt.ny = max(0, yb - ya + 1);
-    rt.nrows = rt.ny * max(0, zb - za + 1);
   }
   wave_sync();
+  const int nz = rt.nz;
+  if (nz <= kMaxSlices) {
+    // candidate rows of slice zlo + lane, prefix-summed over the slices
+    int cnt = 0, ya = 0;
+    if (lane < nz) {
+      double L[4][3];
+      for (int q = 0; q < 4; ++q)
+        for (int c = 0; c < 3; ++c) L[q][c] = ((double)xo[3 * q + c] + 0.5) * kLat;
+      int yb;
+      slice_rows(L, rt.zlo + lane, D[1], ya, yb);
+      cnt = max(0, yb - ya + 1);
+    }
+    const int incl = wave_incl_scan(cnt, lane);
+    if (lane < nz) {
+      rt.rs[lane] = incl - cnt;
+      rt.y0[lane] = ya;
+    }
+    if (lane == 63) {
+      rt.rs[min(nz, kMaxSlices)] = incl;
+      rt.nrows = incl;
+      rt.sliced = 1;
+    }
+  } else if (lane == 0) {
+    rt.nrows = nz * rt.ny;
+    rt.sliced = 0;
+  }
   if (lane < 3) {
     const int r = lane;
     rt.P0[r] = (double)xt[r] - (rt.J[r][0] * (double)xo[0] + rt.J[r][1] * (double)xo[1] + rt.J[r][2] * (double)xo[2]);
@@ -245,21 +328,34 @@ __device__ __forceinline__ void row_span(const RasterTet& rt, int y, int z, int 
 }
 
 struct WaveRows {
-  int start[64];  // exclusive prefix of span lengths
-  int lin[64];    // own-image linear index of the span's first voxel
-  float bx[64], by[64], bz[64];  // mapped position of the span's first voxel
+  int start[64];   // exclusive prefix of span lengths, by compacted (non-empty) row
+  float4 rec[64];  // x: own-image linear index minus start (as int bits); yzw: mapped position of the span's first voxel
+  int marker[64];  // per voxel slot of the current 64-voxel chunk: 1 where a row starts
 };
 
-// Computes the spans of rows [64 b, 64 b + 64) of rt into wr; returns the
-// number of voxels.  Row r = y-major within a slice: y = ylo + r % ny.
+// Computes the spans of rows [64 b, 64 b + 64) of rt, stores the non-empty
+// ones compacted (in row order) in wr, and returns the number of voxels.  Row r
+// is y-major within a slice: y = ylo + r % ny.  *my_start receives the first
+// voxel index of this lane's row, or a large negative value if it is empty.
 __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int DxDy,
-                                          WaveRows& wr) {
+                                          WaveRows& wr, int* my_start) {
   const int r = b * 64 + lane;
   int len = 0, lin = 0;
   float bx = 0.f, by = 0.f, bz = 0.f;
   if (r < rt.nrows) {
-    const int y = rt.ylo + r % rt.ny;
-    const int z = rt.zlo + r / rt.ny;
+    int y, z;
+    if (rt.sliced) {
+      int j = 0;  // last slice whose first candidate row is <= r
+      const int nz = rt.nz;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (j + step < nz && rt.rs[j + step] <= r) j += step;
+      y = rt.y0[j] + (r - rt.rs[j]);
+      z = rt.zlo + j;
+    } else {
+      y = rt.ylo + r % rt.ny;
+      z = rt.zlo + r / rt.ny;
+    }
     int x0, x1;
     row_span(rt, y, z, D[0], x0, x1);
     if (x1 >= x0) {
@@ -272,52 +368,82 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
     }
   }
   const int incl = wave_incl_scan(len, lane);
+  const int start = incl - len;
+  const unsigned long long ne = __ballot(len > 0);
+  const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(ne >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ne, 0u));
   wave_sync();
-  wr.start[lane] = incl - len;
-  wr.lin[lane] = lin;
-  wr.bx[lane] = bx;
-  wr.by[lane] = by;
-  wr.bz[lane] = bz;
+  if (len > 0) {
+    wr.start[slot] = start;
+    wr.rec[slot] = make_float4(__int_as_float(lin - start), bx, by, bz);
+  }
   wave_sync();
+  *my_start = len > 0 ? start : -(1 << 30);
   return __shfl(incl, 63, 64);
 }
 
-// largest r with start[r] <= q
-__device__ __forceinline__ int find_row(const WaveRows& wr, int q) {
-  int r = 0;
-#pragma unroll
-  for (int step = 32; step >= 1; step >>= 1)
-    if (wr.start[r + step] <= q) r += step;
-  return r;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const float* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, bytes, 0x00020000);
 }
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2v load2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2v, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ float load1(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+
+// Per-wave constants of the sampled (other) image.
+struct SampleCtx {
+  __amdgpu_buffer_rsrc_t own, oth;  // image buffers (padded: every tap of a clamped position is allocated)
+  float Dxm, Dym, Dzm;              // D - 1
+  int sx4, sxy4;                    // byte strides of y and z
+  float tau;
+};
 
 // Sec. 2.3.1 contribution of a voxel pair: squared intensity difference, and
 // the maximal difference 1 where an empty voxel meets a non-empty one; the
 // empty indicator of the sampled position is interpolated like the intensity.
-__device__ __forceinline__ float sample_contrib(const float* __restrict__ oth, int Dx, int DxDy, float Dxm, float Dym,
-                                                float Dzm, int Dxm2, int Dym2, int Dzm2, float tau, float a, float px,
-                                                float py, float pz) {
-  px = fminf(fmaxf(px, 0.f), Dxm);
-  py = fminf(fmaxf(py, 0.f), Dym);
-  pz = fminf(fmaxf(pz, 0.f), Dzm);
-  const int ix = min((int)px, Dxm2), iy = min((int)py, Dym2), iz = min((int)pz, Dzm2);
-  const float fx = px - (float)ix, fy = py - (float)iy, fz = pz - (float)iz;
-  const float* p0 = oth + (iz * DxDy + iy * Dx + ix);
-  const float* p1 = p0 + DxDy;
-  const float v000 = p0[0], v100 = p0[1], v010 = p0[Dx], v110 = p0[Dx + 1];
-  const float v001 = p1[0], v101 = p1[1], v011 = p1[Dx], v111 = p1[Dx + 1];
-  const float e000 = v000 <= tau ? 1.f : 0.f, e100 = v100 <= tau ? 1.f : 0.f;
-  const float e010 = v010 <= tau ? 1.f : 0.f, e110 = v110 <= tau ? 1.f : 0.f;
-  const float e001 = v001 <= tau ? 1.f : 0.f, e101 = v101 <= tau ? 1.f : 0.f;
-  const float e011 = v011 <= tau ? 1.f : 0.f, e111 = v111 <= tau ? 1.f : 0.f;
-  const float i00 = fmaf(fx, v100 - v000, v000), i10 = fmaf(fx, v110 - v010, v010);
-  const float i01 = fmaf(fx, v101 - v001, v001), i11 = fmaf(fx, v111 - v011, v011);
+// The position is clamped to [0, D-1]; at the upper bound the +1 tap has
+// weight 0 (it reads an allocated padding or neighbouring voxel).
+__device__ __forceinline__ float sample_contrib(const SampleCtx& c, float a, float px, float py, float pz) {
+  px = __builtin_amdgcn_fmed3f(px, 0.f, c.Dxm);
+  py = __builtin_amdgcn_fmed3f(py, 0.f, c.Dym);
+  pz = __builtin_amdgcn_fmed3f(pz, 0.f, c.Dzm);
+  const int ix = (int)px, iy = (int)py, iz = (int)pz;
+  const float fx = __builtin_amdgcn_fractf(px), fy = __builtin_amdgcn_fractf(py), fz = __builtin_amdgcn_fractf(pz);
+  const int voff = (ix << 2) + (int)__umul24((unsigned)iy, (unsigned)c.sx4) + (int)__umul24((unsigned)iz, (unsigned)c.sxy4);
+  const float2v t00 = load2(c.oth, voff, 0);
+  const float2v t10 = load2(c.oth, voff, c.sx4);
+  const float2v t01 = load2(c.oth, voff, c.sxy4);
+  const float2v t11 = load2(c.oth, voff, c.sx4 + c.sxy4);
+  const float tau = c.tau;
+  const float i00 = fmaf(fx, t00.y - t00.x, t00.x), i10 = fmaf(fx, t10.y - t10.x, t10.x);
+  const float i01 = fmaf(fx, t01.y - t01.x, t01.x), i11 = fmaf(fx, t11.y - t11.x, t11.x);
   const float i0 = fmaf(fy, i10 - i00, i00), i1 = fmaf(fy, i11 - i01, i01);
   const float b = fmaf(fz, i1 - i0, i0);
-  const float m00 = fmaf(fx, e100 - e000, e000), m10 = fmaf(fx, e110 - e010, e010);
-  const float m01 = fmaf(fx, e101 - e001, e001), m11 = fmaf(fx, e111 - e011, e011);
-  const float m0 = fmaf(fy, m10 - m00, m00), m1 = fmaf(fy, m11 - m01, m01);
-  const float eb = fmaf(fz, m1 - m0, m0);
+  // empty indicators of the 8 taps as wave masks (combined in scalar registers)
+  constexpr int kOLE = 5;  // ordered less-or-equal
+  const unsigned long long m000 = __builtin_amdgcn_fcmpf(t00.x, tau, kOLE), m100 = __builtin_amdgcn_fcmpf(t00.y, tau, kOLE);
+  const unsigned long long m010 = __builtin_amdgcn_fcmpf(t10.x, tau, kOLE), m110 = __builtin_amdgcn_fcmpf(t10.y, tau, kOLE);
+  const unsigned long long m001 = __builtin_amdgcn_fcmpf(t01.x, tau, kOLE), m101 = __builtin_amdgcn_fcmpf(t01.y, tau, kOLE);
+  const unsigned long long m011 = __builtin_amdgcn_fcmpf(t11.x, tau, kOLE), m111 = __builtin_amdgcn_fcmpf(t11.y, tau, kOLE);
+  const unsigned long long all = m000 & m100 & m010 & m110 & m001 & m101 & m011 & m111;
+  const unsigned long long any = m000 | m100 | m010 | m110 | m001 | m101 | m011 | m111;
+  // where the 8 taps agree the interpolated indicator is the first tap's
+  float eb = t00.x <= tau ? 1.f : 0.f;
+  if (any & ~all) {  // some lane has taps on both sides of tau: interpolate its indicator
+    const float e000 = t00.x <= tau ? 1.f : 0.f, e100 = t00.y <= tau ? 1.f : 0.f;
+    const float e010 = t10.x <= tau ? 1.f : 0.f, e110 = t10.y <= tau ? 1.f : 0.f;
+    const float e001 = t01.x <= tau ? 1.f : 0.f, e101 = t01.y <= tau ? 1.f : 0.f;
+    const float e011 = t11.x <= tau ? 1.f : 0.f, e111 = t11.y <= tau ? 1.f : 0.f;
+    const float m00 = fmaf(fx, e100 - e000, e000), m10 = fmaf(fx, e110 - e010, e010);
+    const float m01 = fmaf(fx, e101 - e001, e001), m11 = fmaf(fx, e111 - e011, e011);
+    const float m0 = fmaf(fy, m10 - m00, m00), m1 = fmaf(fy, m11 - m01, m01);
+    eb = fmaf(fz, m1 - m0, m0);
+  }
   const float ea = a <= tau ? 1.f : 0.f;
   const float m = fabsf(ea - eb);
   const float d = a - b;
@@ -458,6 +584,7 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 // Dissimilarity of every (version, tetrahedron) of one group of one solution:
 // writes simws[((s*G + g)*nver + v)*maxA + i]; partial mode also writes the
 // constraint flags and the voxel count of the candidate.
+template <int PARTIAL>
 __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ simws) {
   extern __shared__ __align__(16) unsigned char smem[];
   const DevProblem& pr = a.pr;
@@ -476,7 +603,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
   __shared__ unsigned s_flags;
   __shared__ unsigned s_count[kWaves];
 
-  const int na = group_size(a, g);
+  const int na = (PARTIAL ? a.aff_cnt[g] : min(kFullChunk, pr.T - g * kFullChunk));
   if (na < 0) {  // malformed FOS element
     if (tid == 0) {
       a.flags[(size_t)s * a.G + g] = DSM_FLAG_BAD_FOS;
@@ -507,7 +634,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
       fl |= fc;
       if (!fc && ((idx[c] == 0 && u != 0.0) || (idx[c] == pr.n[c] - 1 && u != kLat * pr.D[c]))) fl |= DSM_FLAG_BORDER;
     }
-    if (v == 0 && a.partial && fl) atomicOr(&s_flags, fl);
+    if (v == 0 && PARTIAL && fl) atomicOr(&s_flags, fl);
   }
   __syncthreads();
 
@@ -530,17 +657,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
     if (!bad_own) {
       const double vol = orient(L[0], L[1], L[2], L[3]);
       if (vol > 0.0 && !bad_oth) {
-        double lo[3], hi[3];
-        for (int c = 0; c < 3; ++c) {
-          lo[c] = fmin(fmin(L[0][c], L[1][c]), fmin(L[2][c], L[3][c]));
-          hi[c] = fmax(fmax(L[0][c], L[1][c]), fmax(L[2][c], L[3][c]));
-        }
-        int za, zb, ya, yb;
-        vox_range(lo[2], hi[2], pr.D[2], za, zb);
-        vox_range(lo[1], hi[1], pr.D[1], ya, yb);
-        const int nrows = max(0, zb - za + 1) * max(0, yb - ya + 1);
-        nunits = (nrows + 63) >> 6;
-      } else if (!(vol > 0.0) && v == 0 && a.partial) {
+        nunits = (candidate_rows(L, pr.D) + 63) >> 6;
+      } else if (!(vol > 0.0) && v == 0 && PARTIAL) {
         atomicOr(&s_flags, own == 0 ? DSM_FLAG_INV_MOVING : DSM_FLAG_INV_FIXED);
       }
     }
@@ -553,53 +671,80 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
   const int total_units = uniform(s_units[nent]);
 
   // ---- voxel sweep
-  const int Dx = pr.D[0], DxDy = pr.DxDy;
-  const float Dxm = (float)(pr.D[0] - 1), Dym = (float)(pr.D[1] - 1), Dzm = (float)(pr.D[2] - 1);
-  const int Dxm2 = pr.D[0] - 2, Dym2 = pr.D[1] - 2, Dzm2 = pr.D[2] - 2;
-  const float tau = pr.tau;
+  const int DxDy = pr.DxDy;
+  SampleCtx sc;
+  sc.Dxm = (float)(pr.D[0] - 1);
+  sc.Dym = (float)(pr.D[1] - 1);
+  sc.Dzm = (float)(pr.D[2] - 1);
+  sc.sx4 = 4 * pr.D[0];
+  sc.sxy4 = 4 * DxDy;
+  sc.tau = pr.tau;
+  const __amdgpu_buffer_rsrc_t rs[2] = {image_rsrc(pr.img[0], pr.img_bytes), image_rsrc(pr.img[1], pr.img_bytes)};
   WaveRows& wr = s_rows[wave];
   RasterTet& rt = s_rt[wave];
-  int cur = -1, own = 0;
+  int cur = -1;
   float jx = 0.f, jy = 0.f, jz = 0.f;
   unsigned counted = 0u;
-  for (int u = wave; u < total_units; u += kWaves) {
+  float sum = 0.f, comp = 0.f;  // compensated per-lane sum of the current (version, direction, tetrahedron)
+  // each wave takes one contiguous range of units, so it sets up few tetrahedra
+  const int u_begin = (wave * total_units) / kWaves, u_end = ((wave + 1) * total_units) / kWaves;
+  for (int u = u_begin; u < u_end; ++u) {
     int e = cur < 0 ? 0 : cur;
     while (uniform(s_units[e + 1]) <= u) ++e;
     e = uniform(e);
     if (e != cur) {
+      if (cur >= 0) {
+        const double tot = wave_sum((double)sum - (double)comp);
+        if (lane == 0) s_part[(size_t)cur * kWaves + wave] += tot;
+        sum = comp = 0.f;
+      }
       cur = e;
       const int v = e / (2 * na), r = e - v * 2 * na, dir = r / na, i = r - dir * na;
-      own = 1 - dir;
+      const int own = 1 - dir;
       const float* xyz = s_xyz + (size_t)(v * na + i) * 24;
       wave_sync();
       setup_raster(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, rt);
       jx = uniformf((float)rt.J[0][0]);
       jy = uniformf((float)rt.J[1][0]);
       jz = uniformf((float)rt.J[2][0]);
+      sc.own = own ? rs[1] : rs[0];
+      sc.oth = own ? rs[0] : rs[1];
     }
-    const float* __restrict__ own_img = pr.img[own];
-    const float* __restrict__ oth_img = pr.img[1 - own];
     const int b = u - uniform(s_units[cur]);
-    const int nvox = uniform(build_rows(rt, b, lane, pr.D, DxDy, wr));
-    float sum = 0.f, comp = 0.f;
+    int my_start;
+    const int nvox = uniform(build_rows(rt, b, lane, pr.D, DxDy, wr, &my_start));
+    int carry = 0;  // non-empty rows that start before the current chunk
     for (int q0 = 0; q0 < nvox; q0 += 64) {
+      // row of voxel q0 + lane: rows starting in this chunk are marked, then
+      // counted below the lane with a ballot
+      wr.marker[lane] = 0;
+      wave_sync();
+      const unsigned pos = (unsigned)(my_start - q0);
+      if (pos < 64u) wr.marker[pos] = 1;
+      wave_sync();
+      const int mk = wr.marker[lane];
+      const unsigned long long M = __ballot(mk != 0);
+      const int r = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M, 0u)) +
+                    mk - 1;
+      carry += __popcll(M);
       const int q = q0 + lane;
       if (q < nvox) {
-        const int r = find_row(wr, q);
         const int off = q - wr.start[r];
+        const float4 rec = wr.rec[r];
         const float fo = (float)off;
-        const float av = own_img[wr.lin[r] + off];
-        const float c = sample_contrib(oth_img, Dx, DxDy, Dxm, Dym, Dzm, Dxm2, Dym2, Dzm2, tau, av,
-                                       fmaf(jx, fo, wr.bx[r]), fmaf(jy, fo, wr.by[r]), fmaf(jz, fo, wr.bz[r]));
+        const float av = load1(sc.own, (__float_as_int(rec.x) + q) << 2);
+        const float c = sample_contrib(sc, av, fmaf(jx, fo, rec.y), fmaf(jy, fo, rec.z), fmaf(jz, fo, rec.w));
         const float y = c - comp;
         const float t = sum + y;
         comp = (t - sum) - y;
         sum = t;
       }
     }
+    if (cur < 2 * na) counted += (unsigned)nvox;  // version 0 (candidate) voxels
+  }
+  if (cur >= 0) {
     const double tot = wave_sum((double)sum - (double)comp);
     if (lane == 0) s_part[(size_t)cur * kWaves + wave] += tot;
-    if (cur < 2 * na) counted += (unsigned)nvox;  // version 0 (candidate) voxels
   }
   if (lane == 0) s_count[wave] = counted;
   __syncthreads();
@@ -612,7 +757,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
       for (int w = 0; w < kWaves; ++w) sim += s_part[((size_t)(v * 2 + dir) * na + i) * kWaves + w];
     out[(size_t)v * a.maxA + i] = sim;
   }
-  if (a.partial && tid == 0) {
+  if (PARTIAL && tid == 0) {
     const size_t oi = (size_t)s * a.G + g;
     a.flags[oi] = s_flags;
     if (a.vcount) {
@@ -829,12 +974,23 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
   const int nb = (rt.nrows + 63) >> 6;
   for (int b = wave; b < nb; b += kWaves) {
     WaveRows& wr = rows[wave];
-    const int nvox = build_rows(rt, b, lane, pr.D, pr.DxDy, wr);
+    int my_start;
+    const int nvox = build_rows(rt, b, lane, pr.D, pr.DxDy, wr, &my_start);
+    int carry = 0;
     for (int q0 = 0; q0 < nvox; q0 += 64) {
+      wr.marker[lane] = 0;
+      wave_sync();
+      const unsigned pos = (unsigned)(my_start - q0);
+      if (pos < 64u) wr.marker[pos] = 1;
+      wave_sync();
+      const int mk = wr.marker[lane];
+      const unsigned long long M = __ballot(mk != 0);
+      const int r = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M, 0u)) +
+                    mk - 1;
+      carry += __popcll(M);
       const int q = q0 + lane;
       if (q < nvox) {
-        const int r = find_row(wr, q);
-        const int idx = wr.lin[r] + (q - wr.start[r]);
+        const int idx = __float_as_int(wr.rec[r].x) + q;
         const int prev = atomicCAS(&owner[idx], -1, t);
         if (prev != -1) atomicAdd(overlap, 1);
       }
@@ -885,13 +1041,19 @@ hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, cons
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const EvalArgs& a, double* simws, hipStream_t stream) {
+hipError_t launch_eval(const EvalArgs& a, double* simws, hipEvent_t ev_begin, hipEvent_t ev_end,
+                       hipStream_t stream) {
   const int64_t nwg = (int64_t)a.S * a.G;
   if (nwg <= 0) return hipSuccess;
   const size_t lds = eval_lds_bytes(a.maxA, a.nver);
-  k_sweep<<<(unsigned)nwg, kWG, lds, stream>>>(a, simws);
+  if (ev_begin) (void)hipEventRecord(ev_begin, stream);
+  if (a.partial)
+    k_sweep<1><<<(unsigned)nwg, kWG, lds, stream>>>(a, simws);
+  else
+    k_sweep<0><<<(unsigned)nwg, kWG, lds, stream>>>(a, simws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (ev_end) (void)hipEventRecord(ev_end, stream);
   k_finish<<<(unsigned)nwg, 64, 0, stream>>>(a, simws);
   return hipGetLastError();
 }

@@ -64,6 +64,8 @@ def lib():
             "dsm_eval_full": ([V, I, V, V, V, V, V], I),
             "dsm_eval_partial": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_rasterize_owner": ([V, V, V, V, V], I),
+            "dsm_problem_timing": ([V, I], I),
+            "dsm_problem_timing_read": ([V, V, I, V], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -217,6 +219,16 @@ class Problem:
                                       _dptr(tet_terms_in), _dptr(old), _dptr(new), _dptr(flags),
                                       _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
         return out
+
+    def timing(self, capacity):
+        """Record the sweep kernel's duration in the next `capacity` evaluation calls."""
+        _check(lib().dsm_problem_timing(self._h, int(capacity)))
+
+    def timing_read(self, max_n=4096):
+        ms = np.zeros(max_n, np.float32)
+        n = C.c_int32()
+        _check(lib().dsm_problem_timing_read(self._h, _np_ptr(ms), int(max_n), C.byref(n)))
+        return ms[:n.value].astype(np.float64)
 
     def rasterize_owner(self, Xgrid, stream=None):
         torch = _torch()
