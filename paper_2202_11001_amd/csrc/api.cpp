@@ -23,7 +23,7 @@ struct dsm_problem {
   int max_S = 0, max_F = 0, max_pts = 0, maxA = 0;
   int device = 0;
   // device buffers owned by the problem
-  float* d_img = nullptr;       // [2][V + padding]
+  float* d_img = nullptr;       // [2][Dz][Dy][Dx][2] z-pair interleaved, each image padded
   size_t img_stride = 0;
   int* d_tets = nullptr;
   double* d_tet_w = nullptr;
@@ -193,11 +193,25 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
     release(p);              \
     return hip_fail(e, what); \
   }
-  const size_t img_stride = (size_t)p->V + image_padding(d->dims[0], d->dims[1]);
-  DSM_TRY(dev_alloc(&p->d_img, 2 * img_stride), "hipMalloc images");
-  DSM_TRY(hipMemset(p->d_img, 0, sizeof(float) * 2 * img_stride), "clear images");
-  DSM_TRY(hipMemcpy(p->d_img, d->moving, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy source image");
-  DSM_TRY(hipMemcpy(p->d_img + img_stride, d->fixed, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy target image");
+  // z-pair interleaved images: element (x,y,z) = (I[z][y][x], I[min(z+1,Dz-1)][y][x])
+  const size_t img_stride = 2 * ((size_t)p->V + image_padding(d->dims[0], d->dims[1]));
+  {
+    std::vector<float> packed(2 * img_stride, 0.0f);
+    const size_t plane = (size_t)d->dims[0] * d->dims[1];
+    const float* src[2] = {d->moving, d->fixed};
+    for (int g = 0; g < 2; ++g)
+      for (int z = 0; z < d->dims[2]; ++z) {
+        const float* a = src[g] + plane * z;
+        const float* b = src[g] + plane * (z + 1 < d->dims[2] ? z + 1 : z);
+        float* dst = packed.data() + g * img_stride + 2 * plane * z;
+        for (size_t i = 0; i < plane; ++i) {
+          dst[2 * i] = a[i];
+          dst[2 * i + 1] = b[i];
+        }
+      }
+    DSM_TRY(dev_alloc(&p->d_img, 2 * img_stride), "hipMalloc images");
+    DSM_TRY(hipMemcpy(p->d_img, packed.data(), sizeof(float) * 2 * img_stride, hipMemcpyHostToDevice), "copy images");
+  }
   p->img_stride = img_stride;
   DSM_TRY(dev_alloc(&p->d_tets, tp.tets.size()), "hipMalloc tets");
   DSM_TRY(hipMemcpy(p->d_tets, tp.tets.data(), sizeof(int) * tp.tets.size(), hipMemcpyHostToDevice), "copy tets");

@@ -15,15 +15,15 @@ constexpr int kWaves = kWG / 64;  // wave64 waves per workgroup
 constexpr double kLat = 128.0;    // lattice steps per voxel
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
 
-// Zero floats after each image so that every trilinear tap of a position
-// clamped to [0, D-1] (including the weight-0 taps past the last voxel of a
-// row, column or slice) lies inside the allocation.
-inline int64_t image_padding(int Dx, int Dy) { return (int64_t)Dx * Dy + Dx + 64; }
+// Packed elements (float pairs) after each z-pair interleaved image so that
+// every tap of a position clamped to [0, D-1] (including the weight-0 taps past
+// the last voxel of a row or column) lies inside the allocation.
+inline int64_t image_padding(int Dx, int Dy) { return (int64_t)Dx + 64; }
 
 // Everything a kernel needs to know about one problem (passed by value).
 struct DevProblem {
-  const float* img[2];   // [0] source (moving), [1] target (fixed); [Dz][Dy][Dx], each followed by padding
-  int img_bytes;         // bytes of one image including its padding (buffer range)
+  const float* img[2];   // [0] source (moving), [1] target (fixed); z-pair interleaved [Dz][Dy][Dx][2], padded
+  int img_bytes;         // bytes of one packed image including its padding (buffer range)
   int D[3];
   int DxDy;
   float tau;             // empty iff value <= tau

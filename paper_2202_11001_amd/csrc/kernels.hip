@@ -385,21 +385,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const float* p, int
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, bytes, 0x00020000);
 }
 
-typedef float float2v __attribute__((ext_vector_type(2)));
+typedef float float4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float2v load2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float2v, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+__device__ __forceinline__ float4v load4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float4v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
 __device__ __forceinline__ float load1(__amdgpu_buffer_rsrc_t r, int voff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
-// Per-wave constants of the sampled (other) image.
+// Per-wave constants of the sampled (other) image.  Images are stored
+// z-pair interleaved: element (x,y,z) holds (I[z][y][x], I[z+1][y][x]), so one
+// 16-byte load returns the taps (x, z), (x, z+1), (x+1, z), (x+1, z+1).
 struct SampleCtx {
   __amdgpu_buffer_rsrc_t own, oth;  // image buffers (padded: every tap of a clamped position is allocated)
   float Dxm, Dym, Dzm;              // D - 1
-  int sx4, sxy4;                    // byte strides of y and z
+  int sx8, sxy8;                    // byte strides of y and z
   float tau;
 };
 
@@ -414,11 +416,12 @@ __device__ __forceinline__ float sample_contrib(const SampleCtx& c, float a, flo
   pz = __builtin_amdgcn_fmed3f(pz, 0.f, c.Dzm);
   const int ix = (int)px, iy = (int)py, iz = (int)pz;
   const float fx = __builtin_amdgcn_fractf(px), fy = __builtin_amdgcn_fractf(py), fz = __builtin_amdgcn_fractf(pz);
-  const int voff = (ix << 2) + (int)__umul24((unsigned)iy, (unsigned)c.sx4) + (int)__umul24((unsigned)iz, (unsigned)c.sxy4);
-  const float2v t00 = load2(c.oth, voff, 0);
-  const float2v t10 = load2(c.oth, voff, c.sx4);
-  const float2v t01 = load2(c.oth, voff, c.sxy4);
-  const float2v t11 = load2(c.oth, voff, c.sx4 + c.sxy4);
+  const int voff = (ix << 3) + (int)__umul24((unsigned)iy, (unsigned)c.sx8) + (int)__umul24((unsigned)iz, (unsigned)c.sxy8);
+  const float4v ty0 = load4(c.oth, voff, 0);      // (x,z) (x,z+1) (x+1,z) (x+1,z+1) at y
+  const float4v ty1 = load4(c.oth, voff, c.sx8);  // the same at y+1
+  struct {
+    float x, y;
+  } t00{ty0.x, ty0.z}, t10{ty1.x, ty1.z}, t01{ty0.y, ty0.w}, t11{ty1.y, ty1.w};
   const float tau = c.tau;
   const float i00 = fmaf(fx, t00.y - t00.x, t00.x), i10 = fmaf(fx, t10.y - t10.x, t10.x);
   const float i01 = fmaf(fx, t01.y - t01.x, t01.x), i11 = fmaf(fx, t11.y - t11.x, t11.x);
@@ -585,7 +588,7 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 // writes simws[((s*G + g)*nver + v)*maxA + i]; partial mode also writes the
 // constraint flags and the voxel count of the candidate.
 template <int PARTIAL>
-__global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ simws) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep(EvalArgs a, double* __restrict__ simws) {
   extern __shared__ __align__(16) unsigned char smem[];
   const DevProblem& pr = a.pr;
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
@@ -676,8 +679,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
   sc.Dxm = (float)(pr.D[0] - 1);
   sc.Dym = (float)(pr.D[1] - 1);
   sc.Dzm = (float)(pr.D[2] - 1);
-  sc.sx4 = 4 * pr.D[0];
-  sc.sxy4 = 4 * DxDy;
+  sc.sx8 = 8 * pr.D[0];
+  sc.sxy8 = 8 * DxDy;
   sc.tau = pr.tau;
   const __amdgpu_buffer_rsrc_t rs[2] = {image_rsrc(pr.img[0], pr.img_bytes), image_rsrc(pr.img[1], pr.img_bytes)};
   WaveRows& wr = s_rows[wave];
@@ -732,7 +735,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(EvalArgs a, double* __restrict__ 
         const int off = q - wr.start[r];
         const float4 rec = wr.rec[r];
         const float fo = (float)off;
-        const float av = load1(sc.own, (__float_as_int(rec.x) + q) << 2);
+        const float av = load1(sc.own, (__float_as_int(rec.x) + q) << 3);
         const float c = sample_contrib(sc, av, fmaf(jx, fo, rec.y), fmaf(jy, fo, rec.z), fmaf(jz, fo, rec.w));
         const float y = c - comp;
         const float t = sum + y;
