@@ -180,6 +180,89 @@ dsm_status dsm_rasterize_owner(dsm_problem* p, const float* Xgrid, int32_t* owne
 dsm_status dsm_problem_timing(dsm_problem* p, int32_t capacity);
 dsm_status dsm_problem_timing_read(dsm_problem* p, float* ms, int32_t max_n, int32_t* n);
 
+/* ---------------------------------------------------------------------------
+ * Learned pre-screening of partial-evaluation candidates (single-point FOS
+ * elements).  Not part of the paper's method: a small MLP 192 -> 128 -> 128 ->
+ * 3 (ReLU) predicts the three objective deltas of a candidate from local
+ * features and is trained on the deltas that dsm_eval_partial computes
+ * exactly; the exact evaluation stays the judge of every accepted change.
+ * Matrix products run as BF16 matrix-core instructions with FP32 accumulation;
+ * master weights and Adam state are FP32.
+ *
+ * Feature row of candidate k of element f (single point p) of solution s,
+ * float32 [192]:
+ *   [0, 6)     candidate minus current position of p (grid 0 xyz, grid 1 xyz);
+ *   [6, 162)   for each of the 26 lattice neighbours q = p + o, o in
+ *              {-1,0,1}^3 without 0 (dz, dy, dx order, dx fastest), grid 0 then
+ *              grid 1, xyz: (X[q] - candidate) - (U[q] - U[p]) with U the
+ *              undeformed grid; 0 where q does not exist;
+ *   [162, 188) source image at (grid-0 candidate + h o) minus target image at
+ *              (grid-1 candidate + h o), clamped trilinear, h = half the
+ *              undeformed cube extent per axis;
+ *   [188, 192) 0.
+ * Network inputs are the rows standardised with the fitted scaling and rounded
+ * to BF16; outputs are standardised deltas.
+ * ------------------------------------------------------------------------- */
+#define DSM_SUR_FEATURES 192
+#define DSM_SUR_HIDDEN 128
+#define DSM_SUR_OUTPUTS 3
+#define DSM_SUR_NPARAMS 43280 /* W1[128][192] b1[128] W2[128][128] b2[128] W3[16][128] b3[16]; rows 3..15 of W3 and b3 unused (0) */
+
+typedef struct dsm_surrogate dsm_surrogate;
+typedef struct {
+  uint64_t seed;     /* weight initialisation and minibatch sampling */
+  float lr, beta1, beta2, eps; /* Adam */
+  int32_t max_rows;  /* largest S*F*K passed to dsm_surrogate_screen */
+  int32_t max_batch; /* largest minibatch / gradient batch (multiple of 32) */
+} dsm_surrogate_desc;
+
+dsm_status dsm_surrogate_create(const dsm_surrogate_desc* desc, dsm_surrogate** out);
+dsm_status dsm_surrogate_destroy(dsm_surrogate* s);
+const char* dsm_surrogate_last_error(void);
+/* FP32 master parameters, host [DSM_SUR_NPARAMS]: set != 0 writes them (and
+ * refreshes the BF16 copies, synchronously), else reads them. */
+dsm_status dsm_surrogate_params(dsm_surrogate* s, float* host, int32_t set);
+/* Fits the input / output standardisation to N feature rows feats dev
+ * [N][192] and raw deltas dev [N][3] (column mean and 1/std; constant columns
+ * get 1/std = 1).  Synchronises the stream. */
+dsm_status dsm_surrogate_fit_scaling(dsm_surrogate* s, int32_t N, const float* feats, const float* deltas, void* stream);
+/* Host copies of the fitted scaling (any output may be NULL). */
+dsm_status dsm_surrogate_get_scaling(dsm_surrogate* s, float* in_mean, float* in_rstd, float* out_mean, float* out_rstd);
+/* Raw feature rows feats dev [S*F*K][192] for candidates cand dev
+ * [S][F][K][2][3] of single-point elements fos_pts dev [F] of solutions X. */
+dsm_status dsm_surrogate_features(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
+                                  const float* cand, float* feats, void* stream);
+/* Standardises N rows: feats dev [N][192] -> feats_bf16 dev [N][192] (bits of
+ * BF16), and deltas part_new - part_old (dev [N][3] float64) -> targets dev
+ * [N][3] (standardised) and raw_deltas dev [N][3]; any pair may be NULL. */
+dsm_status dsm_surrogate_pack(dsm_surrogate* s, int32_t N, const float* feats, uint16_t* feats_bf16,
+                              const double* part_old, const double* part_new, float* targets, float* raw_deltas,
+                              void* stream);
+/* Network outputs (standardised) pred dev [N][3] for BF16 rows. */
+dsm_status dsm_surrogate_forward(dsm_surrogate* s, int32_t N, const uint16_t* feats_bf16, float* pred, void* stream);
+/* Gradient of the mean squared error (1/N sum_rows mean_outputs (y - t)^2)
+ * over all N <= max_batch rows, without an update: grad dev [DSM_SUR_NPARAMS]
+ * in the parameter layout, loss dev [1] or NULL. */
+dsm_status dsm_surrogate_gradient(dsm_surrogate* s, int32_t N, const uint16_t* feats_bf16, const float* targets,
+                                  float* grad, float* loss, void* stream);
+/* `steps` Adam steps on minibatches of `batch` rows drawn (counter-based, with
+ * replacement) from the N rows; loss dev [steps] or NULL receives each
+ * minibatch loss before its update. */
+dsm_status dsm_surrogate_train(dsm_surrogate* s, int32_t N, const uint16_t* feats_bf16, const float* targets,
+                               int32_t steps, int32_t batch, float* loss, void* stream);
+/* Screens K candidates cand dev [S][F][K][2][3] of single-point elements:
+ * pick dev [S][F] = the candidate with the best predicted Pareto rank among the
+ * K (ties: smallest sum of standardised predictions); run_exact dev [S][F] = 1
+ * iff its predicted delta is accepted (improves an objective without worsening
+ * another, or, with obj dev [S][3] and an archive dev [n_archive][3], the
+ * predicted objective vector is not dominated by an archive member).  pred dev
+ * [S][F][K][3] (raw predicted deltas) and cand_pick dev [S][F][2][3] (the
+ * picked candidates) may be NULL.  Errors: DSM_ERR_CAPACITY if S*F*K > max_rows. */
+dsm_status dsm_surrogate_screen(dsm_surrogate* s, dsm_problem* p, int32_t S, const float* X, int32_t F,
+                                const int32_t* fos_pts, int32_t K, const float* cand, const double* obj,
+                                int32_t n_archive, const double* archive, float* pred, int32_t* pick,
+                                uint8_t* run_exact, float* cand_pick, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

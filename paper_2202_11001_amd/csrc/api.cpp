@@ -14,32 +14,6 @@
 
 using namespace dsm;
 
-struct dsm_problem {
-  DevProblem dev{};
-  HostTopology topo;
-  int dims[3]{};
-  int mesh[3]{};
-  int64_t V = 0;
-  int max_S = 0, max_F = 0, max_pts = 0, maxA = 0;
-  int device = 0;
-  // device buffers owned by the problem
-  float* d_img = nullptr;       // [2][Dz][Dy][Dx][2] z-pair interleaved, each image padded
-  size_t img_stride = 0;
-  int* d_tets = nullptr;
-  double* d_tet_w = nullptr;
-  int* d_star_off = nullptr;
-  int* d_star = nullptr;
-  double* d_gpt = nullptr;      // [n_m + n_f][3]
-  int* d_gcorr = nullptr;
-  int* d_aff = nullptr;         // [max_F][maxA]
-  int* d_aff_cnt = nullptr;     // [max_F]
-  double* d_terms = nullptr;    // [max_S][T][3] workspace for full evaluation
-  double* d_simws = nullptr;    // swept dissimilarity per (solution, group, version, tetrahedron)
-  size_t simws_len = 0;
-  std::vector<float> identity;  // [P][3]
-  std::vector<hipEvent_t> ev;   // timing event pairs (begin, end)
-  int ev_used = 0;
-};
 
 namespace {
 
@@ -70,7 +44,7 @@ void release(dsm_problem* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   void* bufs[] = {p->d_img, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
-                  p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws};
+                  p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws, p->d_ident};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -231,6 +205,9 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
   DSM_TRY(dev_alloc(&p->d_aff, (size_t)std::max(1, p->max_F) * p->maxA), "hipMalloc affected sets");
   DSM_TRY(dev_alloc(&p->d_aff_cnt, (size_t)std::max(1, p->max_F)), "hipMalloc affected counts");
   DSM_TRY(dev_alloc(&p->d_terms, (size_t)p->max_S * tp.T * 3), "hipMalloc term workspace");
+  DSM_TRY(dev_alloc(&p->d_ident, p->identity.size()), "hipMalloc undeformed grid");
+  DSM_TRY(hipMemcpy(p->d_ident, p->identity.data(), sizeof(float) * p->identity.size(), hipMemcpyHostToDevice),
+          "copy undeformed grid");
   {
     const size_t full_groups = (size_t)(tp.T + kFullChunk - 1) / kFullChunk;
     p->simws_len = std::max((size_t)p->max_S * std::max(1, p->max_F) * 2 * p->maxA,

@@ -86,3 +86,32 @@ hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* 
 size_t eval_lds_bytes(int maxA, int nver);
 
 }  // namespace dsm
+
+// The problem object behind the opaque ABI handle.
+struct dsm_problem {
+  dsm::DevProblem dev{};
+  dsm::HostTopology topo;
+  int dims[3]{};
+  int mesh[3]{};
+  int64_t V = 0;
+  int max_S = 0, max_F = 0, max_pts = 0, maxA = 0;
+  int device = 0;
+  // device buffers owned by the problem
+  float* d_img = nullptr;       // [2][Dz][Dy][Dx][2] z-pair interleaved, each image padded
+  size_t img_stride = 0;
+  int* d_tets = nullptr;
+  double* d_tet_w = nullptr;
+  int* d_star_off = nullptr;
+  int* d_star = nullptr;
+  double* d_gpt = nullptr;      // [n_m + n_f][3]
+  int* d_gcorr = nullptr;
+  int* d_aff = nullptr;         // [max_F][maxA]
+  int* d_aff_cnt = nullptr;     // [max_F]
+  double* d_terms = nullptr;    // [max_S][T][3] workspace for full evaluation
+  double* d_simws = nullptr;    // swept dissimilarity per (solution, group, version, tetrahedron)
+  size_t simws_len = 0;
+  std::vector<float> identity;  // [P][3]
+  float* d_ident = nullptr;     // device copy of the undeformed grid [P][3]
+  std::vector<hipEvent_t> ev;   // timing event pairs (begin, end)
+  int ev_used = 0;
+};

@@ -36,6 +36,11 @@ class ProblemDesc(C.Structure):
                 ("max_solutions", C.c_int32), ("max_fos", C.c_int32), ("max_fos_points", C.c_int32)]
 
 
+class SurrogateDesc(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("max_rows", C.c_int32), ("max_batch", C.c_int32)]
+
+
 class ProblemInfo(C.Structure):
     _fields_ = [("P", C.c_int32), ("T", C.c_int32), ("E", C.c_int32), ("max_star", C.c_int32),
                 ("V", C.c_int64), ("max_affected", C.c_int32), ("norm", C.c_double * 3)]
@@ -66,6 +71,18 @@ def lib():
             "dsm_rasterize_owner": ([V, V, V, V, V], I),
             "dsm_problem_timing": ([V, I], I),
             "dsm_problem_timing_read": ([V, V, I, V], I),
+            "dsm_surrogate_create": ([V, V], I),
+            "dsm_surrogate_destroy": ([V], I),
+            "dsm_surrogate_last_error": ([], C.c_char_p),
+            "dsm_surrogate_params": ([V, V, I], I),
+            "dsm_surrogate_fit_scaling": ([V, I, V, V, V], I),
+            "dsm_surrogate_get_scaling": ([V, V, V, V, V], I),
+            "dsm_surrogate_features": ([V, I, V, I, V, I, V, V, V], I),
+            "dsm_surrogate_pack": ([V, I, V, V, V, V, V, V, V], I),
+            "dsm_surrogate_forward": ([V, I, V, V, V], I),
+            "dsm_surrogate_gradient": ([V, I, V, V, V, V, V], I),
+            "dsm_surrogate_train": ([V, I, V, V, I, I, V, V], I),
+            "dsm_surrogate_screen": ([V, V, I, V, I, V, I, V, V, I, V, V, V, V, V, V], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -237,3 +254,111 @@ class Problem:
         overlap = torch.empty(1, dtype=torch.int32, device=Xgrid.device)
         _check(lib().dsm_rasterize_owner(self._h, _dptr(Xgrid), _dptr(owner), _dptr(overlap), _stream(stream)))
         return owner, overlap
+
+
+SUR_FEATURES, SUR_OUTPUTS, SUR_NPARAMS = 192, 3, 43280
+
+
+def _scheck(st):
+    if st != OK:
+        L = lib()
+        raise DsmError(st, f"{L.dsm_status_string(st).decode()}: {L.dsm_surrogate_last_error().decode()}")
+
+
+class Surrogate:
+    """Candidate-screening MLP on the current GPU (``dsm_surrogate``)."""
+
+    def __init__(self, seed=0, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, max_rows=1 << 16, max_batch=4096):
+        d = SurrogateDesc(seed=seed, lr=lr, beta1=beta1, beta2=beta2, eps=eps, max_rows=max_rows, max_batch=max_batch)
+        h = C.c_void_p()
+        _scheck(lib().dsm_surrogate_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.max_rows, self.max_batch = max_rows, max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dsm_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self, new=None):
+        if new is not None:
+            a = np.ascontiguousarray(new, dtype=np.float32)
+            assert a.size == SUR_NPARAMS
+            _scheck(lib().dsm_surrogate_params(self._h, _np_ptr(a), 1))
+            return a
+        a = np.zeros(SUR_NPARAMS, np.float32)
+        _scheck(lib().dsm_surrogate_params(self._h, _np_ptr(a), 0))
+        return a
+
+    def fit_scaling(self, feats, deltas, stream=None):
+        _scheck(lib().dsm_surrogate_fit_scaling(self._h, feats.shape[0], _dptr(feats), _dptr(deltas), _stream(stream)))
+
+    def scaling(self):
+        im, ir = np.zeros(SUR_FEATURES, np.float32), np.zeros(SUR_FEATURES, np.float32)
+        om, orr = np.zeros(SUR_OUTPUTS, np.float32), np.zeros(SUR_OUTPUTS, np.float32)
+        _scheck(lib().dsm_surrogate_get_scaling(self._h, _np_ptr(im), _np_ptr(ir), _np_ptr(om), _np_ptr(orr)))
+        return im, ir, om, orr
+
+    @staticmethod
+    def features(problem, X, pts, cand, stream=None):
+        """Raw features [S*F*K][192] of candidates cand [S][F][K][2][3]."""
+        torch = _torch()
+        S, F, K = cand.shape[:3]
+        out = torch.empty((S * F * K, SUR_FEATURES), dtype=torch.float32, device=X.device)
+        _scheck(lib().dsm_surrogate_features(problem._h, S, _dptr(X), F, _dptr(pts), K, _dptr(cand), _dptr(out),
+                                             _stream(stream)))
+        return out
+
+    def pack(self, feats=None, part_old=None, part_new=None, stream=None):
+        """(bf16 feature rows as int16, standardised targets, raw deltas)."""
+        torch = _torch()
+        N = feats.shape[0] if feats is not None else part_old.shape[0]
+        dev = (feats if feats is not None else part_old).device
+        fb = torch.empty((N, SUR_FEATURES), dtype=torch.int16, device=dev) if feats is not None else None
+        tg = torch.empty((N, SUR_OUTPUTS), dtype=torch.float32, device=dev) if part_old is not None else None
+        raw = torch.empty((N, SUR_OUTPUTS), dtype=torch.float32, device=dev) if part_old is not None else None
+        _scheck(lib().dsm_surrogate_pack(self._h, N, _dptr(feats), _dptr(fb), _dptr(part_old), _dptr(part_new),
+                                         _dptr(tg), _dptr(raw), _stream(stream)))
+        return fb, tg, raw
+
+    def forward(self, feats_bf16, stream=None):
+        torch = _torch()
+        N = feats_bf16.shape[0]
+        out = torch.empty((N, SUR_OUTPUTS), dtype=torch.float32, device=feats_bf16.device)
+        _scheck(lib().dsm_surrogate_forward(self._h, N, _dptr(feats_bf16), _dptr(out), _stream(stream)))
+        return out
+
+    def gradient(self, feats_bf16, targets, stream=None):
+        torch = _torch()
+        g = torch.empty(SUR_NPARAMS, dtype=torch.float32, device=targets.device)
+        loss = torch.empty(1, dtype=torch.float32, device=targets.device)
+        _scheck(lib().dsm_surrogate_gradient(self._h, feats_bf16.shape[0], _dptr(feats_bf16), _dptr(targets), _dptr(g),
+                                             _dptr(loss), _stream(stream)))
+        return g, loss
+
+    def train(self, feats_bf16, targets, steps, batch, stream=None):
+        torch = _torch()
+        loss = torch.empty(max(steps, 1), dtype=torch.float32, device=targets.device)
+        _scheck(lib().dsm_surrogate_train(self._h, feats_bf16.shape[0], _dptr(feats_bf16), _dptr(targets), int(steps),
+                                          int(batch), _dptr(loss), _stream(stream)))
+        return loss[:steps]
+
+    def screen(self, problem, X, pts, cand, obj=None, archive=None, stream=None):
+        """(pick [S][F], run_exact [S][F] uint8, raw predictions [S][F][K][3], picked candidates [S][F][2][3])."""
+        torch = _torch()
+        S, F, K = cand.shape[:3]
+        pred = torch.empty((S, F, K, SUR_OUTPUTS), dtype=torch.float32, device=X.device)
+        pick = torch.empty((S, F), dtype=torch.int32, device=X.device)
+        run = torch.empty((S, F), dtype=torch.uint8, device=X.device)
+        cp = torch.empty((S, F, 2, 3), dtype=torch.float32, device=X.device)
+        na = 0 if archive is None else archive.shape[0]
+        _scheck(lib().dsm_surrogate_screen(self._h, problem._h, S, _dptr(X), F, _dptr(pts), K, _dptr(cand), _dptr(obj),
+                                           na, _dptr(archive), _dptr(pred), _dptr(pick), _dptr(run), _dptr(cp),
+                                           _stream(stream)))
+        return pick, run, pred, cp
