@@ -64,6 +64,7 @@ typedef int32_t dsm_status;
 #define DSM_FLAG_LATTICE 16u    /* a coordinate is not on the 1/128-voxel lattice */
 #define DSM_FLAG_NONFINITE 32u  /* a coordinate is NaN or infinite */
 #define DSM_FLAG_BAD_FOS 64u    /* FOS element malformed (point index, size) */
+#define DSM_FLAG_SKIPPED 128u   /* not evaluated: masked out by the caller */
 
 const char* dsm_status_string(dsm_status s);
 /* Message of the last error on the calling thread ("" if none). */
@@ -161,6 +162,15 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
                             double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
                             void* stream);
 
+/* dsm_eval_partial restricted to the (solution, element) pairs whose entry in
+ * mask dev [S][F] (uint8) is non-zero; the other pairs cost a workgroup launch
+ * only, get flags = DSM_FLAG_SKIPPED, zero partial sums and no term writes.
+ * mask NULL evaluates every pair. */
+dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                                   const int32_t* fos_pts, const float* cand, const uint8_t* mask,
+                                   const double* tet_terms_in, double* part_old, double* part_new, uint32_t* flags,
+                                   double* tet_terms_new, uint32_t* voxel_count, void* stream);
+
 /* Test hook for Sec. 2.3.1 rasterisation: owner dev [Dz][Dy][Dx] int32 receives
  * the id of the tetrahedron of grid coordinates Xgrid dev [P][3] whose exact
  * voxel set contains each voxel (-1 if none); overlap dev [1] int32 counts
@@ -253,15 +263,43 @@ dsm_status dsm_surrogate_train(dsm_surrogate* s, int32_t N, const uint16_t* feat
 /* Screens K candidates cand dev [S][F][K][2][3] of single-point elements:
  * pick dev [S][F] = the candidate with the best predicted Pareto rank among the
  * K (ties: smallest sum of standardised predictions); run_exact dev [S][F] = 1
- * iff its predicted delta is accepted (improves an objective without worsening
- * another, or, with obj dev [S][3] and an archive dev [n_archive][3], the
- * predicted objective vector is not dominated by an archive member).  pred dev
+ * iff its predicted delta is accepted by the rule of dsm_accept (with obj dev
+ * [S][3] and an archive dev [n_archive][3]; without them only changes that
+ * improve an objective and worsen none pass).  pred dev
  * [S][F][K][3] (raw predicted deltas) and cand_pick dev [S][F][2][3] (the
  * picked candidates) may be NULL.  Errors: DSM_ERR_CAPACITY if S*F*K > max_rows. */
 dsm_status dsm_surrogate_screen(dsm_surrogate* s, dsm_problem* p, int32_t S, const float* X, int32_t F,
                                 const int32_t* fos_pts, int32_t K, const float* cand, const double* obj,
                                 int32_t n_archive, const double* archive, float* pred, int32_t* pick,
                                 uint8_t* run_exact, float* cand_pick, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Generation steps of a population optimiser (single-point FOS elements).
+ * ------------------------------------------------------------------------- */
+
+/* cand dev [S][F][K][2][3]: the current position of point fos_pts[f] (dev [F])
+ * in both grids plus N(0, sigma) voxels on its free (non-border) axes, clamped to
+ * the image box and rounded to the 1/128-voxel lattice.  The normal deviates
+ * come from a counter-based generator keyed by (seed, counter, element index):
+ * equal arguments give equal candidates. */
+dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
+                                 float sigma, uint64_t seed, uint64_t counter, float* cand, void* stream);
+
+/* Sec. 2.2: accepts the partial changes of one evaluated batch of single-point
+ * elements whose affected tetrahedra are pairwise disjoint (e.g. points of one
+ * index-parity class) and applies them together.  A change is accepted iff its
+ * flags are 0 and its delta (part_new - part_old, dev [S][F][3]) improves one
+ * objective without worsening another, or improves one objective and the new
+ * objective vector obj[s] + delta is not dominated by any of the n_archive
+ * vectors archive dev [n][3].  Accepted changes write cand dev [S][F][2][3] into
+ * X dev [S][2][P][3] and copy the candidate terms of the point's star from
+ * terms_cand dev [S][T][3] (as written by dsm_eval_partial(_masked)) into
+ * terms_cache dev [S][T][3]; obj dev [S][3] is then recomputed from the cache.
+ * accepted dev [S][F] (uint8) or NULL. */
+dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_pts, const float* cand,
+                      const double* part_old, const double* part_new, const uint32_t* flags, const double* terms_cand,
+                      double* terms_cache, double* obj, int32_t n_archive, const double* archive, uint8_t* accepted,
+                      void* stream);
 
 #ifdef __cplusplus
 }

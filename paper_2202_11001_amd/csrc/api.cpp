@@ -349,8 +349,9 @@ dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj,
   return DSM_OK;
 }
 
-dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
-                            const int32_t* fos_pts, const float* cand, const double* tet_terms_in, double* part_old,
+dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                                   const int32_t* fos_pts, const float* cand, const uint8_t* mask,
+                                   const double* tet_terms_in, double* part_old,
                             double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
                             void* stream) {
   g_err.clear();
@@ -382,10 +383,19 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
   a.flags = flags;
   a.terms_out = tet_terms_new;
   a.vcount = voxel_count;
+  a.mask = mask;
   hipEvent_t eb, ee;
   timing_pair(p, eb, ee);
   if ((e = launch_eval(a, p->d_simws, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
   return DSM_OK;
+}
+
+dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                            const int32_t* fos_pts, const float* cand, const double* tet_terms_in, double* part_old,
+                            double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
+                            void* stream) {
+  return dsm_eval_partial_masked(p, S, X, F, fos_off, fos_pts, cand, nullptr, tet_terms_in, part_old, part_new, flags,
+                                 tet_terms_new, voxel_count, stream);
 }
 
 dsm_status dsm_problem_timing(dsm_problem* p, int32_t capacity) {

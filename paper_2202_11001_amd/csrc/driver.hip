@@ -1,0 +1,142 @@
+// Generation step support for a population optimiser on top of the evaluator:
+// a counter-based candidate sampler and the acceptance of partial changes.
+//
+// Sec. 2.2: each partial change is accepted only if it improves the solution;
+// changes to FOS elements whose affected tetrahedra are disjoint (one colour
+// class of single points: equal index parity on every axis) are independent, so
+// all accepted changes of a class are applied together.  "Improves" is read in
+// the multi-objective sense: the candidate is feasible and either Pareto-
+// dominates the current solution or is not dominated by any member of the
+// elitist archive.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "dsm_internal.h"
+
+namespace dsm {
+namespace {
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// standard normal from two counter-based uniforms (Box-Muller)
+__device__ __forceinline__ double normal(unsigned long long seed, unsigned long long ctr) {
+  const unsigned long long a = mix64(seed + 0x9e3779b97f4a7c15ull * (2 * ctr + 1));
+  const unsigned long long b = mix64(seed + 0x9e3779b97f4a7c15ull * (2 * ctr + 2));
+  const double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+  const double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// cand [S][F][K][2][3]: current position of single point pts[f] plus
+// N(0, sigma) voxels on its free axes, clamped to the image box and rounded to
+// the 1/128-voxel lattice (half to even).
+__global__ void k_sample(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ pts, int K,
+                         float sigma, unsigned long long seed, unsigned long long counter, float* __restrict__ cand) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)S * F * K * 6;
+  if (e >= n) return;
+  const int comp = (int)(e % 6);
+  const int64_t row = e / 6;
+  const int f = (int)((row / K) % F);
+  const int s = (int)(row / ((int64_t)F * K));
+  const int g = comp / 3, a = comp % 3;
+  const int p = pts[f];
+  if (p < 0 || p >= pr.P) {
+    cand[e] = NAN;  // flagged as non-finite by the evaluator
+    return;
+  }
+  const float x = X[(((size_t)s * 2 + g) * pr.P + p) * 3 + a];
+  const int idx = a == 0 ? p % pr.n[0] : (a == 1 ? (p / pr.n[0]) % pr.n[1] : p / (pr.n[0] * pr.n[1]));
+  const bool free_axis = idx > 0 && idx < pr.n[a] - 1;
+  double v = x;
+  if (free_axis) {
+    v += sigma * normal(seed, counter * 0x100000000ull + (unsigned long long)e);
+    v = fmin(fmax(v, -0.5), pr.D[a] - 0.5);
+  }
+  v = rint((v + 0.5) * kLat) / kLat - 0.5;
+  cand[e] = (float)v;
+}
+
+// Accept / apply one colour class of single-point elements.
+__global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, const int* __restrict__ pts,
+                         const float* __restrict__ cand, const double* __restrict__ part_old,
+                         const double* __restrict__ part_new, const uint32_t* __restrict__ flags,
+                         const double* __restrict__ terms_cand, double* __restrict__ cache,
+                         const double* __restrict__ obj, int n_arch, const double* __restrict__ arch,
+                         unsigned char* __restrict__ accepted) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S * F) return;
+  const int s = e / F, f = e % F;
+  bool acc = flags[e] == 0u;
+  if (acc) {
+    double d[3], nv[3];
+    bool le = true, lt = false;
+    for (int o = 0; o < 3; ++o) {
+      d[o] = part_new[(size_t)e * 3 + o] - part_old[(size_t)e * 3 + o];
+      nv[o] = obj[(size_t)s * 3 + o] + d[o];
+      le = le && d[o] <= 0.0;
+      lt = lt || d[o] < 0.0;
+    }
+    acc = le && lt;
+    if (!acc && n_arch > 0) {
+      bool dominated = false, improves = false;
+      for (int o = 0; o < 3; ++o) improves = improves || d[o] < 0.0;
+      for (int q = 0; q < n_arch && !dominated; ++q) {
+        bool ale = true, alt = false;
+        for (int o = 0; o < 3; ++o) {
+          ale = ale && arch[(size_t)q * 3 + o] <= nv[o];
+          alt = alt || arch[(size_t)q * 3 + o] < nv[o];
+        }
+        dominated = ale && alt;
+      }
+      acc = improves && !dominated;
+    }
+  }
+  if (accepted) accepted[e] = acc ? 1 : 0;
+  if (!acc) return;
+  const int p = pts[f];
+  for (int c = 0; c < 6; ++c) X[(((size_t)s * 2 + c / 3) * pr.P + p) * 3 + c % 3] = cand[(size_t)e * 6 + c];
+  for (int j = pr.star_off[p]; j < pr.star_off[p + 1]; ++j) {
+    const size_t t = (size_t)s * pr.T + pr.star[j];
+    for (int o = 0; o < 3; ++o) cache[t * 3 + o] = terms_cand[t * 3 + o];
+  }
+}
+
+}  // namespace
+}  // namespace dsm
+
+using namespace dsm;
+
+extern "C" {
+
+dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
+                                 float sigma, uint64_t seed, uint64_t counter, float* cand, void* stream) {
+  if (!p || !X || !fos_pts || !cand || S < 0 || F < 0 || K < 1 || !(sigma >= 0.f)) return DSM_ERR_ARG;
+  const int64_t n = (int64_t)S * F * K * 6;
+  if (n == 0) return DSM_OK;
+  k_sample<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(p->dev, S, X, F, fos_pts, K, sigma, seed,
+                                                                       counter, cand);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_pts, const float* cand,
+                      const double* part_old, const double* part_new, const uint32_t* flags, const double* terms_cand,
+                      double* terms_cache, double* obj, int32_t n_archive, const double* archive, uint8_t* accepted,
+                      void* stream) {
+  if (!p || !X || !fos_pts || !cand || !part_old || !part_new || !flags || !terms_cand || !terms_cache || !obj)
+    return DSM_ERR_ARG;
+  if (S < 0 || F < 0 || n_archive < 0 || (n_archive > 0 && !archive) || S > p->max_S) return DSM_ERR_ARG;
+  if (S == 0) return DSM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (F > 0)
+    k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, fos_pts, cand, part_old, part_new, flags, terms_cand,
+                                                   terms_cache, obj, n_archive, archive, accepted);
+  if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
+  return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+}  // extern "C"

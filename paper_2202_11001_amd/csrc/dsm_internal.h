@@ -59,6 +59,7 @@ struct EvalArgs {
   uint32_t* flags;       // [S][G]
   double* terms_out;     // [S][T][3] or null
   uint32_t* vcount;      // [S][G] or null
+  const uint8_t* mask;   // [S][G] or null: evaluate only where non-zero (partial)
 };
 
 // Host-side topology (topology.cpp).

@@ -614,6 +614,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
     }
     return;
   }
+  if (PARTIAL && a.mask && a.mask[(size_t)s * a.G + g] == 0) {  // not requested
+    if (tid == 0) {
+      a.flags[(size_t)s * a.G + g] = DSM_FLAG_SKIPPED;
+      if (a.vcount) a.vcount[(size_t)s * a.G + g] = 0;
+    }
+    return;
+  }
   if (tid == 0) s_flags = 0u;
   if (tid < kWaves) s_count[tid] = 0u;
   for (int i = tid; i < na; i += kWG) s_tet[i] = group_tet(a, g, i);
@@ -784,7 +791,7 @@ __global__ __launch_bounds__(64) void k_finish(EvalArgs a, const double* __restr
   const int g = logical / a.S, s = logical - g * a.S;
   const int na = group_size(a, g);
   const size_t oi = (size_t)s * a.G + g;
-  if (na < 0) {
+  if (na < 0 || (a.partial && a.mask && a.mask[oi] == 0)) {
     if (lane < 3) {
       a.part_new[oi * 3 + lane] = 0.0;
       a.part_old[oi * 3 + lane] = 0.0;

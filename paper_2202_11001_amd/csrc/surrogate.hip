@@ -423,8 +423,9 @@ __global__ void k_targets(int N, const double* __restrict__ old, const double* _
 // Screening: per (solution, element) choose one of K candidates by predicted
 // Pareto rank among the K (ties: smallest sum of standardised predictions) and
 // flag it for exact evaluation iff its predicted delta would be accepted: it
-// improves one objective without worsening another, or the predicted objective
-// vector is not dominated by any archive member.
+// improves one objective without worsening another, or it improves one
+// objective and the predicted objective vector is not dominated by any archive
+// member.
 __global__ void k_select(int S, int F, int K, const float* __restrict__ pred_std, const float* __restrict__ out_mean,
                          const float* __restrict__ out_scale, const double* __restrict__ obj, int n_arch,
                          const double* __restrict__ arch, float* __restrict__ pred_raw, int* __restrict__ pick,
@@ -466,7 +467,9 @@ __global__ void k_select(int S, int F, int K, const float* __restrict__ pred_std
     lt = lt || d[o] < 0.0;
   }
   bool accept = le && lt;
-  if (!accept && obj && n_arch > 0) {
+  bool improves = false;
+  for (int o = 0; o < kOut; ++o) improves = improves || d[o] < 0.0;
+  if (!accept && improves && obj && n_arch > 0) {
     double nv[kOut];
     for (int o = 0; o < kOut; ++o) nv[o] = obj[(size_t)s * kOut + o] + d[o];
     bool dominated = false;

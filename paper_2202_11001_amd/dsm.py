@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "dsm.h")
 OK, ERR_ARG, ERR_CAPACITY, ERR_DOMAIN, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = range(7)
 FLAG_INV_MOVING, FLAG_INV_FIXED, FLAG_BORDER, FLAG_DOMAIN, FLAG_LATTICE, FLAG_NONFINITE, FLAG_BAD_FOS = (
     1, 2, 4, 8, 16, 32, 64)
+FLAG_SKIPPED = 128
 
 
 class DsmError(RuntimeError):
@@ -71,6 +72,9 @@ def lib():
             "dsm_rasterize_owner": ([V, V, V, V, V], I),
             "dsm_problem_timing": ([V, I], I),
             "dsm_problem_timing_read": ([V, V, I, V], I),
+            "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
+            "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V], I),
+            "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_surrogate_create": ([V, V], I),
             "dsm_surrogate_destroy": ([V], I),
             "dsm_surrogate_last_error": ([], C.c_char_p),
@@ -223,7 +227,7 @@ class Problem:
         return obj, flags
 
     def eval_partial(self, X, fos_off, fos_pts, cand, tet_terms_in=None, tet_terms_new=None, voxel_count=False,
-                     out=None, stream=None):
+                     out=None, mask=None, stream=None):
         torch = _torch()
         S, F = X.shape[0], fos_off.shape[0] - 1
         if out is None:
@@ -232,10 +236,33 @@ class Problem:
                    torch.empty((S, F), dtype=torch.int32, device=X.device),
                    torch.empty((S, F), dtype=torch.int32, device=X.device) if voxel_count else None)
         old, new, flags, vc = out
-        _check(lib().dsm_eval_partial(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
-                                      _dptr(tet_terms_in), _dptr(old), _dptr(new), _dptr(flags),
-                                      _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
+        if mask is None:
+            _check(lib().dsm_eval_partial(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                          _dptr(tet_terms_in), _dptr(old), _dptr(new), _dptr(flags),
+                                          _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
+        else:
+            _check(lib().dsm_eval_partial_masked(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                                 _dptr(mask), _dptr(tet_terms_in), _dptr(old), _dptr(new),
+                                                 _dptr(flags), _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
         return out
+
+    def sample_candidates(self, X, pts, K, sigma, seed, counter, out=None, stream=None):
+        """Candidates [S][F][K][2][3] (K > 1) or [S][F][2][3] (K == 1)."""
+        torch = _torch()
+        S, F = X.shape[0], pts.shape[0]
+        if out is None:
+            shape = (S, F, 2, 3) if K == 1 else (S, F, K, 2, 3)
+            out = torch.empty(shape, dtype=torch.float32, device=X.device)
+        _check(lib().dsm_sample_candidates(self._h, S, _dptr(X), F, _dptr(pts), int(K), float(sigma), int(seed),
+                                           int(counter), _dptr(out), _stream(stream)))
+        return out
+
+    def accept(self, X, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
+               accepted=None, stream=None):
+        na = 0 if archive is None else archive.shape[0]
+        _check(lib().dsm_accept(self._h, X.shape[0], _dptr(X), pts.shape[0], _dptr(pts), _dptr(cand),
+                                _dptr(part_old), _dptr(part_new), _dptr(flags), _dptr(terms_cand), _dptr(terms_cache),
+                                _dptr(obj), na, _dptr(archive), _dptr(accepted), _stream(stream)))
 
     def timing(self, capacity):
         """Record the sweep kernel's duration in the next `capacity` evaluation calls."""

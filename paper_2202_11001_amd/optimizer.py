@@ -1,0 +1,187 @@
+"""A minimal multi-objective population optimiser on top of the GPU evaluator,
+used to measure what learned candidate screening gains.
+
+Each generation visits the 8 index-parity classes of grid points (points of one
+class share no tetrahedron, so their partial changes are independent,
+Sec. 2.2).  Per class every solution proposes one candidate per point (plain)
+or K candidates of which the surrogate picks one and decides whether to
+evaluate it exactly (screened); exact partial evaluation, acceptance (feasible
+and improving: Pareto improvement or not dominated by the elitist archive) and
+the update of coordinates, term cache and objectives all run in the library's
+kernels.  The elitist archive (non-dominated objective vectors) and the
+hypervolume are kept on the host.
+
+This is not RV-GOMEA: candidates are isotropic Gaussian moves, not samples of
+an estimated distribution.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import dsm
+
+
+def parity_classes(mesh):
+    """Point indices of the 8 index-parity classes, as int32 arrays."""
+    nx, ny, nz = (int(n) for n in mesh)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cls = ((i & 1) + 2 * (j & 1) + 4 * (k & 1)).ravel()
+    return [np.nonzero(cls == c)[0].astype(np.int32) for c in range(8)]
+
+
+def nondominated(points):
+    """Rows of `points` (minimisation) not dominated by another row; duplicates kept once."""
+    pts = np.unique(np.asarray(points, dtype=np.float64), axis=0)
+    if len(pts) == 0:
+        return pts
+    order = np.argsort(pts[:, 0], kind="stable")
+    pts = pts[order]
+    keep = np.ones(len(pts), dtype=bool)
+    for a in range(len(pts)):
+        if not keep[a]:
+            continue
+        dom = np.all(pts[a] <= pts, axis=1) & np.any(pts[a] < pts, axis=1)
+        keep &= ~dom
+    return pts[keep]
+
+
+def hypervolume(points, ref):
+    """Exact 3-D hypervolume dominated by `points` and bounded by `ref`
+    (minimisation): slices along the third objective, each a 2-D union area."""
+    ref = np.asarray(ref, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64)
+    pts = pts[np.all(pts < ref, axis=1)]
+    if len(pts) == 0:
+        return 0.0
+    pts = pts[np.argsort(pts[:, 2], kind="stable")]
+    zs = np.append(pts[:, 2], ref[2])
+    vol = 0.0
+    for s in range(len(pts)):
+        dz = zs[s + 1] - zs[s]
+        if dz <= 0:
+            continue
+        sl = pts[:s + 1, :2]
+        sl = sl[np.argsort(sl[:, 0], kind="stable")]
+        widths = np.diff(np.append(sl[:, 0], ref[0]))
+        area = float(np.sum(widths * (ref[1] - np.minimum.accumulate(sl[:, 1]))))
+        vol += area * dz
+    return vol
+
+
+@dataclass
+class RunLog:
+    hypervolume: list = field(default_factory=list)
+    seconds: list = field(default_factory=list)        # wall time at the end of each generation
+    exact_evals: list = field(default_factory=list)    # exact partial evaluations per generation
+    accepted: list = field(default_factory=list)
+    archive_size: list = field(default_factory=list)
+
+
+class Optimiser:
+    """Population optimiser state on the GPU for one problem."""
+
+    def __init__(self, problem, X, sigma=1.0, seed=1, K=4):
+        import torch
+        self.torch = torch
+        self.p = problem
+        self.X = X.clone()
+        self.S = X.shape[0]
+        self.sigma = float(sigma)
+        self.seed = int(seed)
+        self.K = int(K)
+        self.counter = 0
+        dev = X.device
+        self.classes = [torch.from_numpy(c).to(dev) for c in parity_classes(problem.mesh)]
+        self.offs = [torch.arange(len(c) + 1, dtype=torch.int32, device=dev) for c in self.classes]
+        self.cache = torch.empty((self.S, problem.T, 3), dtype=torch.float64, device=dev)
+        self.terms_cand = torch.zeros_like(self.cache)
+        obj, flags = problem.eval_full(self.X, tet_terms=self.cache)
+        if int((flags != 0).sum().item()):
+            raise ValueError("initial population is infeasible")
+        self.obj = obj
+        self.archive = nondominated(obj.cpu().numpy())
+        self.ref = 1.1 * obj.cpu().numpy().max(axis=0)
+        self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
+
+    def _archive_dev(self):
+        return self.torch.from_numpy(np.ascontiguousarray(self.archive)).to(self.X.device)
+
+    def generation(self, surrogate=None, log=None):
+        """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
+        torch = self.torch
+        n_exact, n_acc = 0, 0
+        arch = self._archive_dev()
+        for pts, off in zip(self.classes, self.offs):
+            F = pts.shape[0]
+            self.counter += 1
+            if surrogate is None:
+                cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, self.counter)
+                mask = None
+            else:
+                candK = self.p.sample_candidates(self.X, pts, self.K, self.sigma, self.seed, self.counter)
+                _, mask, _, cand = surrogate.screen(self.p, self.X, pts, candK, obj=self.obj, archive=arch)
+            old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
+                                                     tet_terms_new=self.terms_cand, mask=mask)
+            if self.collect is not None:
+                feats = dsm.Surrogate.features(self.p, self.X, pts, cand.reshape(self.S, F, 1, 2, 3))
+                ok = (flags == 0).reshape(-1)
+                self.collect.append((feats[ok], old.reshape(-1, 3)[ok], new.reshape(-1, 3)[ok]))
+            acc = torch.empty((self.S, F), dtype=torch.uint8, device=self.X.device)
+            self.p.accept(self.X, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj, archive=arch,
+                          accepted=acc)
+            n_exact += self.S * F if mask is None else int(mask.sum().item())
+            n_acc += int(acc.sum().item())
+        self.archive = nondominated(np.concatenate([self.archive, self.obj.cpu().numpy()]))
+        return n_exact, n_acc
+
+    def hypervolume(self):
+        return hypervolume(self.archive, self.ref)
+
+
+def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20):
+    """A surrogate trained on collected (features, part_old, part_new) rows."""
+    import torch
+    feats = torch.cat([c[0] for c in collected])
+    old = torch.cat([c[1] for c in collected]).contiguous()
+    new = torch.cat([c[2] for c in collected]).contiguous()
+    sur = dsm.Surrogate(seed=seed, max_rows=max_rows, max_batch=batch)
+    sur.fit_scaling(feats, (new - old).to(torch.float32).contiguous())
+    fb, tg, _ = sur.pack(feats, old, new)
+    losses = sur.train(fb, tg, steps=steps, batch=batch)
+    return sur, losses, feats.shape[0]
+
+
+def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
+        K=4, target_hv=None, log_every=0):
+    """Runs `generations` generations; with `train_generations` > 0 the first
+    ones are plain and collect training rows, a surrogate is then trained and
+    the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
+    import torch
+    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K)
+    log = RunLog()
+    t0 = time.perf_counter()
+    sur = surrogate
+    if train_generations > 0:
+        opt.collect = []
+    for g in range(generations):
+        use = sur if (train_generations == 0 or g >= train_generations) else None
+        n_exact, n_acc = opt.generation(surrogate=use)
+        if train_generations > 0 and g + 1 == train_generations:
+            sur, _, _ = train_surrogate(opt.collect, steps=train_steps,
+                                        max_rows=max(1 << 16, opt.S * max(len(c) for c in opt.classes) * K))
+            opt.collect = None
+        torch.cuda.synchronize()
+        log.seconds.append(time.perf_counter() - t0)
+        log.hypervolume.append(opt.hypervolume())
+        log.exact_evals.append(n_exact)
+        log.accepted.append(n_acc)
+        log.archive_size.append(len(opt.archive))
+        if log_every and (g + 1) % log_every == 0:
+            print(f"[optimiser] gen {g + 1}: hv {log.hypervolume[-1]:.6g} exact {n_exact} accepted {n_acc} "
+                  f"archive {len(opt.archive)} t {log.seconds[-1]:.2f}s", flush=True)
+        if target_hv is not None and log.hypervolume[-1] >= target_hv:
+            break
+    return log, opt, sur

@@ -1,0 +1,130 @@
+"""GPU generation steps: counter-based candidate sampling, acceptance and
+application of independent partial changes (Sec. 2.2), and short optimiser
+runs (plain and screened)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2202_11001_amd import optimizer as O
+from paper_2202_11001_amd import workloads as W
+from tests._common import feasible_population, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_11001_amd import dsm  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(f"[gpu-optimiser] {msg}", file=sys.stderr, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def test_sampler_properties():
+    _say("sampler")
+    w = W.batched()
+    gp = dsm.Problem.from_workload(w)
+    I = gp.topology()["identity"]
+    X = np.repeat(np.stack([I, I])[None], 8, axis=0)
+    Xd = _t(X)
+    pts = _t(np.arange(w.P, dtype=np.int32))
+    a = gp.sample_candidates(Xd, pts, 4, 1.5, 42, 7).cpu().numpy()
+    b = gp.sample_candidates(Xd, pts, 4, 1.5, 42, 7).cpu().numpy()
+    c = gp.sample_candidates(Xd, pts, 4, 1.5, 42, 8).cpu().numpy()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    free = W.free_mask(w.mesh)  # [P][3]
+    cur = np.broadcast_to(X.transpose(0, 2, 1, 3)[:, :, None], a.shape)
+    d = a - cur
+    fr = np.broadcast_to(free[None, :, None, None, :], a.shape)
+    assert np.all(d[~fr] == 0)
+    assert np.all(np.rint((a + 0.5) * 128) == (a + 0.5) * 128)
+    hi = np.array(w.dims) - 0.5
+    assert np.all(a >= -0.5) and np.all(a <= hi)
+    dd = d[fr]
+    assert abs(dd.mean()) < 0.02 and abs(dd.std() - 1.5) < 0.03
+
+
+def test_accept_applies_independent_changes():
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    S = X.shape[0]
+    gp = dsm.Problem.from_workload(w)
+    Xd = _t(X)
+    cache = torch.empty((S, gp.T, 3), dtype=torch.float64, device=DEV)
+    obj, _ = gp.eval_full(Xd, tet_terms=cache)
+    obj0 = obj.clone()
+    arch = _t(O.nondominated(obj.cpu().numpy()))
+    cls = O.parity_classes(w.mesh)
+    pts = _t(cls[0])
+    F = len(cls[0])
+    off = _t(np.arange(F + 1, dtype=np.int32))
+    _say("accept one parity class")
+    cand = gp.sample_candidates(Xd, pts, 1, 2.0, 3, 1)
+    terms_cand = torch.zeros_like(cache)
+    old, new, fl, _ = gp.eval_partial(Xd, off, pts, cand, tet_terms_in=cache, tet_terms_new=terms_cand)
+    acc = torch.empty((S, F), dtype=torch.uint8, device=DEV)
+    X1 = Xd.clone()
+    gp.accept(X1, pts, cand, old, new, fl, terms_cand, cache, obj, archive=arch, accepted=acc)
+    torch.cuda.synchronize()
+    # the rule on the GPU's own deltas
+    d = (new - old).cpu().numpy()
+    o0 = obj0.cpu().numpy()
+    A = arch.cpu().numpy()
+    expect = np.zeros((S, F), dtype=bool)
+    for s in range(S):
+        for f in range(F):
+            if fl[s, f].item() != 0:
+                continue
+            dd = d[s, f]
+            if np.all(dd <= 0) and np.any(dd < 0):
+                expect[s, f] = True
+            elif np.any(dd < 0):
+                nv = o0[s] + dd
+                expect[s, f] = not np.any(np.all(A <= nv, axis=1) & np.any(A < nv, axis=1))
+    got = acc.cpu().numpy().astype(bool)
+    assert np.array_equal(got, expect)
+    assert 0 < got.sum() < got.size
+    # coordinates moved exactly where accepted
+    Xn = X1.cpu().numpy()
+    cn = cand.cpu().numpy()
+    for s in range(S):
+        for f, p in enumerate(cls[0]):
+            want = cn[s, f] if got[s, f] else X[s, :, p]
+            assert np.array_equal(Xn[s, :, p], want)
+    # objectives and cache agree with a fresh full evaluation of the new solutions
+    cache2 = torch.empty_like(cache)
+    obj2, fl2 = gp.eval_full(X1, tet_terms=cache2)
+    assert int((fl2 != 0).sum()) == 0
+    np.testing.assert_allclose(obj.cpu().numpy(), obj2.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(cache.cpu().numpy(), cache2.cpu().numpy(), rtol=1e-4, atol=1e-7)
+
+
+def test_short_runs_plain_and_screened():
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w)
+    _say("plain run")
+    log, opt, _ = O.run(gp, _t(X), generations=6, sigma=1.0, seed=5)
+    hv = np.array(log.hypervolume)
+    assert np.all(np.diff(hv) >= -1e-12 * hv[0]) and hv[-1] > hv[0]
+    assert all(e == X.shape[0] * w.P for e in log.exact_evals)
+    _say("screened run")
+    log2, opt2, sur = O.run(gp, _t(X), generations=6, sigma=1.0, seed=5, train_generations=3, train_steps=300)
+    assert sur is not None
+    assert log2.hypervolume[-1] > log2.hypervolume[0]
+    assert all(e <= X.shape[0] * w.P for e in log2.exact_evals[3:])
+    # screened generations evaluate at most the picks flagged by the surrogate
+    obj2, fl2 = gp.eval_full(opt2.X)
+    assert int((fl2 != 0).sum()) == 0
+    np.testing.assert_allclose(opt2.obj.cpu().numpy(), obj2.cpu().numpy(), rtol=1e-5, atol=1e-9)
