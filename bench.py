@@ -95,6 +95,75 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n, "launches": 3}))
 
 
+def screened_step(gp, Xd, offd, ptsd, candd, cache, out, w, S, F, K=4, train_steps=500):
+    """Times one surrogate-screened pass over all (solution, element) pairs: K
+    candidates each, features + MLP forward + selection, then exact partial
+    evaluation of the picks flagged for it.  The surrogate is first trained on
+    the exact deltas of the plain step's candidates."""
+    import torch
+    from paper_2202_11001_amd import dsm
+    old, new, flags, _ = out
+    feats = dsm.Surrogate.features(gp, Xd, ptsd, candd.reshape(S, F, 1, 2, 3))
+    ok = (flags == 0).reshape(-1)
+    f_ok, o_ok, n_ok = feats[ok], old.reshape(-1, 3)[ok].contiguous(), new.reshape(-1, 3)[ok].contiguous()
+    sur = dsm.Surrogate(seed=11, max_rows=S * F * K, max_batch=4096)
+    sur.fit_scaling(f_ok, (n_ok - o_ok).to(torch.float32).contiguous())
+    fb, tg, _ = sur.pack(f_ok, o_ok, n_ok)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = sur.train(fb, tg, steps=train_steps, batch=4096)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del feats, f_ok, fb, tg
+    candK = gp.sample_candidates(Xd, ptsd, K, w.sigma_cand, 77, 1)
+    gp.eval_full(Xd, tet_terms=cache)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    for rep in range(2):  # the second repetition is timed
+        ev[0].record(stream)
+        pick, run, pred, cpick = sur.screen(gp, Xd, ptsd, candK)
+        ev[1].record(stream)
+        gp.eval_partial(Xd, offd, ptsd, cpick, tet_terms_in=cache, out=out, mask=run)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+    t_screen = ev[0].elapsed_time(ev[1])
+    t_exact = ev[1].elapsed_time(ev[2])
+    n_exact = int(run.sum().item())
+    lo = losses.cpu().numpy()
+    log(f"screened step: screen {t_screen:.2f} ms (K={K}), exact {t_exact:.2f} ms for {n_exact}/{S * F} picks; "
+        f"training {train_steps} steps {t_train:.2f} s, loss {lo[:5].mean():.3f} -> {lo[-20:].mean():.3f}")
+    return {"K": K, "ms_per_step": t_screen + t_exact, "screen_ms": t_screen, "exact_ms": t_exact,
+            "exact_evals": n_exact, "pairs": S * F, "candidates_screened_per_s": S * F * K / ((t_screen + t_exact) / 1e3),
+            "train_steps": train_steps, "train_s": t_train, "train_loss_first": float(lo[:5].mean()),
+            "train_loss_last": float(lo[-20:].mean())}
+
+
+def surrogate_run(gp, X, G, train_generations, name):
+    """Plain run of G generations vs a run whose first train_generations
+    generations are plain (collecting exact deltas), followed by surrogate
+    training and screened generations; hypervolume of the elitist archive
+    against a reference point fixed by the initial population."""
+    import torch
+    from paper_2202_11001_amd import optimizer as O
+    Xd = torch.from_numpy(X).to("cuda:0")
+    log(f"plain run: {G} generations")
+    lp, op, _ = O.run(gp, Xd, G, sigma=1.0, seed=5, log_every=10)
+    target = 0.99 * lp.hypervolume[-1]
+    log(f"screened run: {train_generations} plain generations, then screened, until hv >= {target:.6g} or {G}")
+    ls, os_, sur = O.run(gp, Xd, G, sigma=1.0, seed=5, train_generations=train_generations, target_hv=target,
+                         log_every=10)
+    reach = next((i for i, h in enumerate(ls.hypervolume) if h >= target), None)
+    res = {"workload": name, "generations": G, "train_generations": train_generations,
+           "plain": {"final_hv": lp.hypervolume[-1], "seconds": lp.seconds[-1],
+                     "hv": lp.hypervolume, "t": lp.seconds, "exact": lp.exact_evals, "accepted": lp.accepted},
+           "screened": {"final_hv": ls.hypervolume[-1], "seconds": ls.seconds[-1],
+                        "reached_generation": None if reach is None else reach + 1,
+                        "seconds_to_target": None if reach is None else ls.seconds[reach],
+                        "hv": ls.hypervolume, "t": ls.seconds, "exact": ls.exact_evals, "accepted": ls.accepted},
+           "target_hv": target}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,12 +173,16 @@ def main():
     ap.add_argument("--small", action="store_true", help="64^3 workload (quick check)")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: 2 steps, no warmup, no CPU leg")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
+    ap.add_argument("--no-screen", action="store_true", help="skip the surrogate-screened step")
+    ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
+                    help="plain vs surrogate-screened optimiser runs of G generations (hypervolume protocol)")
+    ap.add_argument("--train-generations", type=int, default=30)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
     if args.profile:
-        args.steps, args.warmup, args.no_cpu = 2, 0, True
+        args.steps, args.warmup, args.no_cpu, args.no_screen = 2, 0, True, True
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} not supported: this evaluator runs on one GPU "
               f"(solutions shard across GPUs without exchange, see the design notes)", file=sys.stderr)
@@ -130,6 +203,9 @@ def main():
         return gp.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0
 
     X = w.population(reject=reject)
+    if args.surrogate_run:
+        surrogate_run(gp, X, args.surrogate_run, args.train_generations, w.name)
+        return
     off, pts = w.fos()
     F = len(off) - 1
     cand = w.candidates(X, off, pts)
@@ -166,6 +242,8 @@ def main():
     log(f"step ms: {['%.2f' % x for x in step_ms]}; sweep kernel ms: {['%.2f' % x for x in sweep_ms]}; "
         f"wall {wall:.3f} s")
 
+    screened = None if args.no_screen else screened_step(gp, Xd, offd, ptsd, candd, cache, out, w, S, F)
+
     evals_per_s = S * F / (ms / 1e3)
     samples_per_s = samples / (ms / 1e3)
     achieved = samples * BYTES_PER_SAMPLE / (kms / 1e3) / 1e9
@@ -192,6 +270,8 @@ def main():
                      "algorithmic_bytes_per_launch": samples * BYTES_PER_SAMPLE,
                      "kernel_source_sha256_16": kernel_source_hash()},
     }
+    if screened is not None:
+        res["screened"] = screened
     if not args.no_cpu:
         log("cpu baseline (oracle)...")
         res["cpu_baseline"] = cpu_baseline(w, X, off, pts, cand)

@@ -171,6 +171,35 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
                                    const double* tet_terms_in, double* part_old, double* part_new, uint32_t* flags,
                                    double* tet_terms_new, uint32_t* voxel_count, void* stream);
 
+/* Several registration problems in one fused launch (one workgroup list over
+ * every job's (solution, element) pairs).  A batch object owns the device job
+ * table (max_jobs entries) and a pinned staging copy; it is created once. */
+typedef struct dsm_batch dsm_batch;
+typedef struct {
+  dsm_problem* problem;         /* distinct problems within one call (they own the workspaces) */
+  int32_t S;
+  const float* X;               /* as dsm_eval_partial_masked, per job */
+  int32_t F;
+  const int32_t* fos_off;
+  const int32_t* fos_pts;
+  const float* cand;
+  const uint8_t* mask;          /* may be NULL */
+  const double* tet_terms_in;   /* may be NULL (current terms recomputed) */
+  double* part_old;
+  double* part_new;
+  uint32_t* flags;
+  double* tet_terms_new;        /* may be NULL */
+  uint32_t* voxel_count;        /* may be NULL */
+} dsm_partial_job;
+
+dsm_status dsm_batch_create(int32_t max_jobs, dsm_batch** out);
+dsm_status dsm_batch_destroy(dsm_batch* b);
+/* Enqueues the partial evaluation of every job (results identical to one
+ * dsm_eval_partial_masked call per job).  Errors: DSM_ERR_ARG (null, repeated
+ * problem), DSM_ERR_CAPACITY (n_jobs > max_jobs or a job above its problem's
+ * capacities).  Waits on the host only for the previous call's job-table copy. */
+dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs, void* stream);
+
 /* Test hook for Sec. 2.3.1 rasterisation: owner dev [Dz][Dy][Dx] int32 receives
  * the id of the tetrahedron of grid coordinates Xgrid dev [P][3] whose exact
  * voxel set contains each voxel (-1 if none); overlap dev [1] int32 counts

@@ -342,9 +342,10 @@ dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj,
   a.maxA = kFullChunk;
   a.nver = 1;
   a.terms_out = tet_terms ? tet_terms : p->d_terms;
+  a.simws = p->d_simws;
   hipEvent_t eb, ee;
   timing_pair(p, eb, ee);
-  if ((e = launch_eval(a, p->d_simws, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  if ((e = launch_eval(a, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
   if ((e = launch_full_reduce(p->dev, S, a.terms_out, obj, st)) != hipSuccess) return hip_fail(e, "reduce launch");
   return DSM_OK;
 }
@@ -384,9 +385,10 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
   a.terms_out = tet_terms_new;
   a.vcount = voxel_count;
   a.mask = mask;
+  a.simws = p->d_simws;
   hipEvent_t eb, ee;
   timing_pair(p, eb, ee);
-  if ((e = launch_eval(a, p->d_simws, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
+  if ((e = launch_eval(a, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
   return DSM_OK;
 }
 
@@ -396,6 +398,114 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
                             void* stream) {
   return dsm_eval_partial_masked(p, S, X, F, fos_off, fos_pts, cand, nullptr, tet_terms_in, part_old, part_new, flags,
                                  tet_terms_new, voxel_count, stream);
+}
+
+}  // extern "C"
+
+struct dsm_batch {
+  int max_jobs = 0;
+  EvalArgs* d_jobs = nullptr;
+  int* d_off = nullptr;
+  EvalArgs* h_jobs = nullptr;  // pinned staging
+  int* h_off = nullptr;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+};
+
+extern "C" {
+
+dsm_status dsm_batch_create(int32_t max_jobs, dsm_batch** out) {
+  g_err.clear();
+  if (!out || max_jobs < 1) return fail(DSM_ERR_ARG, "null out or max_jobs < 1");
+  *out = nullptr;
+  auto* b = new dsm_batch();
+  b->max_jobs = max_jobs;
+  hipError_t e = hipMalloc((void**)&b->d_jobs, sizeof(EvalArgs) * max_jobs);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_off, sizeof(int) * (max_jobs + 1));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_jobs, sizeof(EvalArgs) * max_jobs, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_off, sizeof(int) * (max_jobs + 1), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    dsm_batch_destroy(b);
+    return hip_fail(e, "batch allocation");
+  }
+  *out = b;
+  return DSM_OK;
+}
+
+dsm_status dsm_batch_destroy(dsm_batch* b) {
+  g_err.clear();
+  if (!b) return fail(DSM_ERR_ARG, "null batch");
+  if (b->pending && b->copied) (void)hipEventSynchronize(b->copied);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_off) (void)hipFree(b->d_off);
+  if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+  if (b->h_off) (void)hipHostFree(b->h_off);
+  if (b->copied) (void)hipEventDestroy(b->copied);
+  delete b;
+  return DSM_OK;
+}
+
+dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs, void* stream) {
+  g_err.clear();
+  if (!b || (n_jobs > 0 && !jobs) || n_jobs < 0) return fail(DSM_ERR_ARG, "null argument");
+  if (n_jobs > b->max_jobs) return fail(DSM_ERR_CAPACITY, "n_jobs = %d exceeds max_jobs = %d", n_jobs, b->max_jobs);
+  std::vector<EvalArgs> args(n_jobs);
+  std::vector<int> off(n_jobs + 1, 0);
+  size_t lds = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const dsm_partial_job& q = jobs[j];
+    dsm_problem* p = q.problem;
+    if (!p || !q.X || !q.fos_off || !q.fos_pts || !q.cand || !q.part_old || !q.part_new || !q.flags)
+      return fail(DSM_ERR_ARG, "job %d: null argument", j);
+    for (int k = 0; k < j; ++k)
+      if (jobs[k].problem == p) return fail(DSM_ERR_ARG, "job %d repeats the problem of job %d", j, k);
+    if (q.S < 0 || q.F < 0) return fail(DSM_ERR_ARG, "job %d: negative S or F", j);
+    if (q.S > p->max_S || q.F > p->max_F) return fail(DSM_ERR_CAPACITY, "job %d: S or F above the problem's capacity", j);
+    EvalArgs& a = args[j];
+    a = EvalArgs{};
+    a.pr = p->dev;
+    a.S = q.S;
+    a.G = q.F;
+    a.partial = 1;
+    a.X = q.X;
+    a.fos_off = q.fos_off;
+    a.fos_pts = q.fos_pts;
+    a.cand = q.cand;
+    a.aff = p->d_aff;
+    a.aff_cnt = p->d_aff_cnt;
+    a.maxA = p->maxA;
+    a.nver = q.tet_terms_in ? 1 : 2;
+    a.terms_in = q.tet_terms_in;
+    a.part_old = q.part_old;
+    a.part_new = q.part_new;
+    a.flags = q.flags;
+    a.terms_out = q.tet_terms_new;
+    a.vcount = q.voxel_count;
+    a.mask = q.mask;
+    a.simws = p->d_simws;
+    off[j + 1] = off[j] + q.S * q.F;
+    lds = std::max(lds, eval_lds_bytes(a.maxA, a.nver));
+  }
+  if (n_jobs == 0 || off[n_jobs] == 0) return DSM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < n_jobs && e == hipSuccess; ++j)
+    if (jobs[j].S > 0 && jobs[j].F > 0)
+      e = launch_affected(args[j].pr, jobs[j].F, jobs[j].fos_off, jobs[j].fos_pts, jobs[j].problem->max_pts,
+                          args[j].maxA, args[j].aff ? jobs[j].problem->d_aff : nullptr, jobs[j].problem->d_aff_cnt, st);
+  if (e != hipSuccess) return hip_fail(e, "affected-set launch");
+  if (b->pending && (e = hipEventSynchronize(b->copied)) != hipSuccess) return hip_fail(e, "job table wait");
+  memcpy(b->h_jobs, args.data(), sizeof(EvalArgs) * n_jobs);
+  memcpy(b->h_off, off.data(), sizeof(int) * (n_jobs + 1));
+  e = hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(EvalArgs) * n_jobs, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_off, b->h_off, sizeof(int) * (n_jobs + 1), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(b->copied, st);
+  if (e != hipSuccess) return hip_fail(e, "job table copy");
+  b->pending = true;
+  if ((e = launch_eval_batch(b->d_jobs, b->d_off, n_jobs, off[n_jobs], lds, st)) != hipSuccess)
+    return hip_fail(e, "batched evaluation launch");
+  return DSM_OK;
 }
 
 dsm_status dsm_problem_timing(dsm_problem* p, int32_t capacity) {

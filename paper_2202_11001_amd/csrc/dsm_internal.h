@@ -60,6 +60,7 @@ struct EvalArgs {
   double* terms_out;     // [S][T][3] or null
   uint32_t* vcount;      // [S][G] or null
   const uint8_t* mask;   // [S][G] or null: evaluate only where non-zero (partial)
+  double* simws;         // swept dissimilarity workspace of the problem
 };
 
 // Host-side topology (topology.cpp).
@@ -80,8 +81,9 @@ hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* fl
                        hipStream_t stream);
 hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
                            int maxA, int* aff, int* aff_cnt, hipStream_t stream);
-hipError_t launch_eval(const EvalArgs& a, double* simws, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       hipStream_t stream);
+hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end, hipStream_t stream);
+hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, size_t lds,
+                             hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
 size_t eval_lds_bytes(int maxA, int nver);

@@ -588,12 +588,10 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 // writes simws[((s*G + g)*nver + v)*maxA + i]; partial mode also writes the
 // constraint flags and the voxel count of the candidate.
 template <int PARTIAL>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep(EvalArgs a, double* __restrict__ simws) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsigned char* smem) {
+  double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
-  const int nwg = a.S * a.G;
-  const int logical = xcd_logical(blockIdx.x, nwg);
   const int g = logical / a.S, s = logical - g * a.S;
   const int nver = a.nver;
   const EvalLayout Lay = eval_layout(a.maxA, nver);
@@ -778,16 +776,34 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
   }
 }
 
+template <int PARTIAL>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep(EvalArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G), smem);
+}
+
+// Several problems in one launch: workgroup -> job by the job table's
+// workgroup offsets (the XCD mapping is applied to the concatenated list).
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_batch(
+    const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off, int n_jobs, int total) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lg = xcd_logical(blockIdx.x, total);
+  int j = 0;
+  while (j + 1 < n_jobs && wg_off[j + 1] <= lg) ++j;
+  j = uniform(j);
+  sweep_body<1>(jobs[j], lg - wg_off[j], smem);
+}
+
 // ------------------------------------------------------------ finishing kernel
 
 // Adds the deformation and guidance terms (FP64, per tetrahedron) to the swept
 // dissimilarity, writes per-tetrahedron terms, and in partial mode the
 // normalised sums over each group in ascending tetrahedron order.
-__global__ __launch_bounds__(64) void k_finish(EvalArgs a, const double* __restrict__ simws) {
+__device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
   __shared__ double s_terms[2][3][64];
+  const double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
   const int lane = threadIdx.x;
-  const int logical = blockIdx.x;
   const int g = logical / a.S, s = logical - g * a.S;
   const int na = group_size(a, g);
   const size_t oi = (size_t)s * a.G + g;
@@ -858,6 +874,15 @@ __global__ __launch_bounds__(64) void k_finish(EvalArgs a, const double* __restr
     else
       a.part_old[oi * 3 + c] = acco[c] * pr.norm[c];
   }
+}
+
+__global__ __launch_bounds__(64) void k_finish(EvalArgs a) { finish_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(64) void k_finish_batch(const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off,
+                                                     int n_jobs) {
+  int j = 0;
+  while (j + 1 < n_jobs && wg_off[j + 1] <= (int)blockIdx.x) ++j;
+  finish_body(jobs[j], (int)blockIdx.x - wg_off[j]);
 }
 
 // ------------------------------------------------------------ small kernels
@@ -1051,20 +1076,29 @@ hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, cons
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const EvalArgs& a, double* simws, hipEvent_t ev_begin, hipEvent_t ev_end,
-                       hipStream_t stream) {
+hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end, hipStream_t stream) {
   const int64_t nwg = (int64_t)a.S * a.G;
   if (nwg <= 0) return hipSuccess;
   const size_t lds = eval_lds_bytes(a.maxA, a.nver);
   if (ev_begin) (void)hipEventRecord(ev_begin, stream);
   if (a.partial)
-    k_sweep<1><<<(unsigned)nwg, kWG, lds, stream>>>(a, simws);
+    k_sweep<1><<<(unsigned)nwg, kWG, lds, stream>>>(a);
   else
-    k_sweep<0><<<(unsigned)nwg, kWG, lds, stream>>>(a, simws);
+    k_sweep<0><<<(unsigned)nwg, kWG, lds, stream>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end) (void)hipEventRecord(ev_end, stream);
-  k_finish<<<(unsigned)nwg, 64, 0, stream>>>(a, simws);
+  k_finish<<<(unsigned)nwg, 64, 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, size_t lds,
+                             hipStream_t stream) {
+  if (total <= 0) return hipSuccess;
+  k_sweep_batch<<<(unsigned)total, kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_finish_batch<<<(unsigned)total, 64, 0, stream>>>(jobs_dev, wg_off_dev, n_jobs);
   return hipGetLastError();
 }
 

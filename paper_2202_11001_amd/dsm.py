@@ -42,6 +42,13 @@ class SurrogateDesc(C.Structure):
                 ("eps", C.c_float), ("max_rows", C.c_int32), ("max_batch", C.c_int32)]
 
 
+class PartialJob(C.Structure):
+    _fields_ = [("problem", C.c_void_p), ("S", C.c_int32), ("X", C.c_void_p), ("F", C.c_int32),
+                ("fos_off", C.c_void_p), ("fos_pts", C.c_void_p), ("cand", C.c_void_p), ("mask", C.c_void_p),
+                ("tet_terms_in", C.c_void_p), ("part_old", C.c_void_p), ("part_new", C.c_void_p),
+                ("flags", C.c_void_p), ("tet_terms_new", C.c_void_p), ("voxel_count", C.c_void_p)]
+
+
 class ProblemInfo(C.Structure):
     _fields_ = [("P", C.c_int32), ("T", C.c_int32), ("E", C.c_int32), ("max_star", C.c_int32),
                 ("V", C.c_int64), ("max_affected", C.c_int32), ("norm", C.c_double * 3)]
@@ -75,6 +82,9 @@ def lib():
             "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
+            "dsm_batch_create": ([I, V], I),
+            "dsm_batch_destroy": ([V], I),
+            "dsm_eval_partial_batch": ([V, I, V, V], I),
             "dsm_surrogate_create": ([V, V], I),
             "dsm_surrogate_destroy": ([V], I),
             "dsm_surrogate_last_error": ([], C.c_char_p),
@@ -389,3 +399,47 @@ class Surrogate:
                                            na, _dptr(archive), _dptr(pred), _dptr(pick), _dptr(run), _dptr(cp),
                                            _stream(stream)))
         return pick, run, pred, cp
+
+
+class Batch:
+    """Partial evaluation of several problems in one fused launch (``dsm_batch``)."""
+
+    def __init__(self, max_jobs=16):
+        h = C.c_void_p()
+        _check(lib().dsm_batch_create(int(max_jobs), C.byref(h)))
+        self._h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dsm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval_partial(self, jobs, stream=None):
+        """jobs: list of dicts (problem, X, fos_off, fos_pts, cand, [tet_terms_in, mask]); returns a list of
+        (part_old, part_new, flags, voxel_count) per job."""
+        torch = _torch()
+        arr = (PartialJob * len(jobs))()
+        outs = []
+        for j, d in enumerate(jobs):
+            X = d["X"]
+            S, F = X.shape[0], d["fos_off"].shape[0] - 1
+            o = (torch.empty((S, F, 3), dtype=torch.float64, device=X.device),
+                 torch.empty((S, F, 3), dtype=torch.float64, device=X.device),
+                 torch.empty((S, F), dtype=torch.int32, device=X.device),
+                 torch.empty((S, F), dtype=torch.int32, device=X.device))
+            outs.append(o)
+            arr[j] = PartialJob(d["problem"]._h.value, S, X.data_ptr(), F, d["fos_off"].data_ptr(),
+                                d["fos_pts"].data_ptr(), d["cand"].data_ptr(),
+                                d["mask"].data_ptr() if d.get("mask") is not None else None,
+                                d["tet_terms_in"].data_ptr() if d.get("tet_terms_in") is not None else None,
+                                o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), None, o[3].data_ptr())
+        self._keep = (arr, jobs, outs)
+        _check(lib().dsm_eval_partial_batch(self._h, len(jobs), arr, _stream(stream)))
+        return outs

@@ -325,3 +325,44 @@ def ramp(shape, coef=(0.01, 0.02, 0.03), offset=0.1):
     """Linear ramp image I(x, y, z) = offset + coef . (x, y, z) (float32)."""
     x, y, z = _grid(shape)
     return (offset + coef[0] * x + coef[1] * y + coef[2] * z).astype(np.float32)
+
+
+UNEVEN_PROBLEMS = [  # (shape (Dz, Dy, Dx), mesh (nx, ny, nz), population)
+    ((96, 96, 96), (4, 4, 4), 64), ((128, 128, 128), (5, 5, 5), 96), ((80, 192, 192), (6, 6, 4), 128),
+    ((64, 256, 256), (8, 8, 6), 256), ((96, 96, 96), (5, 5, 5), 128), ((128, 128, 128), (6, 6, 6), 64),
+    ((80, 192, 192), (8, 8, 6), 192), ((64, 256, 256), (7, 7, 5), 160), ((96, 96, 96), (8, 8, 6), 96),
+    ((128, 128, 128), (4, 4, 4), 256), ((80, 192, 192), (5, 5, 4), 64), ((64, 256, 256), (6, 6, 5), 192),
+]
+
+
+def downsample2(img):
+    """2x2x2 box average (all dims even)."""
+    Dz, Dy, Dx = img.shape
+    return img.reshape(Dz // 2, 2, Dy // 2, 2, Dx // 2, 2).mean(axis=(1, 3, 5)).astype(np.float32)
+
+
+def uneven(indices=None, level=1):
+    """Several registration problems of uneven volume and mesh size: the
+    two-ellipsoid pair scaled to each shape (seed 100 + i); level 0 is the
+    2x2x2 box-averaged pyramid level (populations drawn there, sigma halved),
+    level 1 the full resolution."""
+    out = []
+    for i in (indices if indices is not None else range(len(UNEVEN_PROBLEMS))):
+        shape, mesh, S = UNEVEN_PROBLEMS[i]
+        w = batched(shape=shape, mesh=mesh, S=S, seed=100 + 4 * i)
+        w.name = f"uneven-{i}-{shape[2]}x{shape[1]}x{shape[0]}"
+        if level == 0:
+            w.moving, w.fixed = downsample2(w.moving), downsample2(w.fixed)
+            hi = np.array([shape[2] // 2 - 1, shape[1] // 2 - 1, shape[0] // 2 - 1], dtype=np.float64)
+            w.guid_moving = snap(np.clip((w.guid_moving.astype(np.float64) - 0.5) / 2, 0, hi))
+            w.guid_fixed = snap(np.clip((w.guid_fixed.astype(np.float64) - 0.5) / 2, 0, hi))
+            w.sigma_pop, w.sigma_cand = w.sigma_pop / 2, w.sigma_cand / 2
+            w.name += "-half"
+        out.append(w)
+    return out
+
+
+def upsample_population(X_half):
+    """Hand-off from the half-resolution level: voxel coordinate x at half
+    resolution is 2 x + 0.5 at full resolution (lattice u -> 2 u, exact)."""
+    return (2.0 * np.asarray(X_half, dtype=np.float64) + 0.5).astype(np.float32)

@@ -284,3 +284,87 @@ def test_batched_sampled():
     vcs = vc.cpu().numpy().astype(np.int64)
     allok = (fl.cpu().numpy() == 0).all(axis=1)
     assert np.all(vcs[allok].sum(axis=1) == 8 * gp.V)
+
+
+def test_clinical_full_size_sampled():
+    """512x512x100 clinical-shaped workload in the benchmark's launch
+    configuration (512 solutions x 600 single-point elements in one launch,
+    cached old terms); the oracle recomputes a sample of (solution, element)
+    pairs and two full evaluations."""
+    w = W.clinical()
+    _say(f"clinical full size {w.name}")
+    gp = _gpu_problem(w, w.S)
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    Xd = _t(X)
+    cache = torch.empty((w.S, gp.T, 3), dtype=torch.float64, device=DEV)
+    obj, flags = gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    assert int((flags != 0).sum()) == 0
+    vcs = vc.cpu().numpy().astype(np.int64)
+    fln = fl.cpu().numpy()
+    allok = (fln == 0).all(axis=1)
+    assert np.all(vcs[allok].sum(axis=1) == 8 * gp.V)  # exactly-once coverage, both grids, every star
+    rng = np.random.default_rng(0)
+    sols = rng.choice(w.S, 4, replace=False)
+    elems = np.sort(rng.choice(w.P, 6, replace=False)).astype(np.int32)
+    off_s = np.arange(len(elems) + 1, dtype=np.int32)
+    for s in sols:
+        c_s = cand[s:s + 1, elems]
+        rold, rnew, rfl, rnv = rp.eval_partial(X[s:s + 1], off_s, elems, c_s)
+        g_fl = fln[s, elems][None].astype(np.uint32)
+        np.testing.assert_array_equal(g_fl, rfl)
+        np.testing.assert_array_equal(vcs[s, elems][None][g_fl == 0], rnv[g_fl == 0])
+        assert_objectives_close(new.cpu().numpy()[s, elems][None], rnew, flags=g_fl, what="part_new")
+        assert_objectives_close(old.cpu().numpy()[s, elems][None], rold, what="part_old")
+        assert_delta_close(old.cpu().numpy()[s, elems][None], new.cpu().numpy()[s, elems][None], rold, rnew, g_fl)
+    robj, rflags = rp.eval_full(X[sols[:2]])
+    assert_objectives_close(obj.cpu().numpy()[sols[:2]], robj, what="full objectives")
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_uneven_batch_one_launch(level):
+    """Problems of uneven volume and mesh size evaluated in one fused launch:
+    results identical to one launch per problem; a sample checked against the
+    oracle.  Level 0 is the 2x box-averaged pyramid level; level 1 starts from
+    its population handed off to full resolution."""
+    idx = [0, 3, 6, 9] if level == 1 else [0, 3, 6, 9, 10]
+    ws = W.uneven(idx, level=level)
+    jobs, single, probs = [], [], []
+    batch = dsm.Batch(max_jobs=len(ws))
+    for i, w in zip(idx, ws):
+        rp = oracle_problem(w)
+        if level == 0:
+            X = feasible_population(w, rp)
+        else:
+            # hand-off: a feasible half-resolution population mapped to full resolution stays feasible
+            wh = W.uneven([i], level=0)[0]
+            X = W.upsample_population(feasible_population(wh, oracle_problem(wh)))
+            assert np.all(rp.fold_check(X)[0] == 0)
+        off, pts = w.fos()
+        cand = w.candidates(X, off, pts)
+        gp = _gpu_problem(w, len(X))
+        probs.append((w, rp, X, off, pts, cand, gp))
+        Xd = _t(X)
+        cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+        gp.eval_full(Xd, tet_terms=cache)
+        jobs.append(dict(problem=gp, X=Xd, fos_off=_t(off), fos_pts=_t(pts), cand=_t(cand), tet_terms_in=cache))
+        single.append(gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True))
+    _say(f"uneven batch level {level}: {[w.name for w in ws]}")
+    outs = batch.eval_partial(jobs)
+    torch.cuda.synchronize()
+    for o, sgl in zip(outs, single):
+        for a, b in zip(o, sgl):
+            np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    rng = np.random.default_rng(level)
+    for (w, rp, X, off, pts, cand, gp), o in zip(probs, outs):
+        s = int(rng.integers(len(X)))
+        elems = np.sort(rng.choice(w.P, 5, replace=False)).astype(np.int32)
+        rold, rnew, rfl, rnv = rp.eval_partial(X[s:s + 1], np.arange(6, dtype=np.int32), elems, cand[s:s + 1, elems])
+        g_fl = o[2].cpu().numpy()[s, elems][None].astype(np.uint32)
+        np.testing.assert_array_equal(g_fl, rfl)
+        assert_objectives_close(o[1].cpu().numpy()[s, elems][None], rnew, flags=g_fl, what=f"{w.name} part_new")
+        assert_objectives_close(o[0].cpu().numpy()[s, elems][None], rold, what=f"{w.name} part_old")
