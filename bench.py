@@ -174,6 +174,7 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: 2 steps, no warmup, no CPU leg")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
     ap.add_argument("--no-screen", action="store_true", help="skip the surrogate-screened step")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch")
     ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
                     help="plain vs surrogate-screened optimiser runs of G generations (hypervolume protocol)")
     ap.add_argument("--train-generations", type=int, default=30)
@@ -213,6 +214,9 @@ def main():
     offd, ptsd, candd = (torch.from_numpy(a).to(dev) for a in (off, pts, cand))
     cache = torch.empty((S, gp.T, 3), dtype=torch.float64, device=dev)
     obj, flags = gp.eval_full(Xd, tet_terms=cache)
+    if not args.no_autotune and not args.profile:
+        best, table = gp.autotune_pitch(Xd, offd, ptsd, candd, tet_terms_in=cache)
+        log(f"image row pitch autotune (ms per step): {table} -> {best}")
     out = (torch.empty((S, F, 3), dtype=torch.float64, device=dev), torch.empty((S, F, 3), dtype=torch.float64, device=dev),
            torch.empty((S, F), dtype=torch.int32, device=dev), torch.empty((S, F), dtype=torch.int32, device=dev))
     gp.eval_partial(Xd, offd, ptsd, candd, tet_terms_in=cache, out=out)

@@ -96,6 +96,7 @@ typedef struct {
   int64_t V;            /* voxels per image */
   int32_t max_affected; /* capacity of one FOS element's affected set */
   double norm[3];       /* normalisers: 1/(V_fixed+V_moving), 1/(E+4T), 1/(n_guid_moving+n_guid_fixed) or 0 */
+  int32_t pitch;        /* row pitch (elements) of the device image layout; see dsm_problem_set_pitch */
 } dsm_problem_info;
 
 /* Copies the images and guidance to the current device, builds the topology
@@ -199,6 +200,29 @@ dsm_status dsm_batch_destroy(dsm_batch* b);
  * problem), DSM_ERR_CAPACITY (n_jobs > max_jobs or a job above its problem's
  * capacities).  Waits on the host only for the previous call's job-table copy. */
 dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs, void* stream);
+
+/* Device image layout.  The sampled images are stored on the device with a
+ * replicated one-voxel border, z-pairs interleaved, in rows of `pitch`
+ * elements (pitch >= Dx + 2).  The pitch changes no result, only speed: the
+ * trilinear gathers of one wave touch several rows at once, and some row
+ * strides make them collide in the memory pipeline.  dsm_problem_set_pitch
+ * re-packs the images for `pitch` (0 = the built-in default); it allocates and
+ * synchronises the device, so call it at setup, not during capture.  Errors:
+ * DSM_ERR_ARG for a pitch below Dx + 2, above 4 (Dx + 2) + 64, or an image
+ * above 2 GiB. */
+dsm_status dsm_problem_set_pitch(dsm_problem* p, int32_t pitch);
+
+/* Autotuning of the layout for one partial-evaluation workload (the same
+ * arguments as dsm_eval_partial, dev pointers): for each of the n_pitch host
+ * candidates `pitches` (n_pitch 0: a built-in list around the default),
+ * re-packs the images, runs the partial evaluation twice on the null stream and
+ * records the second run's time in ms_out host [n_pitch] (or [6] for the
+ * built-in list; may be NULL); the fastest pitch is kept and returned in
+ * *best (may be NULL).  Setup-time call: allocates temporary outputs and
+ * synchronises. */
+dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                              const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_pitch,
+                              const int32_t* pitches, float* ms_out, int32_t* best);
 
 /* Test hook for Sec. 2.3.1 rasterisation: owner dev [Dz][Dy][Dx] int32 receives
  * the id of the tetrahedron of grid coordinates Xgrid dev [P][3] whose exact

@@ -43,11 +43,39 @@ hipError_t dev_alloc(T** p, size_t count) {
 void release(dsm_problem* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-  void* bufs[] = {p->d_img, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
+  void* bufs[] = {p->d_img, p->d_raw, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
                   p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws, p->d_ident};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
+}
+
+// (Re)builds the bordered images for row pitch `pitch` (0 = default) and
+// points the kernels' problem description at them.  Synchronous.
+hipError_t repack(dsm_problem* p, int pitch) {
+  const BorderedLayout bl = bordered_layout(p->dims[0], p->dims[1], p->dims[2], pitch);
+  const size_t stride = 2 * (size_t)bl.elements();
+  hipError_t e = hipSuccess;
+  if (stride != p->img_stride) {
+    if (p->d_img) (void)hipFree(p->d_img);
+    p->d_img = nullptr;
+    p->img_stride = 0;
+    if ((e = dev_alloc(&p->d_img, 2 * stride)) != hipSuccess) return e;
+  }
+  p->img_stride = stride;
+  for (int g = 0; g < 2; ++g)
+    if ((e = launch_pack_bordered(p->d_raw + g * p->V, p->d_img + g * stride, p->dims[0], p->dims[1], p->dims[2], bl,
+                                  nullptr)) != hipSuccess)
+      return e;
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  p->pitch = bl.px;
+  DevProblem& dv = p->dev;
+  dv.img[0] = p->d_img;
+  dv.img[1] = p->d_img + stride;
+  dv.img_bytes = (int)(sizeof(float) * stride);
+  dv.ex = bl.px;
+  dv.exy = bl.px * bl.py;
+  return hipSuccess;
 }
 
 // next free timing pair, or nulls
@@ -167,26 +195,11 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
     release(p);              \
     return hip_fail(e, what); \
   }
-  // z-pair interleaved images: element (x,y,z) = (I[z][y][x], I[min(z+1,Dz-1)][y][x])
-  const size_t img_stride = 2 * ((size_t)p->V + image_padding(d->dims[0], d->dims[1]));
-  {
-    std::vector<float> packed(2 * img_stride, 0.0f);
-    const size_t plane = (size_t)d->dims[0] * d->dims[1];
-    const float* src[2] = {d->moving, d->fixed};
-    for (int g = 0; g < 2; ++g)
-      for (int z = 0; z < d->dims[2]; ++z) {
-        const float* a = src[g] + plane * z;
-        const float* b = src[g] + plane * (z + 1 < d->dims[2] ? z + 1 : z);
-        float* dst = packed.data() + g * img_stride + 2 * plane * z;
-        for (size_t i = 0; i < plane; ++i) {
-          dst[2 * i] = a[i];
-          dst[2 * i + 1] = b[i];
-        }
-      }
-    DSM_TRY(dev_alloc(&p->d_img, 2 * img_stride), "hipMalloc images");
-    DSM_TRY(hipMemcpy(p->d_img, packed.data(), sizeof(float) * 2 * img_stride, hipMemcpyHostToDevice), "copy images");
-  }
-  p->img_stride = img_stride;
+  // images as given, then packed on the device into the bordered z-pair layout
+  DSM_TRY(dev_alloc(&p->d_raw, 2 * (size_t)p->V), "hipMalloc images");
+  DSM_TRY(hipMemcpy(p->d_raw, d->moving, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy images");
+  DSM_TRY(hipMemcpy(p->d_raw + p->V, d->fixed, sizeof(float) * p->V, hipMemcpyHostToDevice), "copy images");
+  DSM_TRY(repack(p, 0), "pack images");
   DSM_TRY(dev_alloc(&p->d_tets, tp.tets.size()), "hipMalloc tets");
   DSM_TRY(hipMemcpy(p->d_tets, tp.tets.data(), sizeof(int) * tp.tets.size(), hipMemcpyHostToDevice), "copy tets");
   DSM_TRY(dev_alloc(&p->d_tet_w, tp.tet_w.size()), "hipMalloc weights");
@@ -217,9 +230,6 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
 #undef DSM_TRY
 
   DevProblem& dv = p->dev;
-  dv.img[0] = p->d_img;
-  dv.img[1] = p->d_img + p->img_stride;
-  dv.img_bytes = (int)(sizeof(float) * p->img_stride);
   for (int a = 0; a < 3; ++a) {
     dv.D[a] = p->dims[a];
     dv.n[a] = p->mesh[a];
@@ -271,7 +281,17 @@ dsm_status dsm_problem_query(const dsm_problem* p, dsm_problem_info* out) {
   out->V = p->V;
   out->max_affected = p->maxA;
   for (int c = 0; c < 3; ++c) out->norm[c] = p->dev.norm[c];
+  out->pitch = p->pitch;
   return DSM_OK;
+}
+
+dsm_status dsm_problem_set_pitch(dsm_problem* p, int32_t pitch) {
+  g_err.clear();
+  if (!p) return fail(DSM_ERR_ARG, "problem is null");
+  if (pitch != 0 && !pitch_ok(p->dims[0], p->dims[1], p->dims[2], pitch))
+    return fail(DSM_ERR_ARG, "pitch %d outside [Dx + 2, 4 (Dx + 2) + 64] or image above 2 GiB", pitch);
+  const hipError_t e = repack(p, pitch);
+  return e == hipSuccess ? DSM_OK : hip_fail(e, "re-pack images");
 }
 
 dsm_status dsm_problem_topology(const dsm_problem* p, int32_t* tets, int32_t* star_off, int32_t* star,
@@ -398,6 +418,64 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
                             void* stream) {
   return dsm_eval_partial_masked(p, S, X, F, fos_off, fos_pts, cand, nullptr, tet_terms_in, part_old, part_new, flags,
                                  tet_terms_new, voxel_count, stream);
+}
+
+dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                              const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_pitch,
+                              const int32_t* pitches, float* ms_out, int32_t* best) {
+  g_err.clear();
+  if (!p || !X || !fos_off || !fos_pts || !cand || n_pitch < 0 || (n_pitch > 0 && !pitches)) return fail(DSM_ERR_ARG, "null argument");
+  if (S <= 0 || F <= 0) return fail(DSM_ERR_ARG, "S and F must be positive");
+  std::vector<int> cands;
+  if (n_pitch > 0) {
+    cands.assign(pitches, pitches + n_pitch);
+  } else {  // default candidates: the default pitch and the next pitches of each class mod 16 elements
+    const int d0 = default_pitch(p->dims[0]);
+    for (int k : {0, 4, 8, 16, 24, 56}) cands.push_back(d0 + k);
+  }
+  for (int c : cands)
+    if (c != 0 && !pitch_ok(p->dims[0], p->dims[1], p->dims[2], c)) return fail(DSM_ERR_ARG, "pitch %d not accepted", c);
+  // temporary outputs (setup-time call: allocation allowed here)
+  double *old = nullptr, *nw = nullptr;
+  uint32_t* fl = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  dsm_status st = DSM_OK;
+  float best_ms = INFINITY;
+  int best_pitch = p->pitch;
+  if ((e = dev_alloc(&old, (size_t)S * F * 3)) != hipSuccess || (e = dev_alloc(&nw, (size_t)S * F * 3)) != hipSuccess ||
+      (e = dev_alloc(&fl, (size_t)S * F)) != hipSuccess || (e = hipEventCreate(&e0)) != hipSuccess ||
+      (e = hipEventCreate(&e1)) != hipSuccess) {
+    st = hip_fail(e, "autotune buffers");
+  }
+  for (size_t k = 0; st == DSM_OK && k < cands.size(); ++k) {
+    if ((e = repack(p, cands[k])) != hipSuccess) {
+      st = hip_fail(e, "re-pack images");
+      break;
+    }
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && st == DSM_OK; ++rep) {  // the first run warms caches and code
+      (void)hipEventRecord(e0, nullptr);
+      st = dsm_eval_partial(p, S, X, F, fos_off, fos_pts, cand, tet_terms_in, old, nw, fl, nullptr, nullptr, nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      if (st == DSM_OK && (e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "autotune run");
+      if (st == DSM_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (st != DSM_OK) break;
+    if (ms_out) ms_out[k] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_pitch = p->pitch;
+    }
+  }
+  if (st == DSM_OK && (e = repack(p, best_pitch)) != hipSuccess) st = hip_fail(e, "re-pack images");
+  if (st == DSM_OK && best) *best = best_pitch;
+  if (old) (void)hipFree(old);
+  if (nw) (void)hipFree(nw);
+  if (fl) (void)hipFree(fl);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
 }
 
 }  // extern "C"

@@ -15,15 +15,38 @@ constexpr int kWaves = kWG / 64;  // wave64 waves per workgroup
 constexpr double kLat = 128.0;    // lattice steps per voxel
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
 
-// Packed elements (float pairs) after each z-pair interleaved image so that
-// every tap of a position clamped to [0, D-1] (including the weight-0 taps past
-// the last voxel of a row or column) lies inside the allocation.
-inline int64_t image_padding(int Dx, int Dy) { return (int64_t)Dx + 64; }
+// Sampled images are stored z-pair interleaved with a replicated one-voxel
+// border: element (x', y', z') of the (Dx+2) x (Dy+2) x (Dz+1) element grid
+// holds (I[c(z'-1)][c(y'-1)][c(x'-1)], I[c(z')][c(y'-1)][c(x'-1)]) with c()
+// clamping each index into the image.  A position p (voxel units) is sampled
+// at p + 1: every tap of any p in [-0.5, D-0.5] then lies inside the element
+// grid, and the taps that fall outside the image repeat the border value, so
+// interpolating them gives exactly the value at the position clamped to
+// [0, D-1] without a clamp instruction.
+// The row pitch px (elements per stored row, >= Dx + 2) is a tuning
+// parameter: the gathers of one wave touch a few rows at once, and some row
+// strides make them collide in the memory pipeline.  The default is the
+// smallest pitch >= Dx + 2 that is 8 mod 16 elements (row stride 64 mod 128
+// bytes); dsm_autotune_pitch measures alternatives.
+struct BorderedLayout {
+  int px, py, pz;  // element grid dims
+  __host__ __device__ int64_t elements() const { return (int64_t)px * py * pz; }
+};
+inline int default_pitch(int Dx) { return Dx + 2 + ((8 - (Dx + 2) % 16) + 16) % 16; }
+inline BorderedLayout bordered_layout(int Dx, int Dy, int Dz, int pitch) {
+  return {pitch > 0 ? pitch : default_pitch(Dx), Dy + 2, Dz + 1};
+}
+// Largest accepted pitch: the byte offsets of one image must fit a 32-bit buffer offset.
+inline bool pitch_ok(int Dx, int Dy, int Dz, int pitch) {
+  return pitch >= Dx + 2 && pitch <= 4 * (Dx + 2) + 64 &&
+         (int64_t)pitch * (Dy + 2) * (Dz + 1) * 8 < ((int64_t)1 << 31);
+}
 
 // Everything a kernel needs to know about one problem (passed by value).
 struct DevProblem {
-  const float* img[2];   // [0] source (moving), [1] target (fixed); z-pair interleaved [Dz][Dy][Dx][2], padded
-  int img_bytes;         // bytes of one packed image including its padding (buffer range)
+  const float* img[2];   // [0] source (moving), [1] target (fixed); bordered z-pair layout (BorderedLayout)
+  int img_bytes;         // bytes of one bordered image (buffer range)
+  int ex, exy;           // element strides of y and z in the bordered layout
   int D[3];
   int DxDy;
   float tau;             // empty iff value <= tau
@@ -86,6 +109,8 @@ hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, in
                              hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
+hipError_t launch_pack_bordered(const float* raw, float* out, int Dx, int Dy, int Dz, BorderedLayout bl,
+                                hipStream_t stream);
 size_t eval_lds_bytes(int maxA, int nver);
 
 }  // namespace dsm
@@ -100,8 +125,10 @@ struct dsm_problem {
   int max_S = 0, max_F = 0, max_pts = 0, maxA = 0;
   int device = 0;
   // device buffers owned by the problem
-  float* d_img = nullptr;       // [2][Dz][Dy][Dx][2] z-pair interleaved, each image padded
-  size_t img_stride = 0;
+  float* d_img = nullptr;       // [2][Dz+1][Dy+2][pitch][2] bordered z-pair layout
+  size_t img_stride = 0;        // floats per bordered image
+  float* d_raw = nullptr;       // [2][Dz][Dy][Dx] the images as given (source, target), for re-packing
+  int pitch = 0;                // row pitch of d_img in elements
   int* d_tets = nullptr;
   double* d_tet_w = nullptr;
   int* d_star_off = nullptr;

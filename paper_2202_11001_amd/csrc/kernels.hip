@@ -330,15 +330,17 @@ __device__ __forceinline__ void row_span(const RasterTet& rt, int y, int z, int 
 struct WaveRows {
   int start[64];   // exclusive prefix of span lengths, by compacted (non-empty) row
   float4 rec[64];  // x: own-image linear index minus start (as int bits); yzw: mapped position of the span's first voxel
-  int marker[64];  // per voxel slot of the current 64-voxel chunk: 1 where a row starts
+  int marker[128];  // per voxel slot of the current 128-voxel chunk pair: 1 where a row starts
 };
 
 // Computes the spans of rows [64 b, 64 b + 64) of rt, stores the non-empty
 // ones compacted (in row order) in wr, and returns the number of voxels.  Row r
-// is y-major within a slice: y = ylo + r % ny.  *my_start receives the first
-// voxel index of this lane's row, or a large negative value if it is empty.
-__device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int DxDy,
-                                          WaveRows& wr, int* my_start) {
+// is y-major within a slice: y = ylo + r % ny.  The linear index stored for a
+// span's first voxel (x0, y, z) is base + z sz + y sy + x0, its mapped position
+// P0 + J (x0, y, z) + shift.  *my_start receives the first voxel index of this
+// lane's row, or a large negative value if it is empty.
+__device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int sy, int sz,
+                                          int base, float shift, WaveRows& wr, int* my_start) {
   const int r = b * 64 + lane;
   int len = 0, lin = 0;
   float bx = 0.f, by = 0.f, bz = 0.f;
@@ -360,11 +362,11 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
     row_span(rt, y, z, D[0], x0, x1);
     if (x1 >= x0) {
       len = x1 - x0 + 1;
-      lin = z * DxDy + y * D[0] + x0;
+      lin = base + z * sz + y * sy + x0;
       const double v[3] = {(double)x0, (double)y, (double)z};
-      bx = (float)(rt.P0[0] + rt.J[0][0] * v[0] + rt.J[0][1] * v[1] + rt.J[0][2] * v[2]);
-      by = (float)(rt.P0[1] + rt.J[1][0] * v[0] + rt.J[1][1] * v[1] + rt.J[1][2] * v[2]);
-      bz = (float)(rt.P0[2] + rt.J[2][0] * v[0] + rt.J[2][1] * v[1] + rt.J[2][2] * v[2]);
+      bx = (float)(rt.P0[0] + rt.J[0][0] * v[0] + rt.J[0][1] * v[1] + rt.J[0][2] * v[2] + shift);
+      by = (float)(rt.P0[1] + rt.J[1][0] * v[0] + rt.J[1][1] * v[1] + rt.J[1][2] * v[2] + shift);
+      bz = (float)(rt.P0[2] + rt.J[2][0] * v[0] + rt.J[2][1] * v[1] + rt.J[2][2] * v[2] + shift);
     }
   }
   const int incl = wave_incl_scan(len, lane);
@@ -395,30 +397,43 @@ __device__ __forceinline__ float load1(__amdgpu_buffer_rsrc_t r, int voff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
-// Per-wave constants of the sampled (other) image.  Images are stored
-// z-pair interleaved: element (x,y,z) holds (I[z][y][x], I[z+1][y][x]), so one
-// 16-byte load returns the taps (x, z), (x, z+1), (x+1, z), (x+1, z+1).
+// Per-wave constants of the sampled (other) image.  Images use the bordered
+// z-pair layout: element (x', y', z') holds the values at (x'-1, y'-1, z'-1)
+// and (x'-1, y'-1, z'), border-replicated, so one 16-byte load at element
+// (ix, iy, iz) returns the taps (x, z), (x, z+1), (x+1, z), (x+1, z+1) of the
+// cell of shifted position q = p + 1 with ix = floor(q_x) etc.
 struct SampleCtx {
-  __amdgpu_buffer_rsrc_t own, oth;  // image buffers (padded: every tap of a clamped position is allocated)
-  float Dxm, Dym, Dzm;              // D - 1
+  __amdgpu_buffer_rsrc_t own, oth;  // bordered image buffers
   int sx8, sxy8;                    // byte strides of y and z
   float tau;
 };
 
+// The 8 trilinear taps of the sampled image around shifted position
+// (px, py, pz) = p + 1, p in [-0.5, D-0.5] up to rounding: truncation is floor,
+// and the replicated border stands in for clamping p to [0, D-1].
+struct Taps {
+  float4v ty0, ty1;  // (x,z) (x,z+1) (x+1,z) (x+1,z+1) at y and at y+1
+  float fx, fy, fz;
+};
+
+__device__ __forceinline__ Taps load_taps(const SampleCtx& c, float px, float py, float pz) {
+  Taps t;
+  const int ix = (int)px, iy = (int)py, iz = (int)pz;
+  t.fx = __builtin_amdgcn_fractf(px);
+  t.fy = __builtin_amdgcn_fractf(py);
+  t.fz = __builtin_amdgcn_fractf(pz);
+  const int voff = (int)(__umul24((unsigned)iy, (unsigned)c.sx8) + (__umul24((unsigned)iz, (unsigned)c.sxy8) + ((unsigned)ix << 3)));
+  t.ty0 = load4(c.oth, voff, 0);
+  t.ty1 = load4(c.oth, voff, c.sx8);
+  return t;
+}
+
 // Sec. 2.3.1 contribution of a voxel pair: squared intensity difference, and
 // the maximal difference 1 where an empty voxel meets a non-empty one; the
 // empty indicator of the sampled position is interpolated like the intensity.
-// The position is clamped to [0, D-1]; at the upper bound the +1 tap has
-// weight 0 (it reads an allocated padding or neighbouring voxel).
-__device__ __forceinline__ float sample_contrib(const SampleCtx& c, float a, float px, float py, float pz) {
-  px = __builtin_amdgcn_fmed3f(px, 0.f, c.Dxm);
-  py = __builtin_amdgcn_fmed3f(py, 0.f, c.Dym);
-  pz = __builtin_amdgcn_fmed3f(pz, 0.f, c.Dzm);
-  const int ix = (int)px, iy = (int)py, iz = (int)pz;
-  const float fx = __builtin_amdgcn_fractf(px), fy = __builtin_amdgcn_fractf(py), fz = __builtin_amdgcn_fractf(pz);
-  const int voff = (ix << 3) + (int)__umul24((unsigned)iy, (unsigned)c.sx8) + (int)__umul24((unsigned)iz, (unsigned)c.sxy8);
-  const float4v ty0 = load4(c.oth, voff, 0);      // (x,z) (x,z+1) (x+1,z) (x+1,z+1) at y
-  const float4v ty1 = load4(c.oth, voff, c.sx8);  // the same at y+1
+__device__ __forceinline__ float contrib_of(const SampleCtx& c, float a, const Taps& tp) {
+  const float4v ty0 = tp.ty0, ty1 = tp.ty1;
+  const float fx = tp.fx, fy = tp.fy, fz = tp.fz;
   struct {
     float x, y;
   } t00{ty0.x, ty0.z}, t10{ty1.x, ty1.z}, t01{ty0.y, ty0.w}, t11{ty1.y, ty1.w};
@@ -679,14 +694,11 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   const int total_units = uniform(s_units[nent]);
 
   // ---- voxel sweep
-  const int DxDy = pr.DxDy;
   SampleCtx sc;
-  sc.Dxm = (float)(pr.D[0] - 1);
-  sc.Dym = (float)(pr.D[1] - 1);
-  sc.Dzm = (float)(pr.D[2] - 1);
-  sc.sx8 = 8 * pr.D[0];
-  sc.sxy8 = 8 * DxDy;
+  sc.sx8 = 8 * pr.ex;
+  sc.sxy8 = 8 * pr.exy;
   sc.tau = pr.tau;
+  const int own_base = pr.exy + pr.ex + 1;  // element of voxel (0, 0, 0)
   const __amdgpu_buffer_rsrc_t rs[2] = {image_rsrc(pr.img[0], pr.img_bytes), image_rsrc(pr.img[1], pr.img_bytes)};
   WaveRows& wr = s_rows[wave];
   RasterTet& rt = s_rt[wave];
@@ -720,33 +732,43 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     }
     const int b = u - uniform(s_units[cur]);
     int my_start;
-    const int nvox = uniform(build_rows(rt, b, lane, pr.D, DxDy, wr, &my_start));
+    const int nvox = uniform(build_rows(rt, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
     int carry = 0;  // non-empty rows that start before the current chunk
-    for (int q0 = 0; q0 < nvox; q0 += 64) {
-      // row of voxel q0 + lane: rows starting in this chunk are marked, then
-      // counted below the lane with a ballot
+    for (int q0 = 0; q0 < nvox; q0 += 128) {
+      // voxels q0 + lane and q0 + 64 + lane: rows starting in this pair of
+      // chunks are marked, then counted below each slot with a ballot
       wr.marker[lane] = 0;
+      wr.marker[64 + lane] = 0;
       wave_sync();
       const unsigned pos = (unsigned)(my_start - q0);
-      if (pos < 64u) wr.marker[pos] = 1;
+      if (pos < 128u) wr.marker[pos] = 1;
       wave_sync();
-      const int mk = wr.marker[lane];
-      const unsigned long long M = __ballot(mk != 0);
-      const int r = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M, 0u)) +
-                    mk - 1;
-      carry += __popcll(M);
-      const int q = q0 + lane;
-      if (q < nvox) {
-        const int off = q - wr.start[r];
-        const float4 rec = wr.rec[r];
-        const float fo = (float)off;
-        const float av = load1(sc.own, (__float_as_int(rec.x) + q) << 3);
-        const float c = sample_contrib(sc, av, fmaf(jx, fo, rec.y), fmaf(jy, fo, rec.z), fmaf(jz, fo, rec.w));
-        const float y = c - comp;
-        const float t = sum + y;
-        comp = (t - sum) - y;
-        sum = t;
-      }
+      const int mk0 = wr.marker[lane], mk1 = wr.marker[64 + lane];
+      const unsigned long long M0 = __ballot(mk0 != 0), M1 = __ballot(mk1 != 0);
+      const int r0 = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M0, 0u)) +
+                     mk0 - 1;
+      carry += __popcll(M0);
+      const int r1 = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M1, 0u)) +
+                     mk1 - 1;
+      carry += __popcll(M1);
+      // slots past the last voxel repeat the last voxel (same row) and are
+      // weighted 0, so both samples' loads are issued before either is used
+      const int qa = q0 + lane, qb = qa + 64;
+      const int ea = min(qa, nvox - 1), eb = min(qb, nvox - 1);
+      const int sa = wr.start[r0], sb = wr.start[r1];
+      const float4 reca = wr.rec[r0], recb = wr.rec[r1];
+      const float foa = (float)(ea - sa), fob = (float)(eb - sb);
+      const float ava = load1(sc.own, (__float_as_int(reca.x) + ea) << 3);
+      const Taps ta = load_taps(sc, fmaf(jx, foa, reca.y), fmaf(jy, foa, reca.z), fmaf(jz, foa, reca.w));
+      const float avb = load1(sc.own, (__float_as_int(recb.x) + eb) << 3);
+      const Taps tb = load_taps(sc, fmaf(jx, fob, recb.y), fmaf(jy, fob, recb.z), fmaf(jz, fob, recb.w));
+      const float ca = contrib_of(sc, ava, ta);
+      const float cb = contrib_of(sc, avb, tb);
+      const float c = (qa < nvox ? ca : 0.f) + (qb < nvox ? cb : 0.f);
+      const float y = c - comp;
+      const float t = sum + y;
+      comp = (t - sum) - y;
+      sum = t;
     }
     if (cur < 2 * na) counted += (unsigned)nvox;  // version 0 (candidate) voxels
   }
@@ -1010,7 +1032,7 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
   for (int b = wave; b < nb; b += kWaves) {
     WaveRows& wr = rows[wave];
     int my_start;
-    const int nvox = build_rows(rt, b, lane, pr.D, pr.DxDy, wr, &my_start);
+    const int nvox = build_rows(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
     int carry = 0;
     for (int q0 = 0; q0 < nvox; q0 += 64) {
       wr.marker[lane] = 0;
@@ -1030,6 +1052,26 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
         if (prev != -1) atomicAdd(overlap, 1);
       }
     }
+  }
+}
+
+// Bordered z-pair layout from an image [Dz][Dy][Dx]: element (x', y', z')
+// = (I[c(z'-1)][c(y'-1)][c(x'-1)], I[c(z')][c(y'-1)][c(x'-1)]); elements of a
+// row past x' = Dx + 1 (pitch padding) repeat the last voxel.
+__global__ void k_pack_bordered(const float* __restrict__ raw, float* __restrict__ out, int Dx, int Dy, int Dz,
+                                BorderedLayout bl) {
+  const int64_t n = bl.elements();
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e % bl.px);
+    const int64_t r = e / bl.px;
+    const int y = (int)(r % bl.py), z = (int)(r / bl.py);
+    const int cx = min(max(x - 1, 0), Dx - 1), cy = min(max(y - 1, 0), Dy - 1);
+    const int z0 = min(max(z - 1, 0), Dz - 1), z1 = min(z, Dz - 1);
+    const size_t row = (size_t)cy * Dx + cx, plane = (size_t)Dx * Dy;
+    float2 v;
+    v.x = raw[(size_t)z0 * plane + row];
+    v.y = raw[(size_t)z1 * plane + row];
+    reinterpret_cast<float2*>(out)[e] = v;
   }
 }
 
@@ -1104,6 +1146,14 @@ hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, in
 
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream) {
   k_full_reduce<<<S, kWG, 0, stream>>>(pr, terms, obj);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_bordered(const float* raw, float* out, int Dx, int Dy, int Dz, BorderedLayout bl,
+                                hipStream_t stream) {
+  const int64_t n = bl.elements();
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  k_pack_bordered<<<blocks, 256, 0, stream>>>(raw, out, Dx, Dy, Dz, bl);
   return hipGetLastError();
 }
 

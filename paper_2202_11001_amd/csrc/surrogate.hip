@@ -304,15 +304,15 @@ __global__ void k_iota(int n, int* idx) {
 
 // ---------------------------------------------------------------- features
 
-// clamped trilinear sample of a z-pair interleaved image at voxel position p
-__device__ float sample_packed(const float* img, const int D[3], float px, float py, float pz) {
-  px = fminf(fmaxf(px, 0.f), (float)(D[0] - 1));
-  py = fminf(fmaxf(py, 0.f), (float)(D[1] - 1));
-  pz = fminf(fmaxf(pz, 0.f), (float)(D[2] - 1));
-  const int ix = min((int)px, D[0] - 2), iy = min((int)py, D[1] - 2), iz = min((int)pz, D[2] - 2);
+// trilinear sample of a bordered z-pair image at voxel position p clamped to [0, D-1]
+__device__ float sample_packed(const DevProblem& pr, const float* img, float px, float py, float pz) {
+  px = fminf(fmaxf(px, 0.f), (float)(pr.D[0] - 1)) + 1.f;
+  py = fminf(fmaxf(py, 0.f), (float)(pr.D[1] - 1)) + 1.f;
+  pz = fminf(fmaxf(pz, 0.f), (float)(pr.D[2] - 1)) + 1.f;
+  const int ix = (int)px, iy = (int)py, iz = (int)pz;
   const float fx = px - ix, fy = py - iy, fz = pz - iz;
-  const float* e = img + 2 * ((size_t)iz * D[0] * D[1] + (size_t)iy * D[0] + ix);
-  const float* f = e + 2 * D[0];
+  const float* e = img + 2 * ((size_t)iz * pr.exy + (size_t)iy * pr.ex + ix);
+  const float* f = e + 2 * pr.ex;
   // e: (x,y,z),(x,y,z+1),(x+1,y,z),(x+1,y,z+1); f: the same at y+1
   const float c00 = e[0] + fx * (e[2] - e[0]), c01 = e[1] + fx * (e[3] - e[1]);
   const float c10 = f[0] + fx * (f[2] - f[0]), c11 = f[1] + fx * (f[3] - f[1]);
@@ -363,8 +363,8 @@ __global__ void k_features(DevProblem pr, const float* __restrict__ X, int S, in
             o[6 + 6 * slot + 3 * g + a] = v;
           }
         const float off[3] = {h[0] * dx, h[1] * dy, h[2] * dz};
-        const float im = sample_packed(pr.img[0], pr.D, c[0] + off[0], c[1] + off[1], c[2] + off[2]);
-        const float it = sample_packed(pr.img[1], pr.D, c[3] + off[0], c[4] + off[1], c[5] + off[2]);
+        const float im = sample_packed(pr, pr.img[0], c[0] + off[0], c[1] + off[1], c[2] + off[2]);
+        const float it = sample_packed(pr, pr.img[1], c[3] + off[0], c[4] + off[1], c[5] + off[2]);
         o[162 + slot] = im - it;
         ++slot;
       }

@@ -51,7 +51,7 @@ class PartialJob(C.Structure):
 
 class ProblemInfo(C.Structure):
     _fields_ = [("P", C.c_int32), ("T", C.c_int32), ("E", C.c_int32), ("max_star", C.c_int32),
-                ("V", C.c_int64), ("max_affected", C.c_int32), ("norm", C.c_double * 3)]
+                ("V", C.c_int64), ("max_affected", C.c_int32), ("norm", C.c_double * 3), ("pitch", C.c_int32)]
 
 
 _lib = None
@@ -85,6 +85,8 @@ def lib():
             "dsm_batch_create": ([I, V], I),
             "dsm_batch_destroy": ([V], I),
             "dsm_eval_partial_batch": ([V, I, V, V], I),
+            "dsm_problem_set_pitch": ([V, I], I),
+            "dsm_autotune_pitch": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
             "dsm_surrogate_create": ([V, V], I),
             "dsm_surrogate_destroy": ([V], I),
             "dsm_surrogate_last_error": ([], C.c_char_p),
@@ -273,6 +275,37 @@ class Problem:
         _check(lib().dsm_accept(self._h, X.shape[0], _dptr(X), pts.shape[0], _dptr(pts), _dptr(cand),
                                 _dptr(part_old), _dptr(part_new), _dptr(flags), _dptr(terms_cand), _dptr(terms_cache),
                                 _dptr(obj), na, _dptr(archive), _dptr(accepted), _stream(stream)))
+
+    @property
+    def pitch(self):
+        """Row pitch (elements) of the device image layout."""
+        info = ProblemInfo()
+        _check(lib().dsm_problem_query(self._h, C.byref(info)))
+        return int(info.pitch)
+
+    def set_pitch(self, pitch):
+        """Re-packs the device images with row pitch `pitch` (0 = default); synchronises."""
+        _check(lib().dsm_problem_set_pitch(self._h, int(pitch)))
+
+    def autotune_pitch(self, X, fos_off, fos_pts, cand, tet_terms_in=None, pitches=None):
+        """Times the partial evaluation for each candidate pitch and keeps the
+        fastest; returns (best pitch, {pitch: ms})."""
+        S, F = X.shape[0], fos_off.shape[0] - 1
+        pl = np.ascontiguousarray(pitches if pitches is not None else [], dtype=np.int32)
+        n = len(pl) if pitches is not None else 6
+        ms = np.zeros(n, np.float32)
+        best = C.c_int32()
+        _check(lib().dsm_autotune_pitch(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                        _dptr(tet_terms_in), len(pl) if pitches is not None else 0,
+                                        _np_ptr(pl), _np_ptr(ms), C.byref(best)))
+        if pitches is None:
+            pl = self._default_pitch_candidates()
+        return int(best.value), {int(p): float(t) for p, t in zip(pl, ms)}
+
+    def _default_pitch_candidates(self):
+        Dx = self.dims[0]
+        d0 = Dx + 2 + ((8 - (Dx + 2) % 16) + 16) % 16
+        return [d0 + k for k in (0, 4, 8, 16, 24, 56)]
 
     def timing(self, capacity):
         """Record the sweep kernel's duration in the next `capacity` evaluation calls."""

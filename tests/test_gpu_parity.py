@@ -368,3 +368,45 @@ def test_uneven_batch_one_launch(level):
         np.testing.assert_array_equal(g_fl, rfl)
         assert_objectives_close(o[1].cpu().numpy()[s, elems][None], rnew, flags=g_fl, what=f"{w.name} part_new")
         assert_objectives_close(o[0].cpu().numpy()[s, elems][None], rold, what=f"{w.name} part_old")
+
+
+def test_layout_pitch_changes_nothing():
+    """The row pitch of the device image layout changes no result bit, and
+    the autotuner keeps one of its candidates."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    gp = _gpu_problem(w, len(X))
+    Xd, offd, ptsd, cd = _t(X), _t(off), _t(pts), _t(cand)
+    Dx = w.dims[0]
+
+    def run():
+        obj, fl = gp.eval_full(Xd)
+        res = gp.eval_partial(Xd, offd, ptsd, cd, voxel_count=True)
+        torch.cuda.synchronize()
+        return [obj.cpu().numpy(), fl.cpu().numpy()] + [r.cpu().numpy() for r in res]
+
+    _say(f"pitch default {gp.pitch}")
+    ref_out = run()
+    for pitch in (Dx + 2, Dx + 13, Dx + 2 + 64, 0):
+        gp.set_pitch(pitch)
+        assert gp.pitch == (pitch if pitch else ref_pitch_default(Dx))
+        for a, b in zip(run(), ref_out):
+            np.testing.assert_array_equal(a, b)
+    cands = [Dx + 2, Dx + 6, Dx + 10]
+    best, table = gp.autotune_pitch(Xd, offd, ptsd, cd, pitches=cands)
+    assert best in cands and gp.pitch == best and len(table) == 3 and all(t > 0 for t in table.values())
+    for a, b in zip(run(), ref_out):
+        np.testing.assert_array_equal(a, b)
+    with pytest.raises(dsm.DsmError):
+        gp.set_pitch(Dx + 1)
+
+
+def ref_pitch_default(Dx):
+    """Smallest pitch >= Dx + 2 that is 8 mod 16."""
+    p = Dx + 2
+    while p % 16 != 8:
+        p += 1
+    return p
