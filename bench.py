@@ -138,20 +138,42 @@ def screened_step(gp, Xd, offd, ptsd, candd, cache, out, w, S, F, K=4, train_ste
             "train_loss_last": float(lo[-20:].mean())}
 
 
+def generation_timing(gp, Xd, n=3):
+    """Milliseconds per plain optimiser generation (8 class steps: sample,
+    evaluate, accept) run eagerly and replayed from a captured HIP graph."""
+    import torch
+    from paper_2202_11001_amd import optimizer as O
+    res = {}
+    for mode in ("eager", "graph"):
+        opt = O.Optimiser(gp, Xd, sigma=1.0, seed=11, graph=mode == "graph")
+        opt.generation()  # capture / warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            opt.generation()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        res[mode + "_ms"] = float(np.median(ts))
+    return res
+
+
 def surrogate_run(gp, X, G, train_generations, name):
     """Plain run of G generations vs a run whose first train_generations
     generations are plain (collecting exact deltas), followed by surrogate
     training and screened generations; hypervolume of the elitist archive
-    against a reference point fixed by the initial population."""
+    against a reference point fixed by the initial population.  Generations
+    replay a captured HIP graph (the collecting ones run eagerly); the clock
+    counts optimisation and training, not the hypervolume monitoring."""
     import torch
     from paper_2202_11001_amd import optimizer as O
     Xd = torch.from_numpy(X).to("cuda:0")
     log(f"plain run: {G} generations")
-    lp, op, _ = O.run(gp, Xd, G, sigma=1.0, seed=5, log_every=10)
+    lp, op, _ = O.run(gp, Xd, G, sigma=1.0, seed=5, log_every=10, graph=True)
     target = 0.99 * lp.hypervolume[-1]
     log(f"screened run: {train_generations} plain generations, then screened, until hv >= {target:.6g} or {G}")
     ls, os_, sur = O.run(gp, Xd, G, sigma=1.0, seed=5, train_generations=train_generations, target_hv=target,
-                         log_every=10)
+                         log_every=10, graph=True)
     reach = next((i for i, h in enumerate(ls.hypervolume) if h >= target), None)
     res = {"workload": name, "generations": G, "train_generations": train_generations,
            "plain": {"final_hv": lp.hypervolume[-1], "seconds": lp.seconds[-1],
@@ -247,6 +269,9 @@ def main():
         f"wall {wall:.3f} s")
 
     screened = None if args.no_screen else screened_step(gp, Xd, offd, ptsd, candd, cache, out, w, S, F)
+    generation = None if args.profile else generation_timing(gp, Xd)
+    if generation:
+        log(f"optimiser generation ms: {generation}")
 
     evals_per_s = S * F / (ms / 1e3)
     samples_per_s = samples / (ms / 1e3)
@@ -276,6 +301,8 @@ def main():
     }
     if screened is not None:
         res["screened"] = screened
+    if generation is not None:
+        res["generation"] = generation
     if not args.no_cpu:
         log("cpu baseline (oracle)...")
         res["cpu_baseline"] = cpu_baseline(w, X, off, pts, cand)

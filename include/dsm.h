@@ -317,7 +317,7 @@ dsm_status dsm_surrogate_train(dsm_surrogate* s, int32_t N, const uint16_t* feat
  * pick dev [S][F] = the candidate with the best predicted Pareto rank among the
  * K (ties: smallest sum of standardised predictions); run_exact dev [S][F] = 1
  * iff its predicted delta is accepted by the rule of dsm_accept (with obj dev
- * [S][3] and an archive dev [n_archive][3]; without them only changes that
+ * [S][3] and an archive dev [n_archive][3], +inf rows ending it; without them only changes that
  * improve an objective and worsen none pass).  pred dev
  * [S][F][K][3] (raw predicted deltas) and cand_pick dev [S][F][2][3] (the
  * picked candidates) may be NULL.  Errors: DSM_ERR_CAPACITY if S*F*K > max_rows. */
@@ -334,9 +334,13 @@ dsm_status dsm_surrogate_screen(dsm_surrogate* s, dsm_problem* p, int32_t S, con
  * in both grids plus N(0, sigma) voxels on its free (non-border) axes, clamped to
  * the image box and rounded to the 1/128-voxel lattice.  The normal deviates
  * come from a counter-based generator keyed by (seed, counter, element index):
- * equal arguments give equal candidates. */
+ * equal arguments give equal candidates.  counter_dev dev [1] or NULL: when
+ * given, the counter is counter + *counter_dev, read when the kernel runs (a
+ * captured HIP graph then draws new candidates on every replay once the
+ * caller advances *counter_dev on the device). */
 dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
-                                 float sigma, uint64_t seed, uint64_t counter, float* cand, void* stream);
+                                 float sigma, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
+                                 void* stream);
 
 /* Sec. 2.2: accepts the partial changes of one evaluated batch of single-point
  * elements whose affected tetrahedra are pairwise disjoint (e.g. points of one
@@ -344,7 +348,8 @@ dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int3
  * flags are 0 and its delta (part_new - part_old, dev [S][F][3]) improves one
  * objective without worsening another, or improves one objective and the new
  * objective vector obj[s] + delta is not dominated by any of the n_archive
- * vectors archive dev [n][3].  Accepted changes write cand dev [S][F][2][3] into
+ * vectors archive dev [n][3]; a row whose first value is +inf ends the archive
+ * (a fixed-capacity archive padded with +inf rows can be captured in a graph).  Accepted changes write cand dev [S][F][2][3] into
  * X dev [S][2][P][3] and copy the candidate terms of the point's star from
  * terms_cand dev [S][T][3] (as written by dsm_eval_partial(_masked)) into
  * terms_cache dev [S][T][3]; obj dev [S][3] is then recomputed from the cache.

@@ -35,8 +35,10 @@ __device__ __forceinline__ double normal(unsigned long long seed, unsigned long 
 // N(0, sigma) voxels on its free axes, clamped to the image box and rounded to
 // the 1/128-voxel lattice (half to even).
 __global__ void k_sample(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ pts, int K,
-                         float sigma, unsigned long long seed, unsigned long long counter, float* __restrict__ cand) {
+                         float sigma, unsigned long long seed, unsigned long long counter,
+                         const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (counter_dev) counter += *counter_dev;
   const int64_t n = (int64_t)S * F * K * 6;
   if (e >= n) return;
   const int comp = (int)(e % 6);
@@ -86,6 +88,7 @@ __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, con
       bool dominated = false, improves = false;
       for (int o = 0; o < 3; ++o) improves = improves || d[o] < 0.0;
       for (int q = 0; q < n_arch && !dominated; ++q) {
+        if (arch[(size_t)q * 3] == INFINITY) break;  // padding ends the archive
         bool ale = true, alt = false;
         for (int o = 0; o < 3; ++o) {
           ale = ale && arch[(size_t)q * 3 + o] <= nv[o];
@@ -114,12 +117,14 @@ using namespace dsm;
 extern "C" {
 
 dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
-                                 float sigma, uint64_t seed, uint64_t counter, float* cand, void* stream) {
+                                 float sigma, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
+                                 void* stream) {
   if (!p || !X || !fos_pts || !cand || S < 0 || F < 0 || K < 1 || !(sigma >= 0.f)) return DSM_ERR_ARG;
   const int64_t n = (int64_t)S * F * K * 6;
   if (n == 0) return DSM_OK;
   k_sample<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(p->dev, S, X, F, fos_pts, K, sigma, seed,
-                                                                       counter, cand);
+                                                                       counter, (const unsigned long long*)counter_dev,
+                                                                       cand);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 

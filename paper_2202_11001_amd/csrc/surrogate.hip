@@ -474,6 +474,7 @@ __global__ void k_select(int S, int F, int K, const float* __restrict__ pred_std
     for (int o = 0; o < kOut; ++o) nv[o] = obj[(size_t)s * kOut + o] + d[o];
     bool dominated = false;
     for (int a = 0; a < n_arch && !dominated; ++a) {
+      if (arch[(size_t)a * kOut] == INFINITY) break;  // padding ends the archive
       bool ale = true, alt = false;
       for (int o = 0; o < kOut; ++o) {
         ale = ale && arch[(size_t)a * kOut + o] <= nv[o];

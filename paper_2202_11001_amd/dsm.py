@@ -80,7 +80,7 @@ def lib():
             "dsm_problem_timing": ([V, I], I),
             "dsm_problem_timing_read": ([V, V, I, V], I),
             "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
-            "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V], I),
+            "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
             "dsm_batch_destroy": ([V], I),
@@ -258,15 +258,16 @@ class Problem:
                                                  _dptr(flags), _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
         return out
 
-    def sample_candidates(self, X, pts, K, sigma, seed, counter, out=None, stream=None):
-        """Candidates [S][F][K][2][3] (K > 1) or [S][F][2][3] (K == 1)."""
+    def sample_candidates(self, X, pts, K, sigma, seed, counter, out=None, stream=None, counter_dev=None):
+        """Candidates [S][F][K][2][3] (K > 1) or [S][F][2][3] (K == 1); the counter is
+        counter + counter_dev[0] when a device counter (int64 [1]) is given."""
         torch = _torch()
         S, F = X.shape[0], pts.shape[0]
         if out is None:
             shape = (S, F, 2, 3) if K == 1 else (S, F, K, 2, 3)
             out = torch.empty(shape, dtype=torch.float32, device=X.device)
         _check(lib().dsm_sample_candidates(self._h, S, _dptr(X), F, _dptr(pts), int(K), float(sigma), int(seed),
-                                           int(counter), _dptr(out), _stream(stream)))
+                                           int(counter), _dptr(counter_dev), _dptr(out), _stream(stream)))
         return out
 
     def accept(self, X, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,

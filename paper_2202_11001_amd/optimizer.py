@@ -37,15 +37,29 @@ def nondominated(points):
     pts = np.unique(np.asarray(points, dtype=np.float64), axis=0)
     if len(pts) == 0:
         return pts
-    order = np.argsort(pts[:, 0], kind="stable")
-    pts = pts[order]
     keep = np.ones(len(pts), dtype=bool)
-    for a in range(len(pts)):
-        if not keep[a]:
-            continue
-        dom = np.all(pts[a] <= pts, axis=1) & np.any(pts[a] < pts, axis=1)
-        keep &= ~dom
+    for b in range(0, len(pts), 1024):  # rows b.. against all rows, in blocks
+        blk = pts[b:b + 1024]
+        le = np.all(pts[None, :, :] <= blk[:, None, :], axis=2)
+        lt = np.any(pts[None, :, :] < blk[:, None, :], axis=2)
+        keep[b:b + 1024] = ~np.any(le & lt, axis=1)
     return pts[keep]
+
+
+def merge_archive(archive, new):
+    """Non-dominated rows of archive (itself non-dominated) and new points."""
+    new = nondominated(new)
+    if len(archive) == 0:
+        return new
+    arch = np.asarray(archive, dtype=np.float64)
+    # archive rows dominated by a new point, new points dominated by (or equal to) an archive row
+    le = np.all(new[None, :, :] <= arch[:, None, :], axis=2)
+    lt = np.any(new[None, :, :] < arch[:, None, :], axis=2)
+    arch_keep = ~np.any(le & lt, axis=1)
+    le2 = np.all(arch[None, :, :] <= new[:, None, :], axis=2)
+    new_keep = ~np.any(le2, axis=1)
+    out = np.concatenate([arch[arch_keep], new[new_keep]])
+    return out[np.lexsort(out.T[::-1])]
 
 
 def hypervolume(points, ref):
@@ -74,16 +88,22 @@ def hypervolume(points, ref):
 @dataclass
 class RunLog:
     hypervolume: list = field(default_factory=list)
-    seconds: list = field(default_factory=list)        # wall time at the end of each generation
+    seconds: list = field(default_factory=list)        # optimisation time (monitoring excluded) after each generation
     exact_evals: list = field(default_factory=list)    # exact partial evaluations per generation
     accepted: list = field(default_factory=list)
     archive_size: list = field(default_factory=list)
 
 
 class Optimiser:
-    """Population optimiser state on the GPU for one problem."""
+    """Population optimiser state on the GPU for one problem.
 
-    def __init__(self, problem, X, sigma=1.0, seed=1, K=4):
+    With ``graph=True`` each generation's 8 class steps (sample, screen,
+    evaluate, accept) are captured once in a HIP graph and replayed: the sampler
+    reads its counter from device memory and the elitist archive is a
+    fixed-capacity device buffer padded with +inf rows, so a replay needs no
+    host work.  Eager and graph generations give bit-identical results."""
+
+    def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14):
         import torch
         self.torch = torch
         self.p = problem
@@ -92,7 +112,6 @@ class Optimiser:
         self.sigma = float(sigma)
         self.seed = int(seed)
         self.K = int(K)
-        self.counter = 0
         dev = X.device
         self.classes = [torch.from_numpy(c).to(dev) for c in parity_classes(problem.mesh)]
         self.offs = [torch.arange(len(c) + 1, dtype=torch.int32, device=dev) for c in self.classes]
@@ -105,24 +124,41 @@ class Optimiser:
         self.archive = nondominated(obj.cpu().numpy())
         self.ref = 1.1 * obj.cpu().numpy().max(axis=0)
         self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
+        # sampler counter: generation g uses counters 8 g + 1 ... 8 g + 8
+        self.counter_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.use_graph = bool(graph)
+        self.capacity = int(archive_capacity)
+        self.arch_dev = torch.full((self.capacity, 3), float("inf"), dtype=torch.float64, device=dev)
+        self._graph = None
+        self._graph_sur = None
+        self._outs = None
 
-    def _archive_dev(self):
-        return self.torch.from_numpy(np.ascontiguousarray(self.archive)).to(self.X.device)
+    @property
+    def counter(self):
+        return int(self.counter_dev.item())
 
-    def generation(self, surrogate=None, log=None):
-        """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
+    def _load_archive(self):
+        n = len(self.archive)
+        if n > self.capacity:
+            raise ValueError(f"archive of {n} points exceeds the capacity {self.capacity}")
+        self.arch_dev[n:].fill_(float("inf"))
+        if n:
+            self.arch_dev[:n].copy_(self.torch.from_numpy(np.ascontiguousarray(self.archive)))
+
+    def _steps(self, surrogate):
+        """The 8 class steps of one generation, enqueued on the current stream
+        without host synchronisation; returns per class (mask or None, accepted)."""
         torch = self.torch
-        n_exact, n_acc = 0, 0
-        arch = self._archive_dev()
-        for pts, off in zip(self.classes, self.offs):
+        outs = []
+        for c, (pts, off) in enumerate(zip(self.classes, self.offs)):
             F = pts.shape[0]
-            self.counter += 1
             if surrogate is None:
-                cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, self.counter)
+                cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
                 mask = None
             else:
-                candK = self.p.sample_candidates(self.X, pts, self.K, self.sigma, self.seed, self.counter)
-                _, mask, _, cand = surrogate.screen(self.p, self.X, pts, candK, obj=self.obj, archive=arch)
+                candK = self.p.sample_candidates(self.X, pts, self.K, self.sigma, self.seed, c + 1,
+                                                 counter_dev=self.counter_dev)
+                _, mask, _, cand = surrogate.screen(self.p, self.X, pts, candK, obj=self.obj, archive=self.arch_dev)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
                                                      tet_terms_new=self.terms_cand, mask=mask)
             if self.collect is not None:
@@ -130,11 +166,33 @@ class Optimiser:
                 ok = (flags == 0).reshape(-1)
                 self.collect.append((feats[ok], old.reshape(-1, 3)[ok], new.reshape(-1, 3)[ok]))
             acc = torch.empty((self.S, F), dtype=torch.uint8, device=self.X.device)
-            self.p.accept(self.X, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj, archive=arch,
-                          accepted=acc)
-            n_exact += self.S * F if mask is None else int(mask.sum().item())
-            n_acc += int(acc.sum().item())
-        self.archive = nondominated(np.concatenate([self.archive, self.obj.cpu().numpy()]))
+            self.p.accept(self.X, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
+                          archive=self.arch_dev, accepted=acc)
+            outs.append((mask, acc, cand, old, new, flags))
+        self.counter_dev += 8
+        return outs
+
+    def generation(self, surrogate=None, log=None):
+        """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
+        torch = self.torch
+        self._load_archive()
+        if self.use_graph and self.collect is None:
+            if self._graph is None or self._graph_sur is not surrogate:
+                # warm up once on a side stream, then capture
+                s = torch.cuda.Stream()
+                s.wait_stream(torch.cuda.current_stream())
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=s):
+                    self._outs = self._steps(surrogate)
+                self._graph, self._graph_sur = g, surrogate
+                # capture recorded the work without running it
+            self._graph.replay()
+            outs = self._outs
+        else:
+            outs = self._steps(surrogate)
+        n_exact = sum(self.S * acc.shape[1] if mask is None else int(mask.sum().item()) for mask, acc, *_ in outs)
+        n_acc = sum(int(acc.sum().item()) for _, acc, *_ in outs)
+        self.archive = merge_archive(self.archive, self.obj.cpu().numpy())
         return n_exact, n_acc
 
     def hypervolume(self):
@@ -155,18 +213,19 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
-        K=4, target_hv=None, log_every=0):
+        K=4, target_hv=None, log_every=0, graph=False):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
-    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K)
+    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph)
     log = RunLog()
-    t0 = time.perf_counter()
+    t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate
     if train_generations > 0:
         opt.collect = []
     for g in range(generations):
+        t0 = time.perf_counter()
         use = sur if (train_generations == 0 or g >= train_generations) else None
         n_exact, n_acc = opt.generation(surrogate=use)
         if train_generations > 0 and g + 1 == train_generations:
@@ -174,7 +233,8 @@ def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_genera
                                         max_rows=max(1 << 16, opt.S * max(len(c) for c in opt.classes) * K))
             opt.collect = None
         torch.cuda.synchronize()
-        log.seconds.append(time.perf_counter() - t0)
+        t_opt += time.perf_counter() - t0
+        log.seconds.append(t_opt)
         log.hypervolume.append(opt.hypervolume())
         log.exact_evals.append(n_exact)
         log.accepted.append(n_acc)

@@ -49,3 +49,14 @@ def test_hypervolume_exact():
         assert O.hypervolume(pts, ref_) == __import__("pytest").approx(_hv_bruteforce(pts, ref_), rel=1e-12)
     # points outside the reference box contribute nothing
     assert O.hypervolume([[11, 1, 1]], ref_) == 0.0
+
+
+def test_merge_archive_equals_filtering_the_union():
+    rng = np.random.default_rng(5)
+    arch = O.nondominated(rng.random((300, 3)))
+    for _ in range(5):
+        new = np.round(rng.random((64, 3)), 2)
+        new[:4] = arch[:4]  # duplicates of archive rows
+        merged = O.merge_archive(arch, new)
+        np.testing.assert_array_equal(merged, O.nondominated(np.concatenate([arch, new])))
+        arch = merged
