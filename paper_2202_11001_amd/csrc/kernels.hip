@@ -799,14 +799,14 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
 }
 
 template <int PARTIAL>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep(EvalArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_sweep(EvalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G), smem);
 }
 
 // Several problems in one launch: workgroup -> job by the job table's
 // workgroup offsets (the XCD mapping is applied to the concatenated list).
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_batch(
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_sweep_batch(
     const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off, int n_jobs, int total) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lg = xcd_logical(blockIdx.x, total);
