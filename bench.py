@@ -158,6 +158,65 @@ def generation_timing(gp, Xd, n=3):
     return res
 
 
+def surrogate_report(gp, opt, sur, K=4, seed=4242):
+    """Held-out quality of the trained surrogate on the final screened
+    population: K fresh candidates for every (solution, point) of one parity
+    class, all evaluated exactly.  Reports RMSE, R^2 and sign agreement of the
+    predicted deltas per objective, and the ablation trained pick vs random
+    pick vs an untrained network's pick (mean standardised exact delta of the
+    pick, fraction of picks accepted by the exact acceptance rule)."""
+    import torch
+    from paper_2202_11001_amd import dsm
+    from paper_2202_11001_amd import optimizer as O
+    pts = opt.classes[0]
+    F, S = pts.shape[0], opt.S
+    off = torch.arange(F + 1, dtype=torch.int32, device=pts.device)
+    candK = gp.sample_candidates(opt.X, pts, K, opt.sigma, seed, 1)
+    true = torch.empty((S, F, K, 3), dtype=torch.float64, device=pts.device)
+    ok = torch.ones((S, F), dtype=torch.bool, device=pts.device)
+    for k in range(K):
+        o, n, fl, _ = gp.eval_partial(opt.X, off, pts, candK[:, :, k].contiguous(), tet_terms_in=opt.cache)
+        true[:, :, k] = n - o
+        ok &= fl == 0
+    pick, _, pred, _ = sur.screen(gp, opt.X, pts, candK)
+    fresh = dsm.Surrogate(seed=99, max_rows=S * F * K, max_batch=1024)
+    im, irs, om, ors = sur.scaling()
+    fresh.set_scaling(im, irs, om, ors)
+    pick0 = fresh.screen(gp, opt.X, pts, candK)[0]
+    t = true[ok].reshape(-1, 3).cpu().numpy()
+    p = pred[ok].reshape(-1, 3).to(torch.float64).cpu().numpy()
+    res = {"candidates": int(t.shape[0]), "rmse": [], "r2": [], "sign_agreement": []}
+    for c in range(3):
+        err = p[:, c] - t[:, c]
+        var = float(np.var(t[:, c]))
+        res["rmse"].append(float(np.sqrt(np.mean(err ** 2))))
+        res["r2"].append(float(1 - np.mean(err ** 2) / var) if var > 0 else None)
+        res["sign_agreement"].append(float(np.mean(np.sign(p[:, c]) == np.sign(t[:, c]))))
+    tn = true.cpu().numpy()
+    okn = ok.cpu().numpy()
+    score = ((tn - om) * ors).sum(axis=-1)
+    arch = np.asarray(opt.archive)
+    objn = opt.obj.cpu().numpy()
+
+    def accepted(d, s_idx):
+        if np.all(d <= 0) and np.any(d < 0):
+            return True
+        if not np.any(d < 0):
+            return False
+        nv = objn[s_idx] + d
+        return not np.any(np.all(arch <= nv, axis=1) & np.any(arch < nv, axis=1))
+
+    rng = np.random.default_rng(seed)
+    picks = {"trained": pick.cpu().numpy(), "untrained": pick0.cpu().numpy(),
+             "random": rng.integers(0, K, size=(S, F))}
+    ss = np.nonzero(okn)
+    for name, pk in picks.items():
+        sel = pk[ss]
+        res[f"{name}_mean_std_delta"] = float(score[ss[0], ss[1], sel].mean())
+        res[f"{name}_accept_rate"] = float(np.mean([accepted(tn[a, b, k], a) for a, b, k in zip(ss[0], ss[1], sel)]))
+    return res
+
+
 def surrogate_run(gp, X, G, train_generations, name):
     """Plain run of G generations vs a run whose first train_generations
     generations are plain (collecting exact deltas), followed by surrogate
@@ -175,6 +234,8 @@ def surrogate_run(gp, X, G, train_generations, name):
     ls, os_, sur = O.run(gp, Xd, G, sigma=1.0, seed=5, train_generations=train_generations, target_hv=target,
                          log_every=10, graph=True)
     reach = next((i for i, h in enumerate(ls.hypervolume) if h >= target), None)
+    quality = surrogate_report(gp, os_, sur)
+    log(f"surrogate held-out quality: {quality}")
     res = {"workload": name, "generations": G, "train_generations": train_generations,
            "plain": {"final_hv": lp.hypervolume[-1], "seconds": lp.seconds[-1],
                      "hv": lp.hypervolume, "t": lp.seconds, "exact": lp.exact_evals, "accepted": lp.accepted},
@@ -182,7 +243,7 @@ def surrogate_run(gp, X, G, train_generations, name):
                         "reached_generation": None if reach is None else reach + 1,
                         "seconds_to_target": None if reach is None else ls.seconds[reach],
                         "hv": ls.hypervolume, "t": ls.seconds, "exact": ls.exact_evals, "accepted": ls.accepted},
-           "target_hv": target}
+           "target_hv": target, "surrogate_quality": quality}
     print(json.dumps(res), flush=True)
 
 

@@ -291,6 +291,10 @@ dsm_status dsm_surrogate_params(dsm_surrogate* s, float* host, int32_t set);
 dsm_status dsm_surrogate_fit_scaling(dsm_surrogate* s, int32_t N, const float* feats, const float* deltas, void* stream);
 /* Host copies of the fitted scaling (any output may be NULL). */
 dsm_status dsm_surrogate_get_scaling(dsm_surrogate* s, float* in_mean, float* in_rstd, float* out_mean, float* out_rstd);
+/* Sets the scaling from host [192], [192], [3], [3] arrays (e.g. those of
+ * another network, for comparisons at equal standardisation); synchronous. */
+dsm_status dsm_surrogate_set_scaling(dsm_surrogate* s, const float* in_mean, const float* in_rstd, const float* out_mean,
+                                     const float* out_rstd);
 /* Raw feature rows feats dev [S*F*K][192] for candidates cand dev
  * [S][F][K][2][3] of single-point elements fos_pts dev [F] of solutions X. */
 dsm_status dsm_surrogate_features(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,

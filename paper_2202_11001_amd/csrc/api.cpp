@@ -44,7 +44,7 @@ void release(dsm_problem* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   void* bufs[] = {p->d_img, p->d_raw, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
-                  p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws, p->d_ident};
+                  p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws, p->d_ident, p->d_cflags, p->d_ccount};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -227,6 +227,12 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
                             (size_t)p->max_S * full_groups * kFullChunk);
   }
   DSM_TRY(dev_alloc(&p->d_simws, p->simws_len), "hipMalloc sweep workspace");
+  p->nchunk = (p->maxA + kPartChunk - 1) / kPartChunk;
+  {
+    const size_t nc = (size_t)p->max_S * std::max(1, p->max_F) * p->nchunk;
+    DSM_TRY(dev_alloc(&p->d_cflags, nc), "hipMalloc chunk flags");
+    DSM_TRY(dev_alloc(&p->d_ccount, nc), "hipMalloc chunk counts");
+  }
 #undef DSM_TRY
 
   DevProblem& dv = p->dev;
@@ -254,7 +260,7 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
   dv.norm[2] = (ng[0] + ng[1]) > 0 ? 1.0 / (double)(ng[0] + ng[1]) : 0.0;
 
   // the evaluation kernel's dynamic LDS must fit one workgroup
-  const size_t lds = std::max(eval_lds_bytes(p->maxA, 2), eval_lds_bytes(kFullChunk, 1));
+  const size_t lds = eval_lds_bytes(kMaxChunk, 2);
   if (lds > 64 * 1024) {
     release(p);
     return fail(DSM_ERR_CAPACITY, "max_fos_points too large: affected set of %d tetrahedra needs %zu B of LDS", p->maxA,
@@ -406,6 +412,9 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
   a.vcount = voxel_count;
   a.mask = mask;
   a.simws = p->d_simws;
+  a.nchunk = p->nchunk;
+  a.cflags = p->d_cflags;
+  a.ccount = p->d_ccount;
   hipEvent_t eb, ee;
   timing_pair(p, eb, ee);
   if ((e = launch_eval(a, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
@@ -499,9 +508,9 @@ dsm_status dsm_batch_create(int32_t max_jobs, dsm_batch** out) {
   auto* b = new dsm_batch();
   b->max_jobs = max_jobs;
   hipError_t e = hipMalloc((void**)&b->d_jobs, sizeof(EvalArgs) * max_jobs);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_off, sizeof(int) * (max_jobs + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_off, sizeof(int) * 2 * (max_jobs + 1));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_jobs, sizeof(EvalArgs) * max_jobs, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_off, sizeof(int) * (max_jobs + 1), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_off, sizeof(int) * 2 * (max_jobs + 1), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
   if (e != hipSuccess) {
     dsm_batch_destroy(b);
@@ -529,7 +538,7 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
   if (!b || (n_jobs > 0 && !jobs) || n_jobs < 0) return fail(DSM_ERR_ARG, "null argument");
   if (n_jobs > b->max_jobs) return fail(DSM_ERR_CAPACITY, "n_jobs = %d exceeds max_jobs = %d", n_jobs, b->max_jobs);
   std::vector<EvalArgs> args(n_jobs);
-  std::vector<int> off(n_jobs + 1, 0);
+  std::vector<int> off(n_jobs + 1, 0), foff(n_jobs + 1, 0);  // workgroup offsets: sweep, finish
   size_t lds = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const dsm_partial_job& q = jobs[j];
@@ -562,8 +571,12 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
     a.vcount = q.voxel_count;
     a.mask = q.mask;
     a.simws = p->d_simws;
-    off[j + 1] = off[j] + q.S * q.F;
-    lds = std::max(lds, eval_lds_bytes(a.maxA, a.nver));
+    a.nchunk = p->nchunk;
+    a.cflags = p->d_cflags;
+    a.ccount = p->d_ccount;
+    off[j + 1] = off[j] + q.S * q.F * a.nchunk;
+    foff[j + 1] = foff[j] + q.S * q.F;
+    lds = std::max(lds, eval_lds_bytes(kMaxChunk, a.nver));
   }
   if (n_jobs == 0 || off[n_jobs] == 0) return DSM_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -576,12 +589,14 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
   if (b->pending && (e = hipEventSynchronize(b->copied)) != hipSuccess) return hip_fail(e, "job table wait");
   memcpy(b->h_jobs, args.data(), sizeof(EvalArgs) * n_jobs);
   memcpy(b->h_off, off.data(), sizeof(int) * (n_jobs + 1));
+  memcpy(b->h_off + (n_jobs + 1), foff.data(), sizeof(int) * (n_jobs + 1));
   e = hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(EvalArgs) * n_jobs, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(b->d_off, b->h_off, sizeof(int) * (n_jobs + 1), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_off, b->h_off, sizeof(int) * 2 * (n_jobs + 1), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(b->copied, st);
   if (e != hipSuccess) return hip_fail(e, "job table copy");
   b->pending = true;
-  if ((e = launch_eval_batch(b->d_jobs, b->d_off, n_jobs, off[n_jobs], lds, st)) != hipSuccess)
+  if ((e = launch_eval_batch(b->d_jobs, b->d_off, n_jobs, off[n_jobs], foff[n_jobs], lds, st)) != hipSuccess)
     return hip_fail(e, "batched evaluation launch");
   return DSM_OK;
 }

@@ -14,6 +14,8 @@ constexpr int kWG = 256;          // threads per workgroup of the evaluation ker
 constexpr int kWaves = kWG / 64;  // wave64 waves per workgroup
 constexpr double kLat = 128.0;    // lattice steps per voxel
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
+constexpr int kPartChunk = 8;     // affected tetrahedra per workgroup in partial evaluation
+constexpr int kMaxChunk = kFullChunk > kPartChunk ? kFullChunk : kPartChunk;
 
 // Sampled images are stored z-pair interleaved with a replicated one-voxel
 // border: element (x', y', z') of the (Dx+2) x (Dy+2) x (Dz+1) element grid
@@ -84,6 +86,9 @@ struct EvalArgs {
   uint32_t* vcount;      // [S][G] or null
   const uint8_t* mask;   // [S][G] or null: evaluate only where non-zero (partial)
   double* simws;         // swept dissimilarity workspace of the problem
+  int nchunk;            // partial: workgroups (chunks of kFullChunk affected tetrahedra) per group
+  uint32_t* cflags;      // partial: [S][G][nchunk] constraint flags per chunk
+  uint32_t* ccount;      // partial: [S][G][nchunk] candidate voxel count per chunk
 };
 
 // Host-side topology (topology.cpp).
@@ -105,8 +110,9 @@ hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* fl
 hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
                            int maxA, int* aff, int* aff_cnt, hipStream_t stream);
 hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end, hipStream_t stream);
-hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, size_t lds,
-                             hipStream_t stream);
+// wg_off_dev [2][n_jobs + 1]: workgroup offsets of the jobs in the sweep, then in the finishing kernel
+hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, int total_finish,
+                             size_t lds, hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
 hipError_t launch_pack_bordered(const float* raw, float* out, int Dx, int Dy, int Dz, BorderedLayout bl,
@@ -140,6 +146,9 @@ struct dsm_problem {
   double* d_terms = nullptr;    // [max_S][T][3] workspace for full evaluation
   double* d_simws = nullptr;    // swept dissimilarity per (solution, group, version, tetrahedron)
   size_t simws_len = 0;
+  uint32_t* d_cflags = nullptr; // [max_S][max_F][nchunk] per-chunk flags of a partial evaluation
+  uint32_t* d_ccount = nullptr; // [max_S][max_F][nchunk] per-chunk voxel counts
+  int nchunk = 1;               // ceil(maxA / kFullChunk)
   std::vector<float> identity;  // [P][3]
   float* d_ident = nullptr;     // device copy of the undeformed grid [P][3]
   std::vector<hipEvent_t> ev;   // timing event pairs (begin, end)

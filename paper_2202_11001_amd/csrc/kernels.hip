@@ -599,17 +599,25 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 
 // ------------------------------------------------------------ voxel sweep kernel
 
-// Dissimilarity of every (version, tetrahedron) of one group of one solution:
-// writes simws[((s*G + g)*nver + v)*maxA + i]; partial mode also writes the
-// constraint flags and the voxel count of the candidate.
+// Dissimilarity of every (version, tetrahedron) of one chunk of at most
+// kPartChunk affected tetrahedra (partial evaluation) or of one group of
+// kFullChunk tetrahedra (full evaluation) of one solution: writes
+// simws[((s*G + g)*nver + v)*maxA + i].  Workgroups are numbered (group, chunk,
+// solution) with the solution fastest, so the workgroups resident on an XCD
+// sweep the same few tetrahedra of many solutions and share their image
+// region in L2.  Partial mode also writes the chunk's constraint flags and
+// candidate voxel count to cflags / ccount [S][G][nchunk]; k_finish combines
+// them.
 template <int PARTIAL>
 __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsigned char* smem) {
   double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
-  const int g = logical / a.S, s = logical - g * a.S;
+  const int nchunk = PARTIAL ? a.nchunk : 1;
+  const int g = logical / (a.S * nchunk), rem = logical - g * (a.S * nchunk);
+  const int c = rem / a.S, s = rem - c * a.S;
   const int nver = a.nver;
-  const EvalLayout Lay = eval_layout(a.maxA, nver);
+  const EvalLayout Lay = eval_layout(kMaxChunk, nver);
   int* s_tet = (int*)(smem + Lay.tet);
   float* s_xyz = (float*)(smem + Lay.xyz);
   int* s_units = (int*)(smem + Lay.units);
@@ -619,24 +627,15 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   __shared__ unsigned s_flags;
   __shared__ unsigned s_count[kWaves];
 
-  const int na = (PARTIAL ? a.aff_cnt[g] : min(kFullChunk, pr.T - g * kFullChunk));
-  if (na < 0) {  // malformed FOS element
-    if (tid == 0) {
-      a.flags[(size_t)s * a.G + g] = DSM_FLAG_BAD_FOS;
-      if (a.vcount) a.vcount[(size_t)s * a.G + g] = 0;
-    }
-    return;
-  }
-  if (PARTIAL && a.mask && a.mask[(size_t)s * a.G + g] == 0) {  // not requested
-    if (tid == 0) {
-      a.flags[(size_t)s * a.G + g] = DSM_FLAG_SKIPPED;
-      if (a.vcount) a.vcount[(size_t)s * a.G + g] = 0;
-    }
-    return;
-  }
+  // this chunk's tetrahedra: slots [i0, i0 + na) of the group
+  const int na_all = PARTIAL ? a.aff_cnt[g] : min(kFullChunk, pr.T - g * kFullChunk);
+  const int i0 = c * (PARTIAL ? kPartChunk : kFullChunk);
+  if (na_all <= i0) return;  // malformed element (count -1) or no tetrahedra in this chunk: k_finish sets the flags
+  if (PARTIAL && a.mask && a.mask[(size_t)s * a.G + g] == 0) return;  // not requested
+  const int na = min(PARTIAL ? kPartChunk : kFullChunk, na_all - i0);
   if (tid == 0) s_flags = 0u;
   if (tid < kWaves) s_count[tid] = 0u;
-  for (int i = tid; i < na; i += kWG) s_tet[i] = group_tet(a, g, i);
+  for (int i = tid; i < na; i += kWG) s_tet[i] = group_tet(a, g, i0 + i);
   __syncthreads();
 
   // vertex coordinates of every (version, tetrahedron, grid, vertex) and the
@@ -779,7 +778,7 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   if (lane == 0) s_count[wave] = counted;
   __syncthreads();
 
-  double* out = simws + ((size_t)s * a.G + g) * nver * a.maxA;
+  double* out = simws + ((size_t)s * a.G + g) * nver * a.maxA + i0;
   for (int e = tid; e < nver * na; e += kWG) {
     const int v = e / na, i = e - v * na;
     double sim = 0.0;
@@ -788,20 +787,18 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     out[(size_t)v * a.maxA + i] = sim;
   }
   if (PARTIAL && tid == 0) {
-    const size_t oi = (size_t)s * a.G + g;
-    a.flags[oi] = s_flags;
-    if (a.vcount) {
-      unsigned tot = 0u;
-      for (int w = 0; w < kWaves; ++w) tot += s_count[w];
-      a.vcount[oi] = tot;
-    }
+    const size_t ci = ((size_t)s * a.G + g) * nchunk + c;
+    a.cflags[ci] = s_flags;
+    unsigned tot = 0u;
+    for (int w = 0; w < kWaves; ++w) tot += s_count[w];
+    a.ccount[ci] = tot;
   }
 }
 
 template <int PARTIAL>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_sweep(EvalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G), smem);
+  sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G * (PARTIAL ? a.nchunk : 1)), smem);
 }
 
 // Several problems in one launch: workgroup -> job by the job table's
@@ -834,7 +831,20 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
       a.part_new[oi * 3 + lane] = 0.0;
       a.part_old[oi * 3 + lane] = 0.0;
     }
+    if (a.partial && lane == 0) {
+      a.flags[oi] = na < 0 ? DSM_FLAG_BAD_FOS : DSM_FLAG_SKIPPED;
+      if (a.vcount) a.vcount[oi] = 0u;
+    }
     return;
+  }
+  if (a.partial && lane == 0) {  // combine the chunks' flags and voxel counts in chunk order
+    unsigned fl = 0u, cnt = 0u;
+    for (int c = 0; c * kPartChunk < na; ++c) {
+      fl |= a.cflags[oi * a.nchunk + c];
+      cnt += a.ccount[oi * a.nchunk + c];
+    }
+    a.flags[oi] = fl;
+    if (a.vcount) a.vcount[oi] = cnt;
   }
   const double* sims = simws + oi * a.nver * a.maxA;
   double accn[3] = {0, 0, 0}, acco[3] = {0, 0, 0};
@@ -1121,10 +1131,10 @@ hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, cons
 hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end, hipStream_t stream) {
   const int64_t nwg = (int64_t)a.S * a.G;
   if (nwg <= 0) return hipSuccess;
-  const size_t lds = eval_lds_bytes(a.maxA, a.nver);
+  const size_t lds = eval_lds_bytes(kMaxChunk, a.nver);
   if (ev_begin) (void)hipEventRecord(ev_begin, stream);
   if (a.partial)
-    k_sweep<1><<<(unsigned)nwg, kWG, lds, stream>>>(a);
+    k_sweep<1><<<(unsigned)(nwg * a.nchunk), kWG, lds, stream>>>(a);
   else
     k_sweep<0><<<(unsigned)nwg, kWG, lds, stream>>>(a);
   hipError_t e = hipGetLastError();
@@ -1134,13 +1144,13 @@ hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end
   return hipGetLastError();
 }
 
-hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, size_t lds,
-                             hipStream_t stream) {
+hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, int total_finish,
+                             size_t lds, hipStream_t stream) {
   if (total <= 0) return hipSuccess;
   k_sweep_batch<<<(unsigned)total, kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_finish_batch<<<(unsigned)total, 64, 0, stream>>>(jobs_dev, wg_off_dev, n_jobs);
+  k_finish_batch<<<(unsigned)total_finish, 64, 0, stream>>>(jobs_dev, wg_off_dev + (n_jobs + 1), n_jobs);
   return hipGetLastError();
 }
 

@@ -712,6 +712,20 @@ dsm_status dsm_surrogate_get_scaling(dsm_surrogate* m, float* in_mean, float* in
   return e == hipSuccess ? DSM_OK : sfail(DSM_ERR_DEVICE, hipGetErrorString(e));
 }
 
+dsm_status dsm_surrogate_set_scaling(dsm_surrogate* m, const float* in_mean, const float* in_rstd, const float* out_mean,
+                                     const float* out_rstd) {
+  s_err.clear();
+  if (!m || !in_mean || !in_rstd || !out_mean || !out_rstd) return sfail(DSM_ERR_ARG, "null argument");
+  hipError_t e = hipMemcpy(m->d_in_mean, in_mean, sizeof(float) * kIn, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->d_in_rstd, in_rstd, sizeof(float) * kIn, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->d_out_mean, out_mean, sizeof(float) * kOut, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->d_out_rstd, out_rstd, sizeof(float) * kOut, hipMemcpyHostToDevice);
+  float sc[kOut];
+  for (int o = 0; o < kOut; ++o) sc[o] = 1.f / out_rstd[o];
+  if (e == hipSuccess) e = hipMemcpy(m->d_out_scale, sc, sizeof(float) * kOut, hipMemcpyHostToDevice);
+  return e == hipSuccess ? DSM_OK : sfail(DSM_ERR_DEVICE, hipGetErrorString(e));
+}
+
 dsm_status dsm_surrogate_features(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
                                   const float* cand, float* feats, void* stream) {
   s_err.clear();

@@ -93,6 +93,7 @@ def lib():
             "dsm_surrogate_params": ([V, V, I], I),
             "dsm_surrogate_fit_scaling": ([V, I, V, V, V], I),
             "dsm_surrogate_get_scaling": ([V, V, V, V, V], I),
+            "dsm_surrogate_set_scaling": ([V, V, V, V, V], I),
             "dsm_surrogate_features": ([V, I, V, I, V, I, V, V, V], I),
             "dsm_surrogate_pack": ([V, I, V, V, V, V, V, V, V], I),
             "dsm_surrogate_forward": ([V, I, V, V, V], I),
@@ -375,6 +376,10 @@ class Surrogate:
         om, orr = np.zeros(SUR_OUTPUTS, np.float32), np.zeros(SUR_OUTPUTS, np.float32)
         _scheck(lib().dsm_surrogate_get_scaling(self._h, _np_ptr(im), _np_ptr(ir), _np_ptr(om), _np_ptr(orr)))
         return im, ir, om, orr
+
+    def set_scaling(self, in_mean, in_rstd, out_mean, out_rstd):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (in_mean, in_rstd, out_mean, out_rstd)]
+        _scheck(lib().dsm_surrogate_set_scaling(self._h, *[_np_ptr(a) for a in arrs]))
 
     @staticmethod
     def features(problem, X, pts, cand, stream=None):

@@ -215,3 +215,13 @@ def test_training_and_screening_gain():
     # picked candidates are gathered correctly
     cp = cpick.cpu().numpy()
     assert np.array_equal(cp, np.take_along_axis(candK, pick[:, :, None, None, None], axis=2)[:, :, 0])
+
+
+def test_set_scaling_roundtrip():
+    rng = np.random.default_rng(3)
+    sc = [rng.normal(size=192).astype(np.float32), rng.uniform(0.5, 2, 192).astype(np.float32),
+          rng.normal(size=3).astype(np.float32), rng.uniform(0.5, 2, 3).astype(np.float32)]
+    sur = dsm.Surrogate(seed=1)
+    sur.set_scaling(*sc)
+    for a, b in zip(sur.scaling(), sc):
+        np.testing.assert_array_equal(a, b)
