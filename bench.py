@@ -185,13 +185,15 @@ def surrogate_report(gp, opt, sur, K=4, seed=4242):
     pick0 = fresh.screen(gp, opt.X, pts, candK)[0]
     t = true[ok].reshape(-1, 3).cpu().numpy()
     p = pred[ok].reshape(-1, 3).to(torch.float64).cpu().numpy()
-    res = {"candidates": int(t.shape[0]), "rmse": [], "r2": [], "sign_agreement": []}
+    res = {"candidates": int(t.shape[0]), "rmse": [], "r2": [], "sign_agreement_nonzero": [], "nonzero_fraction": []}
     for c in range(3):
         err = p[:, c] - t[:, c]
         var = float(np.var(t[:, c]))
+        nz = t[:, c] != 0  # e.g. no guidance point in the star: the exact delta is 0
         res["rmse"].append(float(np.sqrt(np.mean(err ** 2))))
         res["r2"].append(float(1 - np.mean(err ** 2) / var) if var > 0 else None)
-        res["sign_agreement"].append(float(np.mean(np.sign(p[:, c]) == np.sign(t[:, c]))))
+        res["sign_agreement_nonzero"].append(float(np.mean(np.sign(p[nz, c]) == np.sign(t[nz, c]))) if nz.any() else None)
+        res["nonzero_fraction"].append(float(nz.mean()))
     tn = true.cpu().numpy()
     okn = ok.cpu().numpy()
     score = ((tn - om) * ors).sum(axis=-1)

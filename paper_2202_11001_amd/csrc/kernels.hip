@@ -327,9 +327,15 @@ __device__ __forceinline__ void row_span(const RasterTet& rt, int y, int z, int 
   x1 = hi;
 }
 
+// One compacted (non-empty) row: both fields are read from one LDS address.
+struct RowRec {
+  float4 rec;  // x: own-image linear index minus start (as int bits); yzw: mapped position of the span's first voxel
+  int start;   // exclusive prefix of span lengths
+  int pad[3];
+};
+
 struct WaveRows {
-  int start[64];   // exclusive prefix of span lengths, by compacted (non-empty) row
-  float4 rec[64];  // x: own-image linear index minus start (as int bits); yzw: mapped position of the span's first voxel
+  RowRec row[64];
   int marker[128];  // per voxel slot of the current 128-voxel chunk pair: 1 where a row starts
 };
 
@@ -375,8 +381,8 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
   const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(ne >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ne, 0u));
   wave_sync();
   if (len > 0) {
-    wr.start[slot] = start;
-    wr.rec[slot] = make_float4(__int_as_float(lin - start), bx, by, bz);
+    wr.row[slot].start = start;
+    wr.row[slot].rec = make_float4(__int_as_float(lin - start), bx, by, bz);
   }
   wave_sync();
   *my_start = len > 0 ? start : -(1 << 30);
@@ -450,8 +456,12 @@ __device__ __forceinline__ float contrib_of(const SampleCtx& c, float a, const T
   const unsigned long long m011 = __builtin_amdgcn_fcmpf(t11.x, tau, kOLE), m111 = __builtin_amdgcn_fcmpf(t11.y, tau, kOLE);
   const unsigned long long all = m000 & m100 & m010 & m110 & m001 & m101 & m011 & m111;
   const unsigned long long any = m000 | m100 | m010 | m110 | m001 | m101 | m011 | m111;
-  // where the 8 taps agree the interpolated indicator is the first tap's
-  float eb = t00.x <= tau ? 1.f : 0.f;
+  const bool ea = a <= tau;
+  const float d = a - b;
+  // where the 8 taps of every lane agree, the interpolated indicator is the
+  // first tap's: m is 0 or 1 and the contribution is d^2 or 1 (the values of
+  // the general formula below)
+  float res = ea != (t00.x <= tau) ? 1.f : d * d;
   if (any & ~all) {  // some lane has taps on both sides of tau: interpolate its indicator
     const float e000 = t00.x <= tau ? 1.f : 0.f, e100 = t00.y <= tau ? 1.f : 0.f;
     const float e010 = t10.x <= tau ? 1.f : 0.f, e110 = t10.y <= tau ? 1.f : 0.f;
@@ -460,12 +470,35 @@ __device__ __forceinline__ float contrib_of(const SampleCtx& c, float a, const T
     const float m00 = fmaf(fx, e100 - e000, e000), m10 = fmaf(fx, e110 - e010, e010);
     const float m01 = fmaf(fx, e101 - e001, e001), m11 = fmaf(fx, e111 - e011, e011);
     const float m0 = fmaf(fy, m10 - m00, m00), m1 = fmaf(fy, m11 - m01, m01);
-    eb = fmaf(fz, m1 - m0, m0);
+    const float eb = fmaf(fz, m1 - m0, m0);
+    const float m = fabsf((ea ? 1.f : 0.f) - eb);
+    res = fmaf(1.f - m, d * d, m);
   }
-  const float ea = a <= tau ? 1.f : 0.f;
-  const float m = fabsf(ea - eb);
-  const float d = a - b;
-  return fmaf(1.f - m, d * d, m);
+  return res;
+}
+
+// Samples voxels q0 + lane (row r0) and q0 + 64 + lane (row r1) of the
+// compacted rows and adds their contributions to the lane's compensated sum.
+// Both samples' loads are issued before either is used.  With TAIL, slots
+// past the last voxel repeat the last voxel (same row) and are weighted 0.
+template <bool TAIL>
+__device__ __forceinline__ void sweep_pair(const WaveRows& wr, const SampleCtx& sc, int q0, int nvox, int lane, int r0,
+                                           int r1, float jx, float jy, float jz, float& sum, float& comp) {
+  const int qa = q0 + lane, qb = qa + 64;
+  const int ea = TAIL ? min(qa, nvox - 1) : qa, eb = TAIL ? min(qb, nvox - 1) : qb;
+  const RowRec ra = wr.row[r0], rb = wr.row[r1];
+  const float foa = (float)(ea - ra.start), fob = (float)(eb - rb.start);
+  const float ava = load1(sc.own, (__float_as_int(ra.rec.x) + ea) << 3);
+  const Taps ta = load_taps(sc, fmaf(jx, foa, ra.rec.y), fmaf(jy, foa, ra.rec.z), fmaf(jz, foa, ra.rec.w));
+  const float avb = load1(sc.own, (__float_as_int(rb.rec.x) + eb) << 3);
+  const Taps tb = load_taps(sc, fmaf(jx, fob, rb.rec.y), fmaf(jy, fob, rb.rec.z), fmaf(jz, fob, rb.rec.w));
+  const float ca = contrib_of(sc, ava, ta);
+  const float cb = contrib_of(sc, avb, tb);
+  const float c = TAIL ? (qa < nvox ? ca : 0.f) + (qb < nvox ? cb : 0.f) : ca + cb;
+  const float y = c - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
 }
 
 __device__ __forceinline__ double len_mm(const double sp[3], const double a[3], const double b[3]) {
@@ -750,24 +783,10 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
       const int r1 = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M1, 0u)) +
                      mk1 - 1;
       carry += __popcll(M1);
-      // slots past the last voxel repeat the last voxel (same row) and are
-      // weighted 0, so both samples' loads are issued before either is used
-      const int qa = q0 + lane, qb = qa + 64;
-      const int ea = min(qa, nvox - 1), eb = min(qb, nvox - 1);
-      const int sa = wr.start[r0], sb = wr.start[r1];
-      const float4 reca = wr.rec[r0], recb = wr.rec[r1];
-      const float foa = (float)(ea - sa), fob = (float)(eb - sb);
-      const float ava = load1(sc.own, (__float_as_int(reca.x) + ea) << 3);
-      const Taps ta = load_taps(sc, fmaf(jx, foa, reca.y), fmaf(jy, foa, reca.z), fmaf(jz, foa, reca.w));
-      const float avb = load1(sc.own, (__float_as_int(recb.x) + eb) << 3);
-      const Taps tb = load_taps(sc, fmaf(jx, fob, recb.y), fmaf(jy, fob, recb.z), fmaf(jz, fob, recb.w));
-      const float ca = contrib_of(sc, ava, ta);
-      const float cb = contrib_of(sc, avb, tb);
-      const float c = (qa < nvox ? ca : 0.f) + (qb < nvox ? cb : 0.f);
-      const float y = c - comp;
-      const float t = sum + y;
-      comp = (t - sum) - y;
-      sum = t;
+      if (q0 + 128 <= nvox)
+        sweep_pair<false>(wr, sc, q0, nvox, lane, r0, r1, jx, jy, jz, sum, comp);
+      else
+        sweep_pair<true>(wr, sc, q0, nvox, lane, r0, r1, jx, jy, jz, sum, comp);
     }
     if (cur < 2 * na) counted += (unsigned)nvox;  // version 0 (candidate) voxels
   }
@@ -1057,7 +1076,7 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
       carry += __popcll(M);
       const int q = q0 + lane;
       if (q < nvox) {
-        const int idx = __float_as_int(wr.rec[r].x) + q;
+        const int idx = __float_as_int(wr.row[r].rec.x) + q;
         const int prev = atomicCAS(&owner[idx], -1, t);
         if (prev != -1) atomicAdd(overlap, 1);
       }
