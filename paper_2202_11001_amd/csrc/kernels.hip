@@ -131,7 +131,7 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 }
 
 // Parameters of one (tetrahedron, direction) for rasterising the own grid's
-// voxels and mapping them into the other grid.  Lives in wave-private LDS.
+// voxels and mapping them into the other grid.  Lives in LDS.
 constexpr int kMaxSlices = 64;  // slice-table capacity; taller tetrahedra enumerate bounding-box rows
 
 struct RasterTet {
@@ -142,28 +142,30 @@ struct RasterTet {
   int zlo, nz, ylo, ny;  // bounding box (slices, rows)
   int nrows;             // candidate rows
   int sliced;            // 1: candidate rows from the slice table, 0: every bounding-box row
-  int y0[kMaxSlices];    // first candidate row of each slice
-  int rs[kMaxSlices + 1];  // exclusive prefix of candidate rows per slice
+  unsigned short y0[kMaxSlices];      // first candidate row of each slice
+  unsigned short rs[kMaxSlices + 1];  // exclusive prefix of candidate rows per slice (<= 64 * 512)
 };
 
 // Conservative row range [ya, yb] of the cross-section of the tetrahedron
-// (own-grid lattice vertices L) with voxel slice z: the y-extent of the
-// section polygon, whose vertices are the edge / plane intersections, widened
-// by one row on each side against rounding (the exact spans decide the voxels).
-__device__ __forceinline__ void slice_rows(const double L[4][3], int z, int Dy, int& ya, int& yb) {
-  const double Uz = kLat * z + 64.0;
-  double lo = INFINITY, hi = -INFINITY;
+// (own-grid lattice vertices L, integers below 2^17 and hence exact in FP32)
+// with voxel slice z: the y-extent of the section polygon, whose vertices are
+// the edge / plane intersections, widened by one row on each side.  The
+// intersections are computed in FP32 with an approximate reciprocal (error
+// far below one row); the exact spans decide the voxels.
+__device__ __forceinline__ void slice_rows(const float L[4][3], int z, int Dy, int& ya, int& yb) {
+  const float Uz = 128.f * z + 64.f;
+  float lo = INFINITY, hi = -INFINITY;
   for (int a = 0; a < 4; ++a) {
     if (L[a][2] == Uz) {
-      lo = fmin(lo, L[a][1]);
-      hi = fmax(hi, L[a][1]);
+      lo = fminf(lo, L[a][1]);
+      hi = fmaxf(hi, L[a][1]);
     }
     for (int b = a + 1; b < 4; ++b) {
-      const double za = L[a][2], zb = L[b][2];
+      const float za = L[a][2], zb = L[b][2];
       if ((za < Uz && zb > Uz) || (za > Uz && zb < Uz)) {
-        const double y = L[a][1] + (Uz - za) / (zb - za) * (L[b][1] - L[a][1]);
-        lo = fmin(lo, y);
-        hi = fmax(hi, y);
+        const float y = fmaf((Uz - za) * __builtin_amdgcn_rcpf(zb - za), L[b][1] - L[a][1], L[a][1]);
+        lo = fminf(lo, y);
+        hi = fmaxf(hi, y);
       }
     }
   }
@@ -172,29 +174,8 @@ __device__ __forceinline__ void slice_rows(const double L[4][3], int z, int Dy, 
     yb = -1;
     return;
   }
-  ya = max(0, (int)ceil((lo - 64.0) / kLat) - 1);
-  yb = min(Dy - 1, (int)floor((hi - 64.0) / kLat) + 1);
-}
-
-// Number of candidate rows of a tetrahedron (same rule as the slice table).
-__device__ int candidate_rows(const double L[4][3], const int D[3]) {
-  double lo[3], hi[3];
-  for (int c = 0; c < 3; ++c) {
-    lo[c] = fmin(fmin(L[0][c], L[1][c]), fmin(L[2][c], L[3][c]));
-    hi[c] = fmax(fmax(L[0][c], L[1][c]), fmax(L[2][c], L[3][c]));
-  }
-  int za, zb, ya, yb;
-  vox_range(lo[2], hi[2], D[2], za, zb);
-  vox_range(lo[1], hi[1], D[1], ya, yb);
-  const int nz = max(0, zb - za + 1), ny = max(0, yb - ya + 1);
-  if (nz > kMaxSlices) return nz * ny;
-  int rows = 0;
-  for (int k = 0; k < nz; ++k) {
-    int a, b;
-    slice_rows(L, za + k, D[1], a, b);
-    rows += max(0, b - a + 1);
-  }
-  return rows;
+  ya = max(0, (int)ceilf((lo - 64.f) * (1.f / 128.f)) - 1);
+  yb = min(Dy - 1, (int)floorf((hi - 64.f) * (1.f / 128.f)) + 1);
 }
 
 // Fills rt for the tetrahedron with own-grid vertices xo[4][3] and other-grid
@@ -267,20 +248,20 @@ __device__ void setup_raster(const float* xo, const float* xt, const int D[3], i
     // candidate rows of slice zlo + lane, prefix-summed over the slices
     int cnt = 0, ya = 0;
     if (lane < nz) {
-      double L[4][3];
+      float L[4][3];
       for (int q = 0; q < 4; ++q)
-        for (int c = 0; c < 3; ++c) L[q][c] = ((double)xo[3 * q + c] + 0.5) * kLat;
+        for (int c = 0; c < 3; ++c) L[q][c] = (xo[3 * q + c] + 0.5f) * 128.f;
       int yb;
       slice_rows(L, rt.zlo + lane, D[1], ya, yb);
       cnt = max(0, yb - ya + 1);
     }
     const int incl = wave_incl_scan(cnt, lane);
     if (lane < nz) {
-      rt.rs[lane] = incl - cnt;
-      rt.y0[lane] = ya;
+      rt.rs[lane] = (unsigned short)(incl - cnt);
+      rt.y0[lane] = (unsigned short)ya;
     }
     if (lane == 63) {
-      rt.rs[min(nz, kMaxSlices)] = incl;
+      rt.rs[min(nz, kMaxSlices)] = (unsigned short)incl;
       rt.nrows = incl;
       rt.sliced = 1;
     }
@@ -569,7 +550,7 @@ __device__ double guidance_term(const DevProblem& pr, const double L[2][4][3], c
 // ------------------------------------------------------------ LDS layout
 
 struct EvalLayout {
-  size_t tet, xyz, units, part, waves, total;
+  size_t tet, xyz, units, part, waves, rts, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -585,8 +566,10 @@ __host__ __device__ inline EvalLayout eval_layout(int maxA, int nver) {
   o = align16(o + sizeof(int) * (2 * (size_t)nver * maxA + 1));
   L.part = o;  // [nver*2*maxA][kWaves] double
   o = align16(o + sizeof(double) * kWaves * 2 * (size_t)nver * maxA);
-  L.waves = o;  // [kWaves] WaveRows + RasterTet
-  o = align16(o + (sizeof(WaveRows) + sizeof(RasterTet)) * kWaves);
+  L.waves = o;  // [kWaves] WaveRows
+  o = align16(o + sizeof(WaveRows) * kWaves);
+  L.rts = o;  // [nver*2*maxA] RasterTet, one per (version, direction, tetrahedron)
+  o = align16(o + sizeof(RasterTet) * 2 * (size_t)nver * maxA);
   L.total = o;
   return L;
 }
@@ -656,7 +639,7 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   int* s_units = (int*)(smem + Lay.units);
   double* s_part = (double*)(smem + Lay.part);
   WaveRows* s_rows = (WaveRows*)(smem + Lay.waves);
-  RasterTet* s_rt = (RasterTet*)(smem + Lay.waves + sizeof(WaveRows) * kWaves);
+  RasterTet* s_rts = (RasterTet*)(smem + Lay.rts);
   __shared__ unsigned s_flags;
   __shared__ unsigned s_count[kWaves];
 
@@ -693,31 +676,33 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   }
   __syncthreads();
 
-  // unit counts per (version, direction, tetrahedron); direction 0 = target
-  // voxels mapped into the source (forward), 1 = source voxels into the target
+  // set-up of every (version, direction, tetrahedron) entry, one wave per
+  // entry: validity, orientation flag, rasterisation parameters and the
+  // number of 64-row units.  Direction 0 = target voxels mapped into the
+  // source (forward), 1 = source voxels into the target.
   const int nent = nver * 2 * na;
-  for (int e = tid; e < nent; e += kWG) {
+  for (int e = wave; e < nent; e += kWaves) {
     const int v = e / (2 * na), r = e - v * 2 * na, dir = r / na, i = r - dir * na;
     const int own = 1 - dir;
     const float* xyz = s_xyz + (size_t)(v * na + i) * 24;
-    double L[4][3];
-    unsigned bad_own = 0u, bad_oth = 0u;
-    for (int q = 0; q < 4; ++q)
-      for (int c = 0; c < 3; ++c) {
-        bad_own |= lattice_of(xyz[(own * 4 + q) * 3 + c], pr.D[c], L[q][c]);
-        double dummy;
-        bad_oth |= lattice_of(xyz[((1 - own) * 4 + q) * 3 + c], pr.D[c], dummy);
-      }
+    double dummy;
+    const bool bad = lane < 24 && lattice_of(xyz[lane], pr.D[lane % 3], dummy) != 0u;
+    const unsigned long long bm = __ballot(bad);
+    const bool bad_own = (bm >> (own * 12)) & 0xfffull, bad_oth = (bm >> ((1 - own) * 12)) & 0xfffull;
     int nunits = 0;
     if (!bad_own) {
+      double L[4][3];
+      for (int q = 0; q < 4; ++q)
+        for (int c = 0; c < 3; ++c) L[q][c] = ((double)xyz[own * 12 + q * 3 + c] + 0.5) * kLat;
       const double vol = orient(L[0], L[1], L[2], L[3]);
       if (vol > 0.0 && !bad_oth) {
-        nunits = (candidate_rows(L, pr.D) + 63) >> 6;
-      } else if (!(vol > 0.0) && v == 0 && PARTIAL) {
+        setup_raster(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, s_rts[e]);
+        nunits = (s_rts[e].nrows + 63) >> 6;
+      } else if (!(vol > 0.0) && v == 0 && PARTIAL && lane == 0) {
         atomicOr(&s_flags, own == 0 ? DSM_FLAG_INV_MOVING : DSM_FLAG_INV_FIXED);
       }
     }
-    s_units[e] = nunits;
+    if (lane == 0) s_units[e] = nunits;
   }
   for (int e = tid; e < nent * kWaves; e += kWG) s_part[e] = 0.0;
   __syncthreads();
@@ -733,7 +718,7 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   const int own_base = pr.exy + pr.ex + 1;  // element of voxel (0, 0, 0)
   const __amdgpu_buffer_rsrc_t rs[2] = {image_rsrc(pr.img[0], pr.img_bytes), image_rsrc(pr.img[1], pr.img_bytes)};
   WaveRows& wr = s_rows[wave];
-  RasterTet& rt = s_rt[wave];
+  const RasterTet* rtp = s_rts;
   int cur = -1;
   float jx = 0.f, jy = 0.f, jz = 0.f;
   unsigned counted = 0u;
@@ -751,20 +736,18 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
         sum = comp = 0.f;
       }
       cur = e;
-      const int v = e / (2 * na), r = e - v * 2 * na, dir = r / na, i = r - dir * na;
+      const int r = e - (e / (2 * na)) * 2 * na, dir = r / na;
       const int own = 1 - dir;
-      const float* xyz = s_xyz + (size_t)(v * na + i) * 24;
-      wave_sync();
-      setup_raster(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, rt);
-      jx = uniformf((float)rt.J[0][0]);
-      jy = uniformf((float)rt.J[1][0]);
-      jz = uniformf((float)rt.J[2][0]);
+      rtp = s_rts + e;
+      jx = uniformf((float)rtp->J[0][0]);
+      jy = uniformf((float)rtp->J[1][0]);
+      jz = uniformf((float)rtp->J[2][0]);
       sc.own = own ? rs[1] : rs[0];
       sc.oth = own ? rs[0] : rs[1];
     }
     const int b = u - uniform(s_units[cur]);
     int my_start;
-    const int nvox = uniform(build_rows(rt, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
+    const int nvox = uniform(build_rows(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
     int carry = 0;  // non-empty rows that start before the current chunk
     for (int q0 = 0; q0 < nvox; q0 += 128) {
       // voxels q0 + lane and q0 + 64 + lane: rows starting in this pair of
