@@ -148,10 +148,12 @@ struct RasterTet {
 
 // Conservative row range [ya, yb] of the cross-section of the tetrahedron
 // (own-grid lattice vertices L, integers below 2^17 and hence exact in FP32)
-// with voxel slice z: the y-extent of the section polygon, whose vertices are
-// the edge / plane intersections, widened by one row on each side.  The
-// intersections are computed in FP32 with an approximate reciprocal (error
-// far below one row); the exact spans decide the voxels.
+// with voxel slice z: the rows whose centres lie in the y-extent of the
+// section polygon (every voxel of the closed tetrahedron in that slice does),
+// whose vertices are the edge / plane intersections.  They are computed in
+// FP32 with an approximate reciprocal, with an error of a few 1e-3 lattice
+// units at most; the extent is widened by 1/2 lattice unit against it.  The
+// exact spans decide the voxels.
 __device__ __forceinline__ void slice_rows(const float L[4][3], int z, int Dy, int& ya, int& yb) {
   const float Uz = 128.f * z + 64.f;
   float lo = INFINITY, hi = -INFINITY;
@@ -174,8 +176,8 @@ __device__ __forceinline__ void slice_rows(const float L[4][3], int z, int Dy, i
     yb = -1;
     return;
   }
-  ya = max(0, (int)ceilf((lo - 64.f) * (1.f / 128.f)) - 1);
-  yb = min(Dy - 1, (int)floorf((hi - 64.f) * (1.f / 128.f)) + 1);
+  ya = max(0, (int)ceilf((lo - 64.5f) * (1.f / 128.f)));
+  yb = min(Dy - 1, (int)floorf((hi - 63.5f) * (1.f / 128.f)));
 }
 
 // Fills rt for the tetrahedron with own-grid vertices xo[4][3] and other-grid
