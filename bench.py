@@ -249,6 +249,72 @@ def surrogate_run(gp, X, G, train_generations, name):
     print(json.dumps(res), flush=True)
 
 
+def uneven_batch(steps=3, warmup=1):
+    """Several registration problems of uneven size in one fused launch per
+    pyramid level: the 12 problems of workloads.UNEVEN_PROBLEMS at the 2x
+    box-averaged level and at full resolution (population handed off by
+    x -> 2x + 0.5); per level, all single-point FOS elements of every
+    solution.  Each problem's image row pitch is autotuned first."""
+    import torch
+    from paper_2202_11001_amd import dsm
+    from paper_2202_11001_amd import workloads as W
+    dev = torch.device("cuda:0")
+    n = len(W.UNEVEN_PROBLEMS)
+    res = {"problems": n, "levels": []}
+    handoff = {}
+    for level in (0, 1):
+        t0 = time.perf_counter()
+        ws = W.uneven(level=level)
+        jobs, probs, samples = [], [], 0
+        for i, w in enumerate(ws):
+            gp = dsm.Problem.from_workload(w)
+
+            def reject(X, gp=gp):
+                return gp.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0
+
+            X = w.population(reject=reject) if level == 0 else W.upsample_population(handoff[i])
+            if level == 0:
+                handoff[i] = X
+            off, pts = w.fos()
+            cand = w.candidates(X, off, pts)
+            Xd = torch.from_numpy(X).to(dev)
+            offd, ptsd, cd = (torch.from_numpy(a).to(dev) for a in (off, pts, cand))
+            cache = torch.empty((X.shape[0], gp.T, 3), dtype=torch.float64, device=dev)
+            gp.eval_full(Xd, tet_terms=cache)
+            gp.autotune_pitch(Xd, offd, ptsd, cd, tet_terms_in=cache)
+            probs.append(gp)
+            jobs.append(dict(problem=gp, X=Xd, fos_off=offd, fos_pts=ptsd, cand=cd, tet_terms_in=cache))
+        log(f"uneven level {level}: {n} problems set up in {time.perf_counter() - t0:.1f} s")
+        batch = dsm.Batch(max_jobs=n)
+        outs = batch.eval_partial(jobs)
+        torch.cuda.synchronize()
+        samples = int(sum(int(o[3].to(torch.int64).sum().item()) for o in outs))
+        evals = sum(j["X"].shape[0] * (j["fos_off"].shape[0] - 1) for j in jobs)
+        flagged = int(sum(int((o[2] != 0).sum().item()) for o in outs))
+        for _ in range(warmup):
+            batch.eval_partial(jobs)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for k in range(steps):
+            batch.eval_partial(jobs)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+        log(f"uneven level {level}: {evals} partial evaluations, {samples} samples, {flagged} flagged, {ms:.2f} ms "
+            f"per fused launch")
+        res["levels"].append({"level": level, "partial_evals": evals, "voxel_samples": samples, "ms": ms,
+                              "partial_evals_per_s": evals / (ms / 1e3), "voxel_samples_per_s": samples / (ms / 1e3),
+                              "algorithmic_GBps": samples * BYTES_PER_SAMPLE / (ms / 1e3) / 1e9})
+        del batch, jobs, probs
+    tot_e = sum(l["partial_evals"] for l in res["levels"])
+    tot_ms = sum(l["ms"] for l in res["levels"])
+    res["total"] = {"partial_evals": tot_e, "voxel_samples": sum(l["voxel_samples"] for l in res["levels"]),
+                    "ms": tot_ms, "partial_evals_per_s": tot_e / (tot_ms / 1e3)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,12 +326,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
     ap.add_argument("--no-screen", action="store_true", help="skip the surrogate-screened step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch")
+    ap.add_argument("--uneven", action="store_true",
+                    help="12 problems of uneven size in one fused launch per pyramid level (reported separately)")
     ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
                     help="plain vs surrogate-screened optimiser runs of G generations (hypervolume protocol)")
     ap.add_argument("--train-generations", type=int, default=30)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.uneven:
+        uneven_batch()
         return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_screen = 2, 0, True, True
