@@ -711,3 +711,37 @@ void ref_normalisers(const ref_problem *p, double *out) {
   out[1] = norm_def(p);
   out[2] = norm_guid(p);
 }
+
+/* ------------------------------------------------------------------ refinement
+ * Sec. 2.4 (grid multi-resolution): every cube of both grids is split into 8
+ * cubes by adding a point in the middle of each cube edge, in the middle of
+ * each face and at the cube's centre.  A grid of n points per axis becomes one
+ * of 2n-1 points per axis: fine point (I,J,K) is the mean of the coarse points
+ * (i,j,k) with i in {floor(I/2), ceil(I/2)} (and likewise for j, k), i.e. of 1
+ * (a coarse point), 2 (edge middle), 4 (face middle) or 8 (cube centre) points.
+ * Readings: the face middle and the centre are the means of the corners (the
+ * faces of a deformed cube need not be planar); the mean is rounded to the
+ * 1/128-voxel lattice, half to even.  Xc [S][2][Pc][3] -> Xf [S][2][Pf][3]. */
+void ref_refine(const int *nc, int S, const float *Xc, float *Xf) {
+  const int nf[3] = {2 * nc[0] - 1, 2 * nc[1] - 1, 2 * nc[2] - 1};
+  const long Pc = (long)nc[0] * nc[1] * nc[2], Pf = (long)nf[0] * nf[1] * nf[2];
+  for (int s = 0; s < S; ++s)
+    for (int g = 0; g < 2; ++g)
+      for (int K = 0; K < nf[2]; ++K)
+        for (int J = 0; J < nf[1]; ++J)
+          for (int I = 0; I < nf[0]; ++I) {
+            const int is[2] = {I / 2, (I + 1) / 2}, js[2] = {J / 2, (J + 1) / 2}, ks[2] = {K / 2, (K + 1) / 2};
+            double sum[3] = {0, 0, 0};
+            int cnt = 0;
+            /* the distinct coarse corners: index pairs collapse where I, J or K is even */
+            for (int a = 0; a < (I % 2 ? 2 : 1); ++a)
+              for (int b = 0; b < (J % 2 ? 2 : 1); ++b)
+                for (int c = 0; c < (K % 2 ? 2 : 1); ++c) {
+                  const float *x = Xc + (((long)s * 2 + g) * Pc + pidx(nc, is[a], js[b], ks[c])) * 3;
+                  for (int d = 0; d < 3; ++d) sum[d] += ((double)x[d] + 0.5) * 128.0; /* lattice units */
+                  ++cnt;
+                }
+            float *y = Xf + (((long)s * 2 + g) * Pf + pidx(nf, I, J, K)) * 3;
+            for (int d = 0; d < 3; ++d) y[d] = (float)(nearbyint(sum[d] / cnt) / 128.0 - 0.5);
+          }
+}

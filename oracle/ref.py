@@ -69,12 +69,26 @@ def lib():
         L.ref_tet_voxels.argtypes = [P, P, C.c_int, P, C.c_int]
         L.ref_trilinear.restype = C.c_double
         L.ref_trilinear.argtypes = [P, C.c_int, P, C.c_int]
+        L.ref_refine.restype = None
+        L.ref_refine.argtypes = [P, C.c_int, P, P]
         _lib = L
     return _lib
 
 
 def _p(a):
     return a.ctypes.data if a is not None else None
+
+
+def refine(mesh_coarse, Xc):
+    """Sec. 2.4 grid refinement of a population Xc [S][2][Pc][3] on a mesh of
+    mesh_coarse points per axis -> [S][2][Pf][3] on 2n-1 points per axis."""
+    nc = np.ascontiguousarray(mesh_coarse, dtype=np.int32)
+    Xc = np.ascontiguousarray(Xc, dtype=np.float32)
+    S = Xc.shape[0]
+    Pf = int(np.prod(2 * nc - 1))
+    Xf = np.zeros((S, 2, Pf, 3), np.float32)
+    lib().ref_refine(_p(nc), S, _p(Xc), _p(Xf))
+    return Xf
 
 
 def orient3d(a, b, c, d) -> float:
