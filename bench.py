@@ -315,6 +315,63 @@ def uneven_batch(steps=3, warmup=1):
     print(json.dumps(res), flush=True)
 
 
+def multires(G1, G2, S1=256, S2=512, coarse_mesh=(6, 6, 4)):
+    """Sec. 2.4 multi-resolution run on the 512x512x100 pair: G1 generations on
+    a coarse mesh (population S1), then a random sample of S2 solutions of its
+    approximation set refined to 2n-1 points per axis and G2 generations there
+    (the paper's scheme: 6^3 -> 11^3 grids, populations 250 -> 500).
+    Generations replay captured HIP graphs."""
+    import torch
+    from paper_2202_11001_amd import dsm
+    from paper_2202_11001_amd import optimizer as O
+    from paper_2202_11001_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wc = W.clinical(mesh=coarse_mesh, S=S1)
+    gpc = dsm.Problem.from_workload(wc)
+    X = wc.population(reject=lambda X: gpc.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0)
+    fine_mesh = tuple(2 * n - 1 for n in coarse_mesh)
+    wf = W.clinical(mesh=fine_mesh, S=S2)
+    gpf = dsm.Problem.from_workload(wf)
+    t0 = time.perf_counter()
+    oc = O.Optimiser(gpc, torch.from_numpy(X).to(dev), sigma=1.0, seed=21, graph=True, keep_solutions=True)
+    hv_c = [oc.hypervolume()]
+    for g in range(G1):
+        oc.generation()
+        hv_c.append(oc.hypervolume())
+        if (g + 1) % 20 == 0:
+            log(f"coarse {coarse_mesh} gen {g + 1}: hv {hv_c[-1]:.6g} archive {len(oc.archive)}")
+    torch.cuda.synchronize()
+    t_coarse = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Xf, rejected = O.seed_finer(oc, gpf, S2, seed=22)
+    torch.cuda.synchronize()
+    t_seed = time.perf_counter() - t0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    dsm.refine_population(coarse_mesh, oc.X)
+    ev[1].record()
+    torch.cuda.synchronize()
+    refine_ms = ev[0].elapsed_time(ev[1])
+    log(f"seeded {S2} refined solutions on {fine_mesh} ({rejected} draws rejected) in {t_seed:.2f} s; "
+        f"refining {S1} solutions takes {refine_ms:.3f} ms")
+    t0 = time.perf_counter()
+    of = O.Optimiser(gpf, Xf, sigma=0.5, seed=23, graph=True)
+    hv_f = [of.hypervolume()]
+    for g in range(G2):
+        of.generation()
+        hv_f.append(of.hypervolume())
+        if (g + 1) % 20 == 0:
+            log(f"fine {fine_mesh} gen {g + 1}: hv {hv_f[-1]:.6g} archive {len(of.archive)}")
+    torch.cuda.synchronize()
+    t_fine = time.perf_counter() - t0
+    res = {"workload": wf.name, "coarse": {"mesh": coarse_mesh, "S": S1, "generations": G1, "seconds": t_coarse,
+                                            "hv_first": hv_c[0], "hv_last": hv_c[-1], "archive": len(oc.archive)},
+           "seed": {"S": S2, "rejected_draws": rejected, "seconds": t_seed, "refine_ms": refine_ms},
+           "fine": {"mesh": fine_mesh, "S": S2, "generations": G2, "seconds": t_fine, "hv_first": hv_f[0],
+                    "hv_last": hv_f[-1], "archive": len(of.archive)}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +383,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
     ap.add_argument("--no-screen", action="store_true", help="skip the surrogate-screened step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch")
+    ap.add_argument("--multires", type=int, nargs=2, default=None, metavar=("G1", "G2"),
+                    help="multi-resolution run: G1 coarse then G2 fine generations (reported separately)")
     ap.add_argument("--uneven", action="store_true",
                     help="12 problems of uneven size in one fused launch per pyramid level (reported separately)")
     ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
@@ -337,6 +396,9 @@ def main():
         return
     if args.uneven:
         uneven_batch()
+        return
+    if args.multires:
+        multires(*args.multires)
         return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_screen = 2, 0, True, True

@@ -346,6 +346,17 @@ dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int3
                                  float sigma, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
                                  void* stream);
 
+/* Sec. 2.4 grid refinement for multi-resolution runs: each cube of both grids
+ * is split into 8 cubes by points at the middle of every cube edge, the middle
+ * of every face and the cube centre (face middles and centres are means of the
+ * corners; a deformed face need not be planar), rounded to the 1/128-voxel
+ * lattice half to even.  Xc dev [S][2][Pc][3] on a mesh of mesh_coarse host [3]
+ * points per axis -> Xf dev [S][2][Pf][3] on (2 nx - 1, 2 ny - 1, 2 nz - 1)
+ * points.  Feasibility of the result is not assumed: check it with
+ * dsm_fold_check on the finer problem.  Errors: DSM_ERR_ARG (null pointers,
+ * S < 0), DSM_ERR_DOMAIN (mesh outside [2, 129] per axis). */
+dsm_status dsm_refine_population(const int32_t* mesh_coarse, int32_t S, const float* Xc, float* Xf, void* stream);
+
 /* Sec. 2.2: accepts the partial changes of one evaluated batch of single-point
  * elements whose affected tetrahedra are pairwise disjoint (e.g. points of one
  * index-parity class) and applies them together.  A change is accepted iff its

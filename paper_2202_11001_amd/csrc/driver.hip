@@ -109,6 +109,31 @@ __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, con
   }
 }
 
+// Sec. 2.4 grid refinement: fine point (I, J, K) of a 2n-1 grid is the mean of
+// the coarse points whose indices are floor or ceil of (I/2, J/2, K/2): a
+// coarse point, an edge middle, a face middle or a cube centre.  The mean of
+// lattice integers (1, 2, 4 or 8 of them) is exact in FP64 and is rounded
+// to the lattice half to even.  One thread per (solution, grid, fine point).
+__global__ void k_refine(int nx, int ny, int nz, int S, const float* __restrict__ Xc, float* __restrict__ Xf) {
+  const int fx = 2 * nx - 1, fy = 2 * ny - 1, fz = 2 * nz - 1;
+  const int64_t Pc = (int64_t)nx * ny * nz, Pf = (int64_t)fx * fy * fz;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)S * 2 * Pf) return;
+  const int64_t sg = e / Pf;
+  const int f = (int)(e - sg * Pf);
+  const int I = f % fx, J = (f / fx) % fy, K = f / (fx * fy);
+  const int i0 = I >> 1, i1 = (I + 1) >> 1, j0 = J >> 1, j1 = (J + 1) >> 1, k0 = K >> 1, k1 = (K + 1) >> 1;
+  const float* base = Xc + sg * Pc * 3;
+  double u[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 8; ++c) {  // the 8 index combinations; repeated corners weigh equally
+    const int i = (c & 1) ? i1 : i0, j = (c & 2) ? j1 : j0, k = (c & 4) ? k1 : k0;
+    const float* x = base + ((int64_t)(k * ny + j) * nx + i) * 3;
+    for (int d = 0; d < 3; ++d) u[d] += ((double)x[d] + 0.5) * kLat;
+  }
+  float* y = Xf + e * 3;
+  for (int d = 0; d < 3; ++d) y[d] = (float)(rint(u[d] * 0.125) / kLat - 0.5);
+}
+
 }  // namespace
 }  // namespace dsm
 
@@ -125,6 +150,16 @@ dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int3
   k_sample<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(p->dev, S, X, F, fos_pts, K, sigma, seed,
                                                                        counter, (const unsigned long long*)counter_dev,
                                                                        cand);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_refine_population(const int32_t* mesh_coarse, int32_t S, const float* Xc, float* Xf, void* stream) {
+  if (!mesh_coarse || S < 0 || (S > 0 && (!Xc || !Xf))) return DSM_ERR_ARG;
+  const int nx = mesh_coarse[0], ny = mesh_coarse[1], nz = mesh_coarse[2];
+  if (nx < 2 || ny < 2 || nz < 2 || nx > 129 || ny > 129 || nz > 129) return DSM_ERR_DOMAIN;
+  const int64_t n = (int64_t)S * 2 * (2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1);
+  if (n == 0) return DSM_OK;
+  k_refine<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(nx, ny, nz, S, Xc, Xf);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 

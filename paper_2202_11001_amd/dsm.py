@@ -86,6 +86,7 @@ def lib():
             "dsm_batch_destroy": ([V], I),
             "dsm_eval_partial_batch": ([V, I, V, V], I),
             "dsm_problem_set_pitch": ([V, I], I),
+            "dsm_refine_population": ([V, I, V, V, V], I),
             "dsm_autotune_pitch": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
             "dsm_surrogate_create": ([V, V], I),
             "dsm_surrogate_destroy": ([V], I),
@@ -124,6 +125,19 @@ def _check(st):
 
 def _np_ptr(a):
     return a.ctypes.data if a is not None and a.size else None
+
+
+def refine_population(mesh_coarse, Xc, out=None, stream=None):
+    """Sec. 2.4 refinement of a device population Xc [S][2][Pc][3] to the mesh of
+    2n-1 points per axis: [S][2][Pf][3] (``dsm_refine_population``)."""
+    torch = _torch()
+    m = np.ascontiguousarray(mesh_coarse, dtype=np.int32)
+    S = Xc.shape[0]
+    Pf = int(np.prod(2 * m - 1))
+    if out is None:
+        out = torch.empty((S, 2, Pf, 3), dtype=torch.float32, device=Xc.device)
+    _check(lib().dsm_refine_population(_np_ptr(m), S, _dptr(Xc), _dptr(out), _stream(stream)))
+    return out
 
 
 def mesh_topology(mesh, dims=None):

@@ -62,6 +62,24 @@ def merge_archive(archive, new):
     return out[np.lexsort(out.T[::-1])]
 
 
+def merge_archive_with(archive, archive_X, new, new_X):
+    """merge_archive that carries a payload row (e.g. the solution) with every
+    objective vector; among equal vectors the archived one is kept."""
+    pts = np.concatenate([np.asarray(archive, np.float64).reshape(-1, 3), np.asarray(new, np.float64)])
+    pay = new_X if len(archive) == 0 else np.concatenate([archive_X, new_X])
+    n = len(pts)
+    keep = np.ones(n, dtype=bool)
+    for b in range(0, n, 1024):
+        blk = pts[b:b + 1024]
+        le = np.all(pts[None, :, :] <= blk[:, None, :], axis=2)
+        lt = np.any(pts[None, :, :] < blk[:, None, :], axis=2)
+        eq = np.all(pts[None, :, :] == blk[:, None, :], axis=2)
+        earlier = np.arange(n)[None, :] < np.arange(b, b + len(blk))[:, None]
+        keep[b:b + 1024] = ~np.any(le & lt, axis=1) & ~np.any(eq & earlier, axis=1)
+    order = np.lexsort(pts[keep].T[::-1])
+    return pts[keep][order], pay[keep][order]
+
+
 def hypervolume(points, ref):
     """Exact 3-D hypervolume dominated by `points` and bounded by `ref`
     (minimisation): slices along the third objective, each a 2-D union area."""
@@ -103,7 +121,8 @@ class Optimiser:
     fixed-capacity device buffer padded with +inf rows, so a replay needs no
     host work.  Eager and graph generations give bit-identical results."""
 
-    def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14):
+    def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
+                 keep_solutions=False):
         import torch
         self.torch = torch
         self.p = problem
@@ -121,7 +140,13 @@ class Optimiser:
         if int((flags != 0).sum().item()):
             raise ValueError("initial population is infeasible")
         self.obj = obj
-        self.archive = nondominated(obj.cpu().numpy())
+        self.keep_solutions = bool(keep_solutions)
+        self.archive_X = None  # with keep_solutions: the solution of every archive row (host)
+        if self.keep_solutions:
+            self.archive, self.archive_X = merge_archive_with(np.zeros((0, 3)), None, obj.cpu().numpy(),
+                                                              self.X.cpu().numpy())
+        else:
+            self.archive = nondominated(obj.cpu().numpy())
         self.ref = 1.1 * obj.cpu().numpy().max(axis=0)
         self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
         # sampler counter: generation g uses counters 8 g + 1 ... 8 g + 8
@@ -192,7 +217,11 @@ class Optimiser:
             outs = self._steps(surrogate)
         n_exact = sum(self.S * acc.shape[1] if mask is None else int(mask.sum().item()) for mask, acc, *_ in outs)
         n_acc = sum(int(acc.sum().item()) for _, acc, *_ in outs)
-        self.archive = merge_archive(self.archive, self.obj.cpu().numpy())
+        if self.keep_solutions:
+            self.archive, self.archive_X = merge_archive_with(self.archive, self.archive_X, self.obj.cpu().numpy(),
+                                                              self.X.cpu().numpy())
+        else:
+            self.archive = merge_archive(self.archive, self.obj.cpu().numpy())
         return n_exact, n_acc
 
     def hypervolume(self):
@@ -245,3 +274,31 @@ def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_genera
         if target_hv is not None and log.hypervolume[-1] >= target_hv:
             break
     return log, opt, sur
+
+
+def seed_finer(opt, problem_fine, S_fine, seed=0):
+    """Sec. 2.4: a random sample (with replacement when the approximation set is
+    smaller) of S_fine solutions of the coarse run's approximation set, refined
+    to the finer mesh on the GPU.  Refined solutions that fail the finer
+    problem's constraints are replaced by further draws; returns the device
+    population and the number of draws rejected."""
+    import torch
+    if opt.archive_X is None:
+        raise ValueError("the coarse optimiser must keep its archive solutions (keep_solutions=True)")
+    rng = np.random.default_rng(seed)
+    pool = opt.archive_X
+    dev = opt.X.device
+    out, rejected = [], 0
+    need = S_fine
+    for _ in range(64):
+        idx = rng.choice(len(pool), size=need, replace=len(pool) < need)
+        Xf = dsm.refine_population(opt.p.mesh, torch.from_numpy(np.ascontiguousarray(pool[idx])).to(dev))
+        ok = (problem_fine.fold_check(Xf) == 0).cpu().numpy()
+        rejected += int((~ok).sum())
+        out.append(Xf[torch.from_numpy(ok).to(dev)])
+        need = S_fine - sum(x.shape[0] for x in out)
+        if need == 0:
+            break
+    if need:
+        raise RuntimeError("could not draw enough feasible refined solutions")
+    return torch.cat(out)[:S_fine].contiguous(), rejected

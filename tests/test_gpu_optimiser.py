@@ -168,3 +168,32 @@ def test_graph_generations_match_eager():
         assert re_ == rg, (gen, re_, rg)
         for a, b in zip(_state(oe), _state(og)):
             np.testing.assert_array_equal(a, b)
+
+
+def test_multiresolution_seeding():
+    """Sec. 2.4: a coarse run keeps its approximation set's solutions; a random
+    sample of them, refined on the GPU, starts a feasible finer run."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp, S=32)
+    gp = dsm.Problem.from_workload(w, max_solutions=64)
+    _say("coarse run keeping archive solutions")
+    oc = O.Optimiser(gp, _t(X), sigma=1.0, seed=2, keep_solutions=True)
+    for _ in range(3):
+        oc.generation()
+    assert oc.archive_X.shape == (len(oc.archive), 2, w.P, 3)
+    # every archived solution reproduces its archived objective vector
+    obj, fl = gp.eval_full(_t(oc.archive_X))
+    np.testing.assert_allclose(obj.cpu().numpy(), oc.archive, rtol=1e-6, atol=1e-12)
+    nf = tuple(2 * n - 1 for n in w.mesh)
+    wf = W.Workload(w.name + "-fine", w.moving, w.fixed, nf, w.spacing, w.tau, 64, w.sigma_pop, w.sigma_cand,
+                    w.seed_pop, w.seed_cand, w.guid_moving, w.guid_fixed, w.corr_moving, w.corr_fixed)
+    gpf = dsm.Problem.from_workload(wf, max_solutions=64)
+    Xf, rejected = O.seed_finer(oc, gpf, 64, seed=5)
+    assert Xf.shape == (64, 2, wf.P, 3)
+    _say(f"fine run from the refined sample ({rejected} draws rejected)")
+    of = O.Optimiser(gpf, Xf, sigma=0.5, seed=3)
+    hv0 = of.hypervolume()
+    for _ in range(2):
+        of.generation()
+    assert of.hypervolume() > hv0

@@ -60,3 +60,14 @@ def test_merge_archive_equals_filtering_the_union():
         merged = O.merge_archive(arch, new)
         np.testing.assert_array_equal(merged, O.nondominated(np.concatenate([arch, new])))
         arch = merged
+
+
+def test_merge_archive_with_payload_matches_plain_merge():
+    rng = np.random.default_rng(9)
+    pts = np.round(rng.random((200, 3)), 2)
+    pay = np.arange(200)[:, None].astype(np.float64)
+    arch, ap = O.merge_archive_with(np.zeros((0, 3)), None, pts[:80], pay[:80])
+    arch, ap = O.merge_archive_with(arch, ap, pts[80:], pay[80:])
+    np.testing.assert_array_equal(arch, O.nondominated(pts))
+    for row, p in zip(arch, ap[:, 0].astype(int)):
+        np.testing.assert_array_equal(pts[p], row)  # every kept row carries its own payload
