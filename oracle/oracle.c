@@ -745,3 +745,153 @@ void ref_refine(const int *nc, int S, const float *Xc, float *Xf) {
             for (int d = 0; d < 3; ++d) y[d] = (float)(nearbyint(sum[d] / cnt) / 128.0 - 0.5);
           }
 }
+
+/* ------------------------------------------------------- literal fold test
+ * Sec. 2.3.4 as the paper states it (an oracle-only comparison with the exact
+ * orientation test the library uses): an interior grid point must lie inside
+ * the closed surface formed by the faces opposite it of its surrounding
+ * tetrahedra, tested by casting a ray and counting triangle crossings; a point
+ * on one border plane must lie inside the polygon formed, in that plane, by
+ * the edges opposite it of the border faces of its surrounding tetrahedra,
+ * tested by casting a ray in the plane and counting segment crossings.
+ * Readings: points on a border edge must lie strictly between their two
+ * neighbours on that edge; corners are fixed.  Arithmetic is exact: lattice
+ * integers and 128-bit determinants; a ray that meets an edge or vertex
+ * exactly is replaced by another direction.  Returns, per solution and grid,
+ * the number of points that violate the test. */
+typedef __int128 i128;
+
+static i128 orient_i(const long a[3], const long b[3], const long c[3], const long d[3]) {
+  const i128 bx = b[0] - a[0], by = b[1] - a[1], bz = b[2] - a[2];
+  const i128 cx = c[0] - a[0], cy = c[1] - a[1], cz = c[2] - a[2];
+  const i128 dx = d[0] - a[0], dy = d[1] - a[1], dz = d[2] - a[2];
+  return bx * (cy * dz - cz * dy) - by * (cx * dz - cz * dx) + bz * (cx * dy - cy * dx);
+}
+
+static int sgn(i128 v) { return v > 0 ? 1 : (v < 0 ? -1 : 0); }
+
+/* does segment PQ cross triangle ABC?  returns 1 / 0, or -1 when degenerate */
+static int seg_tri(const long P[3], const long Q[3], const long A[3], const long B[3], const long C[3]) {
+  const int sp = sgn(orient_i(A, B, C, P)), sq = sgn(orient_i(A, B, C, Q));
+  if (sp == 0 || sq == 0) return -1;
+  if (sp == sq) return 0;
+  const int s1 = sgn(orient_i(P, Q, A, B)), s2 = sgn(orient_i(P, Q, B, C)), s3 = sgn(orient_i(P, Q, C, A));
+  if (s1 == 0 || s2 == 0 || s3 == 0) return -1;
+  return (s1 == s2 && s2 == s3) ? 1 : 0;
+}
+
+/* 2-D: does segment PQ cross segment AB (coordinates u, v)? 1 / 0 / -1 degenerate */
+static i128 orient2(const long a[2], const long b[2], const long c[2]) {
+  return (i128)(b[0] - a[0]) * (c[1] - a[1]) - (i128)(b[1] - a[1]) * (c[0] - a[0]);
+}
+static int seg_seg(const long P[2], const long Q[2], const long A[2], const long B[2]) {
+  const int a = sgn(orient2(P, Q, A)), b = sgn(orient2(P, Q, B));
+  const int c = sgn(orient2(A, B, P)), d = sgn(orient2(A, B, Q));
+  if (a == 0 || b == 0 || c == 0 || d == 0) return -1;
+  return (a != b && c != d) ? 1 : 0;
+}
+
+static void lattice_pt(const float *Xg, int v, long out[3]) {
+  for (int d = 0; d < 3; ++d) out[d] = (long)nearbyint(((double)Xg[3 * v + d] + 0.5) * 128.0);
+}
+
+static const long RAYS[6][3] = {{1L << 22, 1009, 2003}, {3001, 1L << 22, 4007}, {5003, 6007, 1L << 22},
+                               {-(1L << 22), 7001, -8009}, {9001, -(1L << 22), 1013}, {-1019, 1021, -(1L << 22)}};
+
+static int inside_link3(const ref_problem *p, const float *Xg, int v) {
+  long P[3];
+  lattice_pt(Xg, v, P);
+  for (int r = 0; r < 6; ++r) {
+    long Q[3] = {P[0] + RAYS[r][0], P[1] + RAYS[r][1], P[2] + RAYS[r][2]};
+    int cross = 0, degenerate = 0;
+    for (int j = p->star_off[v]; j < p->star_off[v + 1] && !degenerate; ++j) {
+      const int *t = p->tet + 4 * p->star[j];
+      long F[3][3];
+      int m = 0;
+      for (int q = 0; q < 4; ++q)
+        if (t[q] != v) lattice_pt(Xg, t[q], F[m++]);
+      const int hit = seg_tri(P, Q, F[0], F[1], F[2]);
+      if (hit < 0)
+        degenerate = 1;
+      else
+        cross += hit;
+    }
+    if (!degenerate) return cross & 1;
+  }
+  return 0; /* every direction degenerate: treated as a violation */
+}
+
+/* point on border plane `axis`: polygon of the in-plane edges opposite v */
+static int inside_link2(const ref_problem *p, const float *Xg, int v, int axis) {
+  const int ua = axis == 0 ? 1 : 0, va = axis == 2 ? 1 : 2;
+  long P3[3];
+  lattice_pt(Xg, v, P3);
+  const long P[2] = {P3[ua], P3[va]};
+  for (int r = 0; r < 6; ++r) {
+    const long Q[2] = {P[0] + RAYS[r][0] + RAYS[r][2], P[1] + RAYS[r][1] - RAYS[r][2]};
+    int cross = 0, degenerate = 0;
+    for (int j = p->star_off[v]; j < p->star_off[v + 1] && !degenerate; ++j) {
+      const int *t = p->tet + 4 * p->star[j];
+      long E[2][3];
+      int m = 0, on = 1;
+      for (int q = 0; q < 4; ++q) {
+        if (t[q] == v) continue;
+        long w[3];
+        lattice_pt(Xg, t[q], w);
+        if (w[axis] != P3[axis]) {
+          on = 0;
+          continue;
+        }
+        if (m < 2) memcpy(E[m], w, sizeof(w));
+        ++m;
+      }
+      if (!on && m != 2) continue; /* no border face with v in this tetrahedron */
+      if (m != 2) continue;
+      const long A[2] = {E[0][ua], E[0][va]}, B[2] = {E[1][ua], E[1][va]};
+      const int hit = seg_seg(P, Q, A, B);
+      if (hit < 0)
+        degenerate = 1;
+      else
+        cross += hit;
+    }
+    if (!degenerate) return cross & 1;
+  }
+  return 0;
+}
+
+void ref_literal_fold_check(const ref_problem *p, int S, const float *X, int *violations) {
+  for (int s = 0; s < S; ++s)
+    for (int g = 0; g < 2; ++g) {
+      const float *Xg = X + ((long)s * 2 + g) * p->P * 3;
+      int bad = 0;
+      for (int k = 0; k < p->n[2]; ++k)
+        for (int j = 0; j < p->n[1]; ++j)
+          for (int i = 0; i < p->n[0]; ++i) {
+            const int v = pidx(p->n, i, j, k), idx[3] = {i, j, k};
+            int nb = 0, axis = -1, free_axis = -1;
+            for (int d = 0; d < 3; ++d) {
+              if (idx[d] == 0 || idx[d] == p->n[d] - 1) {
+                ++nb;
+                axis = d;
+              } else {
+                free_axis = d;
+              }
+            }
+            int ok = 1;
+            if (nb == 0) {
+              ok = inside_link3(p, Xg, v);
+            } else if (nb == 1) {
+              ok = inside_link2(p, Xg, v, axis);
+            } else if (nb == 2) { /* border edge: strictly between its two neighbours on the edge */
+              int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+              lo[free_axis] -= 1;
+              hi[free_axis] += 1;
+              const double x = Xg[3 * v + free_axis];
+              ok = Xg[3 * pidx(p->n, lo[0], lo[1], lo[2]) + free_axis] < x &&
+                   x < Xg[3 * pidx(p->n, hi[0], hi[1], hi[2]) + free_axis];
+            }
+            bad += !ok;
+          }
+      violations[s * 2 + g] = bad;
+    }
+}

@@ -71,6 +71,8 @@ def lib():
         L.ref_trilinear.argtypes = [P, C.c_int, P, C.c_int]
         L.ref_refine.restype = None
         L.ref_refine.argtypes = [P, C.c_int, P, P]
+        L.ref_literal_fold_check.restype = None
+        L.ref_literal_fold_check.argtypes = [P, C.c_int, P, P]
         _lib = L
     return _lib
 
@@ -183,6 +185,14 @@ class Problem:
         fb = np.zeros(S, dtype=np.int32)
         lib().ref_fold_check(self._h, S, _p(X), _p(flags), _p(fb))
         return flags, fb
+
+    def literal_fold_check(self, X):
+        """Sec. 2.3.4 as stated (points inside the surface / polygon of their
+        surrounding faces, by ray casting): violating points per [S][grid]."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.zeros((X.shape[0], 2), np.int32)
+        lib().ref_literal_fold_check(self._h, X.shape[0], _p(X), _p(out))
+        return out
 
     def eval_full(self, X, want_terms=False):
         X = np.ascontiguousarray(X, dtype=np.float32)
