@@ -372,6 +372,52 @@ def multires(G1, G2, S1=256, S2=512, coarse_mesh=(6, 6, 4)):
     print(json.dumps(res), flush=True)
 
 
+def tetrahedron_fos_step(steps=3, warmup=1):
+    """Partial evaluation with the paper's FOS on the 512x512x100 pair: per
+    cube one of its 6 tetrahedra, whose 4 points move together (in both
+    grids); all 405 elements of all 512 solutions in one launch."""
+    import torch
+    from paper_2202_11001_amd import dsm
+    from paper_2202_11001_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.clinical()
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    X = w.population(reject=lambda X: gp.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0)
+    top = gp.topology()
+    n_cubes = gp.T // 6
+    off, pts = W.tetrahedron_fos(top["tets"], n_cubes, seed=41)
+    cand = w.candidates(X, off, pts)
+    Xd = torch.from_numpy(X).to(dev)
+    offd, ptsd, cd = (torch.from_numpy(a).to(dev) for a in (off, pts, cand))
+    cache = torch.empty((w.S, gp.T, 3), dtype=torch.float64, device=dev)
+    gp.eval_full(Xd, tet_terms=cache)
+    out = gp.eval_partial(Xd, offd, ptsd, cd, tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    samples = int(out[3].to(torch.int64).sum().item())
+    flagged = int((out[2] != 0).sum().item())
+    for _ in range(warmup):
+        gp.eval_partial(Xd, offd, ptsd, cd, tet_terms_in=cache, out=out)
+    torch.cuda.synchronize()
+    gp.timing(steps)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        gp.eval_partial(Xd, offd, ptsd, cd, tet_terms_in=cache, out=out)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+    kms = float(np.mean(gp.timing_read()))
+    gp.timing(0)
+    evals = w.S * n_cubes
+    log(f"tetrahedron FOS: {evals} partial evaluations of 4-point elements, {samples} samples, {flagged} flagged, "
+        f"{ms:.2f} ms per step (sweep {kms:.2f} ms)")
+    print(json.dumps({"workload": w.name, "fos": "one tetrahedron per cube (4 points)", "partial_evals": evals,
+                      "voxel_samples": samples, "flagged": flagged, "ms_per_step": ms, "sweep_ms": kms,
+                      "partial_evals_per_s": evals / (ms / 1e3), "voxel_samples_per_s": samples / (ms / 1e3),
+                      "algorithmic_GBps": samples * BYTES_PER_SAMPLE / (kms / 1e3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,6 +431,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch")
     ap.add_argument("--multires", type=int, nargs=2, default=None, metavar=("G1", "G2"),
                     help="multi-resolution run: G1 coarse then G2 fine generations (reported separately)")
+    ap.add_argument("--tet-fos", action="store_true",
+                    help="partial evaluation with the paper's one-tetrahedron-per-cube FOS (reported separately)")
     ap.add_argument("--uneven", action="store_true",
                     help="12 problems of uneven size in one fused launch per pyramid level (reported separately)")
     ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
@@ -399,6 +447,9 @@ def main():
         return
     if args.multires:
         multires(*args.multires)
+        return
+    if args.tet_fos:
+        tetrahedron_fos_step()
         return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_screen = 2, 0, True, True

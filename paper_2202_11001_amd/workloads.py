@@ -366,3 +366,14 @@ def upsample_population(X_half):
     """Hand-off from the half-resolution level: voxel coordinate x at half
     resolution is 2 x + 0.5 at full resolution (lattice u -> 2 u, exact)."""
     return (2.0 * np.asarray(X_half, dtype=np.float64) + 0.5).astype(np.float32)
+
+
+def tetrahedron_fos(tets, n_cubes, seed):
+    """The paper's FOS for partial changes: per cube, one of its 6 tetrahedra
+    (tetrahedron 6 c + r of cube c, r drawn uniformly), whose 4 points change
+    together.  tets [T][4] is the mesh topology (tetrahedra numbered cube by
+    cube).  Returns CSR (offsets [F+1], points)."""
+    rng = np.random.default_rng(seed)
+    r = rng.integers(0, 6, size=n_cubes)
+    pts = np.asarray(tets, dtype=np.int32)[6 * np.arange(n_cubes) + r].reshape(-1)
+    return (4 * np.arange(n_cubes + 1)).astype(np.int32), pts.astype(np.int32)

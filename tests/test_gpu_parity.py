@@ -410,3 +410,34 @@ def ref_pitch_default(Dx):
     while p % 16 != 8:
         p += 1
     return p
+
+
+def test_tetrahedron_fos_clinical_sampled():
+    """The paper's FOS (per cube one tetrahedron, its 4 points move together)
+    at 512x512x100 in one launch of all elements and solutions; a sample of
+    (solution, element) pairs is recomputed by the oracle."""
+    w = W.clinical()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    n_cubes = rp.T // 6
+    off, pts = W.tetrahedron_fos(rp.tets(), n_cubes, seed=41)
+    cand = w.candidates(X, off, pts)
+    _say(f"tetrahedron FOS at {w.name}: {n_cubes} elements x {w.S} solutions")
+    gp = _gpu_problem(w, w.S, F=n_cubes, max_fos_points=4)
+    Xd = _t(X)
+    cache = torch.empty((w.S, gp.T, 3), dtype=torch.float64, device=DEV)
+    gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for s in rng.choice(w.S, 2, replace=False):
+        elems = np.sort(rng.choice(n_cubes, 3, replace=False))
+        off_s = (4 * np.arange(len(elems) + 1)).astype(np.int32)
+        pts_s = np.concatenate([pts[off[e]:off[e + 1]] for e in elems]).astype(np.int32)
+        cand_s = np.concatenate([cand[s, off[e]:off[e + 1]] for e in elems])[None]
+        rold, rnew, rfl, rnv = rp.eval_partial(X[s:s + 1], off_s, pts_s, cand_s)
+        g_fl = fl.cpu().numpy()[s, elems][None].astype(np.uint32)
+        np.testing.assert_array_equal(g_fl, rfl)
+        np.testing.assert_array_equal(vc.cpu().numpy()[s, elems][None][g_fl == 0], rnv[g_fl == 0])
+        assert_objectives_close(new.cpu().numpy()[s, elems][None], rnew, flags=g_fl, what="part_new")
+        assert_objectives_close(old.cpu().numpy()[s, elems][None], rold, what="part_old")
