@@ -30,6 +30,8 @@
  *     allocation after dsm_problem_create, so the calls can be captured in a
  *     HIP graph.  Calls on one problem must not run concurrently on different
  *     streams (they share the problem's workspace).
+ *   - Sizes of zero (S = 0, F = 0, no jobs) are valid: the call enqueues nothing
+ *     and returns DSM_OK, and the pointers of the empty buffers may be NULL.
  *   - Errors: every function returns a dsm_status; nothing throws across the
  *     ABI.  Host-detectable errors (null pointers, sizes, capacities) are
  *     returned before anything is enqueued.  Errors in device-resident values

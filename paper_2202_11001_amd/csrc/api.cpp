@@ -342,9 +342,10 @@ dsm_status dsm_mesh_topology(const int32_t mesh[3], const int32_t dims[3], int32
 dsm_status dsm_fold_check(dsm_problem* p, int32_t S, const float* X, uint32_t* flags, int32_t* first_bad_tet,
                           void* stream) {
   g_err.clear();
-  if (!p || !X || !flags) return fail(DSM_ERR_ARG, "null argument");
+  if (!p) return fail(DSM_ERR_ARG, "null argument");
   if (S < 0) return fail(DSM_ERR_ARG, "S < 0");
-  if (S == 0) return DSM_OK;
+  if (S == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !flags) return fail(DSM_ERR_ARG, "null argument");
   const hipError_t e = launch_fold(p->dev, S, X, flags, first_bad_tet, (hipStream_t)stream);
   return e == hipSuccess ? DSM_OK : hip_fail(e, "fold check launch");
 }
@@ -352,9 +353,10 @@ dsm_status dsm_fold_check(dsm_problem* p, int32_t S, const float* X, uint32_t* f
 dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj, uint32_t* flags, double* tet_terms,
                          void* stream) {
   g_err.clear();
-  if (!p || !X || !obj || !flags) return fail(DSM_ERR_ARG, "null argument");
+  if (!p) return fail(DSM_ERR_ARG, "null argument");
   if (S < 0) return fail(DSM_ERR_ARG, "S < 0");
-  if (S == 0) return DSM_OK;
+  if (S == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !obj || !flags) return fail(DSM_ERR_ARG, "null argument");
   if (S > p->max_S) return fail(DSM_ERR_CAPACITY, "S = %d exceeds max_solutions = %d", S, p->max_S);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_fold(p->dev, S, X, flags, nullptr, st);
@@ -382,12 +384,13 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
                             double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
                             void* stream) {
   g_err.clear();
-  if (!p || !X || !fos_off || !fos_pts || !cand || !part_old || !part_new || !flags)
-    return fail(DSM_ERR_ARG, "null argument");
+  if (!p) return fail(DSM_ERR_ARG, "null argument");
   if (S < 0 || F < 0) return fail(DSM_ERR_ARG, "negative S or F");
   if (S > p->max_S) return fail(DSM_ERR_CAPACITY, "S = %d exceeds max_solutions = %d", S, p->max_S);
   if (F > p->max_F) return fail(DSM_ERR_CAPACITY, "F = %d exceeds max_fos = %d", F, p->max_F);
-  if (S == 0 || F == 0) return DSM_OK;
+  if (S == 0 || F == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !fos_off || !fos_pts || !cand || !part_old || !part_new || !flags)
+    return fail(DSM_ERR_ARG, "null argument");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_affected(p->dev, F, fos_off, fos_pts, p->max_pts, p->maxA, p->d_aff, p->d_aff_cnt, st);
   if (e != hipSuccess) return hip_fail(e, "affected-set launch");

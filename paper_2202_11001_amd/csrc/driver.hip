@@ -144,9 +144,10 @@ extern "C" {
 dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
                                  float sigma, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
                                  void* stream) {
-  if (!p || !X || !fos_pts || !cand || S < 0 || F < 0 || K < 1 || !(sigma >= 0.f)) return DSM_ERR_ARG;
+  if (!p || S < 0 || F < 0 || K < 1 || !(sigma >= 0.f)) return DSM_ERR_ARG;
   const int64_t n = (int64_t)S * F * K * 6;
-  if (n == 0) return DSM_OK;
+  if (n == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !fos_pts || !cand) return DSM_ERR_ARG;
   k_sample<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(p->dev, S, X, F, fos_pts, K, sigma, seed,
                                                                        counter, (const unsigned long long*)counter_dev,
                                                                        cand);
@@ -167,10 +168,10 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
                       const double* part_old, const double* part_new, const uint32_t* flags, const double* terms_cand,
                       double* terms_cache, double* obj, int32_t n_archive, const double* archive, uint8_t* accepted,
                       void* stream) {
-  if (!p || !X || !fos_pts || !cand || !part_old || !part_new || !flags || !terms_cand || !terms_cache || !obj)
+  if (!p || S < 0 || F < 0 || n_archive < 0 || (n_archive > 0 && !archive) || S > p->max_S) return DSM_ERR_ARG;
+  if (S == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !terms_cache || !obj || (F > 0 && (!fos_pts || !cand || !part_old || !part_new || !flags || !terms_cand)))
     return DSM_ERR_ARG;
-  if (S < 0 || F < 0 || n_archive < 0 || (n_archive > 0 && !archive) || S > p->max_S) return DSM_ERR_ARG;
-  if (S == 0) return DSM_OK;
   hipStream_t st = (hipStream_t)stream;
   if (F > 0)
     k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, fos_pts, cand, part_old, part_new, flags, terms_cand,

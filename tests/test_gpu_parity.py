@@ -441,3 +441,53 @@ def test_tetrahedron_fos_clinical_sampled():
         np.testing.assert_array_equal(vc.cpu().numpy()[s, elems][None][g_fl == 0], rnv[g_fl == 0])
         assert_objectives_close(new.cpu().numpy()[s, elems][None], rnew, flags=g_fl, what="part_new")
         assert_objectives_close(old.cpu().numpy()[s, elems][None], rold, what="part_old")
+
+
+def test_empty_calls_are_no_ops():
+    """S = 0, F = 0 and empty batches enqueue nothing and report success."""
+    w = W.tiny()
+    gp = _gpu_problem(w, w.S)
+    X0 = torch.zeros((0, 2, w.P, 3), dtype=torch.float32, device=DEV)
+    obj, fl = gp.eval_full(X0)
+    assert obj.shape == (0, 3) and fl.shape == (0,)
+    assert gp.fold_check(X0).shape == (0,)
+    off0 = torch.zeros(1, dtype=torch.int32, device=DEV)
+    pts0 = torch.zeros(0, dtype=torch.int32, device=DEV)
+    X = _t(w.population())
+    cand0 = torch.zeros((w.S, 0, 2, 3), dtype=torch.float32, device=DEV)
+    old, new, flg, _ = gp.eval_partial(X, off0, pts0, cand0)
+    assert old.shape == (w.S, 0, 3)
+    assert dsm.refine_population(w.mesh, X0).shape[0] == 0
+    assert dsm.Batch(max_jobs=2).eval_partial([]) == []
+    torch.cuda.synchronize()
+
+
+def test_maximum_image_size_sampled():
+    """512^3 images (the largest the exact lattice predicates support): one
+    full evaluation and sampled partial evaluations against the oracle."""
+    shape = (512, 512, 512)
+    rng = np.random.default_rng(8)
+    coarse = rng.uniform(0, 1, (17, 17, 17)).astype(np.float32)
+    from scipy import ndimage
+    fixed = ndimage.zoom(coarse, 512 / 17, order=1)[:512, :512, :512].astype(np.float32)
+    moving = np.roll(fixed, 3, axis=2)
+    w = W.Workload("max-512^3", moving, fixed, (4, 4, 4), (1.0, 1.0, 1.0), 0.2, 4, 6.0, 4.0, 51, 52)
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    _say(f"{w.name}: {w.S} solutions, {w.P} points")
+    gp = _gpu_problem(w, w.S)
+    obj, fl = gp.eval_full(_t(X))
+    old, new, flg, vc = gp.eval_partial(_t(X), _t(off), _t(pts), _t(cand), voxel_count=True)
+    torch.cuda.synchronize()
+    robj, rfl = rp.eval_full(X[:1])
+    np.testing.assert_array_equal(fl.cpu().numpy()[:1], rfl)
+    assert_objectives_close(obj.cpu().numpy()[:1], robj, what="full objectives at 512^3")
+    elems = np.array([0, 21, 42], dtype=np.int32)  # a corner, an interior and another interior point
+    rold, rnew, rfl2, rnv = rp.eval_partial(X[1:2], np.arange(4, dtype=np.int32), elems, cand[1:2, elems])
+    g_fl = flg.cpu().numpy()[1, elems][None].astype(np.uint32)
+    np.testing.assert_array_equal(g_fl, rfl2)
+    np.testing.assert_array_equal(vc.cpu().numpy()[1, elems][None][g_fl == 0], rnv[g_fl == 0])
+    assert_objectives_close(new.cpu().numpy()[1, elems][None], rnew, flags=g_fl, what="part_new at 512^3")
+    assert_objectives_close(old.cpu().numpy()[1, elems][None], rold, what="part_old at 512^3")
