@@ -100,20 +100,86 @@ __device__ void forward16(const MlpW& w, const unsigned short* x, bool row_valid
   for (int r = 0; r < 4; ++r) y[r] = i < kOut ? acc[r] + b : 0.f;
 }
 
-// One wave per workgroup (64 threads), 16 rows per wave.
-__global__ __launch_bounds__(64) void k_mlp_forward(MlpW w, const unsigned short* __restrict__ xb, int N,
-                                                    float* __restrict__ out) {
-  __shared__ __align__(16) unsigned short h1[16 * kLdsStride], h2[16 * kLdsStride];
-  const int lane = threadIdx.x, i = lane & 15, kb = lane >> 4;
-  const int row0 = blockIdx.x * 16;
-  const bool valid = row0 + i < N;
-  f32x4 y;
-  forward16(w, xb + (size_t)row0 * kIn, valid, h1, h2, lane, y);
-  if (i < kOut)
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 4 * kb + r;
-      if (row < N) out[(size_t)row * kOut + i] = y[r];
+// Screening forward pass: 64 rows per workgroup of 4 waves.  The rows are
+// staged in LDS once; each wave computes a 32-column slice of a layer for all
+// 64 rows, so every weight fragment read from memory serves 4 row blocks.
+constexpr int kXs = kIn + 8;  // padded LDS strides (BF16 elements)
+constexpr int kHs = kHid + 8;
+
+__global__ __launch_bounds__(256) void k_mlp_forward64(MlpW w, const unsigned short* __restrict__ xb, int N,
+                                                       float* __restrict__ out) {
+  __shared__ __align__(16) unsigned short xs[64 * kXs];  // inputs, then H2
+  __shared__ __align__(16) unsigned short h1[64 * kHs];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, kb = lane >> 4;
+  const int row0 = blockIdx.x * 64;
+  for (int e = tid; e < 64 * kIn / 8; e += 256) {
+    const int r = e / (kIn / 8), c = e % (kIn / 8);
+    const u16x8 v = row0 + r < N ? load8(xb + (size_t)(row0 + r) * kIn + 8 * c) : zero8();
+    *(u16x8*)(xs + r * kXs + 8 * c) = v;
+  }
+  __syncthreads();
+  // layer 1: H1 = relu(X W1^T + b1), wave -> columns [32 wave, 32 wave + 32)
+  {
+    f32x4 acc[2][4];
+    for (int t = 0; t < 2; ++t)
+      for (int rb = 0; rb < 4; ++rb) acc[t][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kIn / 32; ++kk) {
+      u16x8 b[2];
+      for (int t = 0; t < 2; ++t) b[t] = load8(w.w1 + (size_t)(32 * wave + 16 * t + i) * kIn + 32 * kk + 8 * kb);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const u16x8 a = *(const u16x8*)(xs + (16 * rb + i) * kXs + 32 * kk + 8 * kb);
+        for (int t = 0; t < 2; ++t) acc[t][rb] = mfma(a, b[t], acc[t][rb]);
+      }
     }
+    for (int t = 0; t < 2; ++t) {
+      const int col = 32 * wave + 16 * t + i;
+      const float bias = w.b1[col];
+      for (int rb = 0; rb < 4; ++rb)
+        for (int r = 0; r < 4; ++r) h1[(16 * rb + 4 * kb + r) * kHs + col] = f2bf(fmaxf(acc[t][rb][r] + bias, 0.f));
+    }
+  }
+  __syncthreads();
+  // layer 2: H2 = relu(H1 W2^T + b2) into the input buffer (no longer needed)
+  unsigned short* h2 = xs;
+  {
+    f32x4 acc[2][4];
+    for (int t = 0; t < 2; ++t)
+      for (int rb = 0; rb < 4; ++rb) acc[t][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kHid / 32; ++kk) {
+      u16x8 b[2];
+      for (int t = 0; t < 2; ++t) b[t] = load8(w.w2 + (size_t)(32 * wave + 16 * t + i) * kHid + 32 * kk + 8 * kb);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const u16x8 a = *(const u16x8*)(h1 + (16 * rb + i) * kHs + 32 * kk + 8 * kb);
+        for (int t = 0; t < 2; ++t) acc[t][rb] = mfma(a, b[t], acc[t][rb]);
+      }
+    }
+    for (int t = 0; t < 2; ++t) {  // the barrier after layer 1 ordered every read of the inputs before this
+      const int col = 32 * wave + 16 * t + i;
+      const float bias = w.b2[col];
+      for (int rb = 0; rb < 4; ++rb)
+        for (int r = 0; r < 4; ++r) h2[(16 * rb + 4 * kb + r) * kHs + col] = f2bf(fmaxf(acc[t][rb][r] + bias, 0.f));
+    }
+  }
+  __syncthreads();
+  // layer 3: Y = H2 W3^T + b3, wave -> row block `wave`
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < kHid / 32; ++kk) {
+    const u16x8 a = *(const u16x8*)(h2 + (16 * wave + i) * kHs + 32 * kk + 8 * kb);
+    const u16x8 b = load8(w.w3 + (size_t)i * kHid + 32 * kk + 8 * kb);
+    acc = mfma(a, b, acc);
+  }
+  if (i < kOut) {
+    const float bias = w.b3[i];
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * wave + 4 * kb + r;
+      if (row < N) out[(size_t)row * kOut + i] = acc[r] + bias;
+    }
+  }
 }
 
 // Training rows: forward and backward of 16 minibatch rows per wave.  Writes
@@ -224,11 +290,14 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(const unsigned short* __restri
   for (int r = 0; r < 4; ++r) dw[(size_t)(16 * ot + 4 * kb + r) * ncols + 16 * ctile + i] = acc[r];
 }
 
-// Bias gradients (fixed-order sums over the batch) and the minibatch loss.
-__global__ void k_mlp_bias_loss(const unsigned short* __restrict__ dz1t, const unsigned short* __restrict__ dz2t,
-                                const unsigned short* __restrict__ dyt, const float* __restrict__ row_loss, int B, int ld,
-                                float* __restrict__ grad, float* __restrict__ loss_out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// Bias gradients and the minibatch loss: one wave per sum, lanes over the
+// batch in a fixed order, then a fixed shuffle tree (deterministic).
+__global__ __launch_bounds__(64) void k_mlp_bias_loss(const unsigned short* __restrict__ dz1t,
+                                                      const unsigned short* __restrict__ dz2t,
+                                                      const unsigned short* __restrict__ dyt,
+                                                      const float* __restrict__ row_loss, int B, int ld,
+                                                      float* __restrict__ grad, float* __restrict__ loss_out) {
+  const int t = blockIdx.x, lane = threadIdx.x;
   const unsigned short* src = nullptr;
   float* dst = nullptr;
   if (t < kHid) {
@@ -240,17 +309,20 @@ __global__ void k_mlp_bias_loss(const unsigned short* __restrict__ dz1t, const u
   } else if (t < 2 * kHid + kOutPad) {
     src = dyt + (size_t)(t - 2 * kHid) * ld;
     dst = grad + kB3 + (t - 2 * kHid);
-  } else if (t == 2 * kHid + kOutPad) {
-    float acc = 0.f;
-    for (int b = 0; b < B; ++b) acc += row_loss[b];
-    if (loss_out) *loss_out = acc / (3.f * (float)B);
-    return;
-  } else {
-    return;
   }
   float acc = 0.f;
-  for (int b = 0; b < B; ++b) acc += bf2f(src[b]);
-  *dst = acc;
+  if (src) {
+    for (int b = lane; b < B; b += 64) acc += bf2f(src[b]);
+  } else {
+    for (int b = lane; b < B; b += 64) acc += row_loss[b];
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    if (src)
+      *dst = acc;
+    else if (loss_out)
+      *loss_out = acc / (3.f * (float)B);
+  }
 }
 
 // Adam step on the FP32 master parameters, then refresh of the BF16 operand copies.
@@ -572,7 +644,7 @@ hipError_t gradient_pass(dsm_surrogate* m, const unsigned short* feats, const fl
   k_mlp_wgrad<<<dim3(kHid / 16, kHid / 16), 64, 0, st>>>(m->d_dz2t, m->d_h1t, ld, kHid, m->d_grad + kW2);
   k_mlp_wgrad<<<dim3(kHid / 16, kOutPad / 16), 64, 0, st>>>(m->d_dyt, m->d_h2t, ld, kHid, m->d_grad + kW3);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_mlp_bias_loss<<<(2 * kHid + kOutPad + 1 + 63) / 64, 64, 0, st>>>(m->d_dz1t, m->d_dz2t, m->d_dyt, m->d_row_loss, B, ld,
+  k_mlp_bias_loss<<<2 * kHid + kOutPad + 1, 64, 0, st>>>(m->d_dz1t, m->d_dz2t, m->d_dyt, m->d_row_loss, B, ld,
                                                                     m->d_grad, loss);
   return hipGetLastError();
 }
@@ -758,7 +830,7 @@ dsm_status dsm_surrogate_forward(dsm_surrogate* m, int32_t N, const uint16_t* fe
   s_err.clear();
   if (!m || !feats_bf16 || !pred || N < 0) return sfail(DSM_ERR_ARG, "null argument");
   if (N == 0) return DSM_OK;
-  k_mlp_forward<<<(N + 15) / 16, 64, 0, (hipStream_t)stream>>>(weights(m), (const unsigned short*)feats_bf16, N, pred);
+  k_mlp_forward64<<<(N + 63) / 64, 256, 0, (hipStream_t)stream>>>(weights(m), (const unsigned short*)feats_bf16, N, pred);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? DSM_OK : sfail(DSM_ERR_DEVICE, hipGetErrorString(e));
 }
@@ -809,7 +881,7 @@ dsm_status dsm_surrogate_screen(dsm_surrogate* m, dsm_problem* p, int32_t S, con
   hipStream_t st = (hipStream_t)stream;
   k_features<<<(unsigned)((n + 127) / 128), 128, 0, st>>>(p->dev, X, S, F, fos_pts, K, cand, p->d_ident, m->d_feat);
   k_pack<<<(unsigned)((n * kIn + 255) / 256), 256, 0, st>>>((int)n, m->d_feat, m->d_in_mean, m->d_in_rstd, m->d_featb);
-  k_mlp_forward<<<(unsigned)((n + 15) / 16), 64, 0, st>>>(weights(m), m->d_featb, (int)n, m->d_pred);
+  k_mlp_forward64<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(weights(m), m->d_featb, (int)n, m->d_pred);
   k_select<<<(S * F + 255) / 256, 256, 0, st>>>(S, F, K, m->d_pred, m->d_out_mean, m->d_out_scale, obj, n_archive, archive,
                                                  pred, pick, run_exact);
   if (cand_pick) k_gather_pick<<<(S * F * 6 + 255) / 256, 256, 0, st>>>(S, F, K, cand, pick, cand_pick);
