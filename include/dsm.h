@@ -301,6 +301,13 @@ dsm_status dsm_surrogate_set_scaling(dsm_surrogate* s, const float* in_mean, con
  * [S][F][K][2][3] of single-point elements fos_pts dev [F] of solutions X. */
 dsm_status dsm_surrogate_features(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
                                   const float* cand, float* feats, void* stream);
+/* The rows of dsm_surrogate_features, standardised with the surrogate's input
+ * statistics and rounded to BF16 in one pass: feats_bf16 dev [S*F*K][192] is
+ * bit for bit what dsm_surrogate_pack makes of the FP32 rows (the screening
+ * path; no FP32 rows are written). */
+dsm_status dsm_surrogate_features_packed(dsm_surrogate* s, dsm_problem* p, int32_t S, const float* X, int32_t F,
+                                         const int32_t* fos_pts, int32_t K, const float* cand, uint16_t* feats_bf16,
+                                         void* stream);
 /* Standardises N rows: feats dev [N][192] -> feats_bf16 dev [N][192] (bits of
  * BF16), and deltas part_new - part_old (dev [N][3] float64) -> targets dev
  * [N][3] (standardised) and raw_deltas dev [N][3]; any pair may be NULL. */

@@ -401,46 +401,74 @@ __device__ float sample_packed(const DevProblem& pr, const float* img, float px,
 //   [162, 188) source image at (candidate + h o) minus target image at
 //              (candidate + h o), h = half the undeformed cube extent per axis;
 //   [188, 192) zero.
-__global__ void k_features(DevProblem pr, const float* __restrict__ X, int S, int F, const int* __restrict__ pts, int K,
-                           const float* __restrict__ cand, const float* __restrict__ ident, float* __restrict__ out) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (row >= (int64_t)S * F * K) return;
+// Rows are numbered (s, f, k) with k fastest.  32 lanes share a row: lane
+// j < 26 computes neighbour slot j (its 6 displacement features and its
+// intensity difference), lane 26 the moved-point features, lane 27 the padding.
+// With PACK the values are standardised with the stored input statistics and
+// rounded to BF16 in the same kernel, bit for bit what k_pack makes of the
+// FP32 rows (sums and products are written with explicit rounding, so that
+// both instantiations compute identical FP32 values).
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_features(DevProblem pr, const float* __restrict__ X, int S, int F,
+                                                  const int* __restrict__ pts, int K, const float* __restrict__ cand,
+                                                  const float* __restrict__ ident, const float* __restrict__ mean,
+                                                  const float* __restrict__ rstd, float* __restrict__ out32,
+                                                  unsigned short* __restrict__ out16) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 5;
+  const int j = threadIdx.x & 31;
+  if (row >= (int64_t)S * F * K || j >= 28) return;
   const int s = (int)(row / ((int64_t)F * K));
   const int f = (int)((row / K) % F);
   const int p = pts[f];
-  float* o = out + row * kIn;
+  const bool valid = p >= 0 && p < pr.P;
   const float* c = cand + row * 6;  // [2][3]
   const float* Xs = X + (size_t)s * 6 * pr.P;
-  if (p < 0 || p >= pr.P) {
-    for (int q = 0; q < kIn; ++q) o[q] = 0.f;
-    return;
-  }
-  for (int g = 0; g < 2; ++g)
-    for (int a = 0; a < 3; ++a) o[3 * g + a] = c[3 * g + a] - Xs[((size_t)g * pr.P + p) * 3 + a];
-  const int pi = p % pr.n[0], pj = (p / pr.n[0]) % pr.n[1], pk = p / (pr.n[0] * pr.n[1]);
-  int slot = 0;
-  float h[3];
-  for (int a = 0; a < 3; ++a) h[a] = (float)pr.D[a] / (2.f * (float)(pr.n[a] - 1));
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (dx == 0 && dy == 0 && dz == 0) continue;
-        const int qi = pi + dx, qj = pj + dy, qk = pk + dz;
-        const bool in = qi >= 0 && qi < pr.n[0] && qj >= 0 && qj < pr.n[1] && qk >= 0 && qk < pr.n[2];
+  float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float vi = 0.f;
+  int col;
+  if (j < 26) {
+    col = 6 + 6 * j;
+    if (valid) {
+      const int t = j < 13 ? j : j + 1;  // centre (13) skipped
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+      const int pi = p % pr.n[0], pj = (p / pr.n[0]) % pr.n[1], pk = p / (pr.n[0] * pr.n[1]);
+      const int qi = pi + dx, qj = pj + dy, qk = pk + dz;
+      if (qi >= 0 && qi < pr.n[0] && qj >= 0 && qj < pr.n[1] && qk >= 0 && qk < pr.n[2]) {
         const int q = qi + pr.n[0] * (qj + pr.n[1] * qk);
         for (int g = 0; g < 2; ++g)
-          for (int a = 0; a < 3; ++a) {
-            float v = 0.f;
-            if (in) v = (Xs[((size_t)g * pr.P + q) * 3 + a] - c[3 * g + a]) - (ident[3 * q + a] - ident[3 * p + a]);
-            o[6 + 6 * slot + 3 * g + a] = v;
-          }
-        const float off[3] = {h[0] * dx, h[1] * dy, h[2] * dz};
-        const float im = sample_packed(pr, pr.img[0], c[0] + off[0], c[1] + off[1], c[2] + off[2]);
-        const float it = sample_packed(pr, pr.img[1], c[3] + off[0], c[4] + off[1], c[5] + off[2]);
-        o[162 + slot] = im - it;
-        ++slot;
+          for (int a = 0; a < 3; ++a)
+            v[3 * g + a] = __fsub_rn(__fsub_rn(Xs[((size_t)g * pr.P + q) * 3 + a], c[3 * g + a]),
+                                     __fsub_rn(ident[3 * q + a], ident[3 * p + a]));
       }
-  for (int q = kNumFeat; q < kIn; ++q) o[q] = 0.f;
+      float off[3];
+      const int d[3] = {dx, dy, dz};
+      for (int a = 0; a < 3; ++a) off[a] = __fmul_rn(__fdiv_rn((float)pr.D[a], 2.f * (float)(pr.n[a] - 1)), (float)d[a]);
+      const float im = sample_packed(pr, pr.img[0], __fadd_rn(c[0], off[0]), __fadd_rn(c[1], off[1]), __fadd_rn(c[2], off[2]));
+      const float it = sample_packed(pr, pr.img[1], __fadd_rn(c[3], off[0]), __fadd_rn(c[4], off[1]), __fadd_rn(c[5], off[2]));
+      vi = __fsub_rn(im, it);
+    }
+  } else if (j == 26) {
+    col = 0;
+    if (valid)
+      for (int g = 0; g < 2; ++g)
+        for (int a = 0; a < 3; ++a) v[3 * g + a] = __fsub_rn(c[3 * g + a], Xs[((size_t)g * pr.P + p) * 3 + a]);
+  } else {
+    col = kNumFeat;  // 4 zero columns
+  }
+  const int nv = j == 27 ? kIn - kNumFeat : 6;
+  if (PACK) {
+    unsigned* o = reinterpret_cast<unsigned*>(out16 + row * kIn + col);  // 4-byte aligned: col is even
+    for (int e = 0; e < nv; e += 2) {
+      const unsigned lo = f2bf(__fmul_rn(__fsub_rn(v[e], mean[col + e]), rstd[col + e]));
+      const unsigned hi = f2bf(__fmul_rn(__fsub_rn(v[e + 1], mean[col + e + 1]), rstd[col + e + 1]));
+      o[e >> 1] = lo | (hi << 16);
+    }
+    if (j < 26) out16[row * kIn + kNumFeat - 26 + j] = f2bf(__fmul_rn(__fsub_rn(vi, mean[162 + j]), rstd[162 + j]));
+  } else {
+    float2* o = reinterpret_cast<float2*>(out32 + row * kIn + col);  // 8-byte aligned: col is even
+    for (int e = 0; e < nv; e += 2) o[e >> 1] = make_float2(v[e], v[e + 1]);
+    if (j < 26) out32[row * kIn + kNumFeat - 26 + j] = vi;
+  }
 }
 
 // Standardise FP32 rows and round to BF16 operands; optionally standardise targets.
@@ -449,7 +477,7 @@ __global__ void k_pack(int N, const float* __restrict__ feats, const float* __re
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)N * kIn) return;
   const int c = (int)(e % kIn);
-  out[e] = f2bf((feats[e] - mean[c]) * rstd[c]);
+  out[e] = f2bf(__fmul_rn(__fsub_rn(feats[e], mean[c]), rstd[c]));
 }
 
 // Column mean and 1/std of N rows of width `width` (fixed-order FP64 sums, one
@@ -589,7 +617,6 @@ struct dsm_surrogate {
   float* d_row_loss = nullptr;
   int* d_idx = nullptr;
   // screening workspace for max_rows rows
-  float* d_feat = nullptr;            // [max_rows][192]
   unsigned short* d_featb = nullptr;  // [max_rows][192]
   float* d_pred = nullptr;            // [max_rows][3]
 };
@@ -621,7 +648,7 @@ void free_sur(dsm_surrogate* m) {
   void* bufs[] = {m->d_params, m->d_m,      m->d_v,        m->d_grad,     m->d_w1,      m->d_w2,   m->d_w3,
                   m->d_w2t,    m->d_w3t,    m->d_in_mean,  m->d_in_rstd,  m->d_out_mean, m->d_out_rstd,
                   m->d_out_scale, m->d_xt,  m->d_h1t,      m->d_h2t,      m->d_dyt,     m->d_dz2t, m->d_dz1t,
-                  m->d_row_loss, m->d_idx,  m->d_feat,     m->d_featb,    m->d_pred};
+                  m->d_row_loss, m->d_idx,  m->d_featb,    m->d_pred};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -696,7 +723,6 @@ dsm_status dsm_surrogate_create(const dsm_surrogate_desc* d, dsm_surrogate** out
   S_TRY(hipMalloc(&m->d_dz1t, 2 * kHid * B));
   S_TRY(hipMalloc(&m->d_row_loss, sizeof(float) * B));
   S_TRY(hipMalloc(&m->d_idx, sizeof(int) * B));
-  S_TRY(hipMalloc(&m->d_feat, sizeof(float) * kIn * (size_t)d->max_rows));
   S_TRY(hipMalloc(&m->d_featb, 2 * kIn * (size_t)d->max_rows));
   S_TRY(hipMalloc(&m->d_pred, sizeof(float) * kOut * (size_t)d->max_rows));
   // He-uniform initial weights, zero biases (host, from the seed); identity scaling
@@ -801,12 +827,27 @@ dsm_status dsm_surrogate_set_scaling(dsm_surrogate* m, const float* in_mean, con
 dsm_status dsm_surrogate_features(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
                                   const float* cand, float* feats, void* stream) {
   s_err.clear();
-  if (!p || !X || !fos_pts || !cand || !feats) return sfail(DSM_ERR_ARG, "null argument");
-  if (S < 0 || F < 0 || K < 1) return sfail(DSM_ERR_ARG, "bad sizes");
+  if (!p || S < 0 || F < 0 || K < 1) return sfail(DSM_ERR_ARG, "null problem or bad sizes");
   const int64_t n = (int64_t)S * F * K;
   if (n == 0) return DSM_OK;
-  k_features<<<(unsigned)((n + 127) / 128), 128, 0, (hipStream_t)stream>>>(p->dev, X, S, F, fos_pts, K, cand, p->d_ident,
-                                                                        feats);
+  if (!X || !fos_pts || !cand || !feats) return sfail(DSM_ERR_ARG, "null argument");
+  k_features<false><<<(unsigned)((n + 7) / 8), 256, 0, (hipStream_t)stream>>>(p->dev, X, S, F, fos_pts, K, cand, p->d_ident,
+                                                                           nullptr, nullptr, feats, nullptr);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? DSM_OK : sfail(DSM_ERR_DEVICE, hipGetErrorString(e));
+}
+
+dsm_status dsm_surrogate_features_packed(dsm_surrogate* m, dsm_problem* p, int32_t S, const float* X, int32_t F,
+                                         const int32_t* fos_pts, int32_t K, const float* cand, uint16_t* feats_bf16,
+                                         void* stream) {
+  s_err.clear();
+  if (!m || !p || S < 0 || F < 0 || K < 1) return sfail(DSM_ERR_ARG, "null argument or bad sizes");
+  const int64_t n = (int64_t)S * F * K;
+  if (n == 0) return DSM_OK;
+  if (!X || !fos_pts || !cand || !feats_bf16) return sfail(DSM_ERR_ARG, "null argument");
+  k_features<true><<<(unsigned)((n + 7) / 8), 256, 0, (hipStream_t)stream>>>(p->dev, X, S, F, fos_pts, K, cand, p->d_ident,
+                                                                          m->d_in_mean, m->d_in_rstd, nullptr,
+                                                                          (unsigned short*)feats_bf16);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? DSM_OK : sfail(DSM_ERR_DEVICE, hipGetErrorString(e));
 }
@@ -879,8 +920,8 @@ dsm_status dsm_surrogate_screen(dsm_surrogate* m, dsm_problem* p, int32_t S, con
   if (n > m->desc.max_rows) return sfail(DSM_ERR_CAPACITY, "S*F*K exceeds max_rows");
   if (n == 0) return DSM_OK;
   hipStream_t st = (hipStream_t)stream;
-  k_features<<<(unsigned)((n + 127) / 128), 128, 0, st>>>(p->dev, X, S, F, fos_pts, K, cand, p->d_ident, m->d_feat);
-  k_pack<<<(unsigned)((n * kIn + 255) / 256), 256, 0, st>>>((int)n, m->d_feat, m->d_in_mean, m->d_in_rstd, m->d_featb);
+  k_features<true><<<(unsigned)((n + 7) / 8), 256, 0, st>>>(p->dev, X, S, F, fos_pts, K, cand, p->d_ident, m->d_in_mean,
+                                                            m->d_in_rstd, nullptr, m->d_featb);
   k_mlp_forward64<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(weights(m), m->d_featb, (int)n, m->d_pred);
   k_select<<<(S * F + 255) / 256, 256, 0, st>>>(S, F, K, m->d_pred, m->d_out_mean, m->d_out_scale, obj, n_archive, archive,
                                                  pred, pick, run_exact);

@@ -97,6 +97,7 @@ def lib():
             "dsm_surrogate_set_scaling": ([V, V, V, V, V], I),
             "dsm_surrogate_features": ([V, I, V, I, V, I, V, V, V], I),
             "dsm_surrogate_pack": ([V, I, V, V, V, V, V, V, V], I),
+            "dsm_surrogate_features_packed": ([V, V, I, V, I, V, I, V, V, V], I),
             "dsm_surrogate_forward": ([V, I, V, V, V], I),
             "dsm_surrogate_gradient": ([V, I, V, V, V, V, V], I),
             "dsm_surrogate_train": ([V, I, V, V, I, I, V, V], I),
@@ -403,6 +404,16 @@ class Surrogate:
         out = torch.empty((S * F * K, SUR_FEATURES), dtype=torch.float32, device=X.device)
         _scheck(lib().dsm_surrogate_features(problem._h, S, _dptr(X), F, _dptr(pts), K, _dptr(cand), _dptr(out),
                                              _stream(stream)))
+        return out
+
+    def features_packed(self, problem, X, pts, cand, stream=None):
+        """Standardised BF16 feature rows (as int16) [S*F*K][192] of candidates
+        cand [S][F][K][2][3], computed and packed in one kernel."""
+        torch = _torch()
+        S, F, K = cand.shape[:3]
+        out = torch.empty((S * F * K, SUR_FEATURES), dtype=torch.int16, device=X.device)
+        _scheck(lib().dsm_surrogate_features_packed(self._h, problem._h, S, _dptr(X), F, _dptr(pts), K, _dptr(cand),
+                                                    _dptr(out), _stream(stream)))
         return out
 
     def pack(self, feats=None, part_old=None, part_new=None, stream=None):

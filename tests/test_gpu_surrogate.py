@@ -130,6 +130,39 @@ def test_features_match_reference():
     assert np.all(f[:, 188:] == 0)
 
 
+@pytest.mark.parametrize("K", [1, 3])
+def test_fused_features_equal_pack_of_features(K):
+    """The screening path's one-kernel features + standardisation + BF16
+    rounding equals the two-step path bit for bit, and both equal numpy's
+    rounding of the standardised FP32 rows; an out-of-range point (-1) gives
+    the standardised zero row."""
+    w = W.tiny()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp, S=3)
+    pts = np.concatenate([[-1], np.arange(w.P)]).astype(np.int32)  # 28 elements: rows not a multiple of 8
+    cand = W.candidates(X, np.arange(w.P + 1, dtype=np.int32), np.arange(w.P, dtype=np.int32), w.mesh, w.dims, 1.0,
+                        17, K=K)  # [S][K][P][2][3], or [S][P][2][3] for K = 1
+    cand = cand[:, :, None] if K == 1 else cand.transpose(0, 2, 1, 3, 4)  # [S][P][K][2][3]
+    cand = np.concatenate([cand[:, :1], cand], axis=1)
+    _say(f"fused features tiny K={K}")
+    gp = dsm.Problem.from_workload(w, max_solutions=3)
+    rng = np.random.default_rng(K)
+    sur = dsm.Surrogate(seed=1, max_rows=3 * len(pts) * K)
+    mean = rng.normal(0, 0.3, 192).astype(np.float32)
+    rstd = rng.uniform(0.5, 4.0, 192).astype(np.float32)
+    sur.set_scaling(mean, rstd, np.zeros(3, np.float32), np.ones(3, np.float32))
+    Xd, ptsd, cd = _t(X), _t(pts), _t(cand)
+    f = dsm.Surrogate.features(gp, Xd, ptsd, cd)
+    two = sur.pack(f)[0].cpu().numpy()
+    one = sur.features_packed(gp, Xd, ptsd, cd).cpu().numpy()
+    assert one.shape == (3 * len(pts) * K, 192)
+    np.testing.assert_array_equal(one, two)
+    fn = f.cpu().numpy()
+    np.testing.assert_array_equal(one, _bf16_bits((fn - mean) * rstd))
+    zero_rows = fn.reshape(3, len(pts), K, 192)[:, 0]
+    assert np.all(zero_rows == 0)
+
+
 def _numpy_select(ps, K):
     """The screening rule on the GPU's own standardised predictions [M][K][3] (float32)."""
     picks = []
