@@ -180,10 +180,16 @@ __device__ __forceinline__ void slice_rows(const float L[4][3], int z, int Dy, i
   yb = min(Dy - 1, (int)floorf((hi - 63.5f) * (1.f / 128.f)));
 }
 
-// Fills rt for the tetrahedron with own-grid vertices xo[4][3] and other-grid
-// vertices xt[4][3] (voxel units, already validated on the lattice); the work
-// is spread over lanes so that no lane holds all of it in registers.
-__device__ void setup_raster(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
+// Rasterisation parameters of the tetrahedron with own-grid vertices xo[4][3]
+// and other-grid vertices xt[4][3] (voxel units, already validated on the
+// lattice), in two parts so that no thread holds all of it in registers.
+// setup_task(k) for k in [0, 14) fills the face functions (k < 4), the affine
+// map's matrix (4 <= k < 13) and the bounding box (k = 13); the 14 tasks may
+// run on any threads.  setup_slices then runs on one wave, after the tasks'
+// writes are visible to it, and fills the slice table and the map's offset.
+constexpr int kSetupTasks = 14;
+
+__device__ void setup_task(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
   if (lane < 4) {
     // face opposite vertex `lane`
     const int i = lane;
@@ -244,7 +250,9 @@ __device__ void setup_raster(const float* xo, const float* xt, const int D[3], i
     rt.ylo = ya;
     rt.ny = max(0, yb - ya + 1);
   }
-  wave_sync();
+}
+
+__device__ void setup_slices(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
   const int nz = rt.nz;
   if (nz <= kMaxSlices) {
     // candidate rows of slice zlo + lane, prefix-summed over the slices
@@ -276,6 +284,13 @@ __device__ void setup_raster(const float* xo, const float* xt, const int D[3], i
     rt.P0[r] = (double)xt[r] - (rt.J[r][0] * (double)xo[0] + rt.J[r][1] * (double)xo[1] + rt.J[r][2] * (double)xo[2]);
   }
   wave_sync();
+}
+
+// Both parts on one wave.
+__device__ void setup_raster(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
+  if (lane < kSetupTasks) setup_task(xo, xt, D, lane, rt);
+  wave_sync();
+  setup_slices(xo, xt, D, lane, rt);
 }
 
 // Exact x-span [x0, x1] (inclusive; empty if x0 > x1) of voxel row (y, z).
@@ -484,6 +499,24 @@ __device__ __forceinline__ void sweep_pair(const WaveRows& wr, const SampleCtx& 
   sum = t;
 }
 
+// The last chunk of a row batch when at most 64 voxels are left: voxel
+// q0 + lane only, slots past the last voxel repeat it and are weighted 0.
+__device__ __forceinline__ void sweep_one(const WaveRows& wr, const SampleCtx& sc, int q0, int nvox, int lane, int r0,
+                                          float jx, float jy, float jz, float& sum, float& comp) {
+  const int qa = q0 + lane;
+  const int ea = min(qa, nvox - 1);
+  const RowRec ra = wr.row[r0];
+  const float foa = (float)(ea - ra.start);
+  const float ava = load1(sc.own, (__float_as_int(ra.rec.x) + ea) << 3);
+  const Taps ta = load_taps(sc, fmaf(jx, foa, ra.rec.y), fmaf(jy, foa, ra.rec.z), fmaf(jz, foa, ra.rec.w));
+  const float ca = contrib_of(sc, ava, ta);
+  const float c = qa < nvox ? ca : 0.f;
+  const float y = c - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
 __device__ __forceinline__ double len_mm(const double sp[3], const double a[3], const double b[3]) {
   const double dx = (a[0] - b[0]) * sp[0], dy = (a[1] - b[1]) * sp[1], dz = (a[2] - b[2]) * sp[2];
   return sqrt(dx * dx + dy * dy + dz * dz);
@@ -678,32 +711,61 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   }
   __syncthreads();
 
-  // set-up of every (version, direction, tetrahedron) entry, one wave per
-  // entry: validity, orientation flag, rasterisation parameters and the
-  // number of 64-row units.  Direction 0 = target voxels mapped into the
-  // source (forward), 1 = source voxels into the target.
+  // set-up of every (version, direction, tetrahedron) entry: validity,
+  // orientation flag, rasterisation parameters and the number of 64-row
+  // units.  Direction 0 = target voxels mapped into the source (forward), 1 =
+  // source voxels into the target.  Entry e's own-grid vertices are at
+  // entry_xyz(e) + 12 own, the other grid's at + 12 (1 - own).
   const int nent = nver * 2 * na;
-  for (int e = wave; e < nent; e += kWaves) {
+  auto entry_xyz = [&](int e, int& own) {
     const int v = e / (2 * na), r = e - v * 2 * na, dir = r / na, i = r - dir * na;
-    const int own = 1 - dir;
-    const float* xyz = s_xyz + (size_t)(v * na + i) * 24;
+    own = 1 - dir;
+    return s_xyz + (size_t)(v * na + i) * 24;
+  };
+  // validity, 32 threads per entry: the 24 coordinates on the lattice, then
+  // the orientation of the own-grid tetrahedron; s_units[e] = 1 if it is set up
+  for (int t = tid; t < nent * 32; t += kWG) {
+    const int e = t >> 5, j = t & 31;
+    int own;
+    const float* xyz = entry_xyz(e, own);
     double dummy;
-    const bool bad = lane < 24 && lattice_of(xyz[lane], pr.D[lane % 3], dummy) != 0u;
-    const unsigned long long bm = __ballot(bad);
+    const bool bad = j < 24 && lattice_of(xyz[j], pr.D[j % 3], dummy) != 0u;
+    const unsigned long long bm = __ballot(bad) >> (lane & 32);  // this entry's half of the wave
     const bool bad_own = (bm >> (own * 12)) & 0xfffull, bad_oth = (bm >> ((1 - own) * 12)) & 0xfffull;
-    int nunits = 0;
+    int ok = 0;
     if (!bad_own) {
       double L[4][3];
       for (int q = 0; q < 4; ++q)
         for (int c = 0; c < 3; ++c) L[q][c] = ((double)xyz[own * 12 + q * 3 + c] + 0.5) * kLat;
       const double vol = orient(L[0], L[1], L[2], L[3]);
-      if (vol > 0.0 && !bad_oth) {
-        setup_raster(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, s_rts[e]);
-        nunits = (s_rts[e].nrows + 63) >> 6;
-      } else if (!(vol > 0.0) && v == 0 && PARTIAL && lane == 0) {
+      if (vol > 0.0 && !bad_oth)
+        ok = 1;
+      else if (!(vol > 0.0) && e < 2 * na && PARTIAL && j == 0)  // candidate version only
         atomicOr(&s_flags, own == 0 ? DSM_FLAG_INV_MOVING : DSM_FLAG_INV_FIXED);
-      }
     }
+    if (j == 0) s_units[e] = ok;
+  }
+  __syncthreads();
+  // face functions, affine map and bounding box: 16 threads per entry
+  for (int t = tid; t < nent * 16; t += kWG) {
+    const int e = t >> 4, k = t & 15;
+    if (k < kSetupTasks && s_units[e]) {
+      int own;
+      const float* xyz = entry_xyz(e, own);
+      setup_task(xyz + own * 12, xyz + (1 - own) * 12, pr.D, k, s_rts[e]);
+    }
+  }
+  __syncthreads();
+  // slice tables, one wave per entry, and the units
+  for (int e = wave; e < nent; e += kWaves) {
+    int nunits = 0;
+    if (uniform(s_units[e])) {
+      int own;
+      const float* xyz = entry_xyz(e, own);
+      setup_slices(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, s_rts[e]);
+      nunits = (s_rts[e].nrows + 63) >> 6;
+    }
+    wave_sync();
     if (lane == 0) s_units[e] = nunits;
   }
   for (int e = tid; e < nent * kWaves; e += kWG) s_part[e] = 0.0;
@@ -770,6 +832,8 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
       carry += __popcll(M1);
       if (q0 + 128 <= nvox)
         sweep_pair<false>(wr, sc, q0, nvox, lane, r0, r1, jx, jy, jz, sum, comp);
+      else if (q0 + 64 >= nvox)
+        sweep_one(wr, sc, q0, nvox, lane, r0, jx, jy, jz, sum, comp);
       else
         sweep_pair<true>(wr, sc, q0, nvox, lane, r0, r1, jx, jy, jz, sum, comp);
     }
