@@ -250,7 +250,7 @@ dsm_status dsm_problem_timing_read(dsm_problem* p, float* ms, int32_t max_n, int
  * elements).  Not part of the paper's method: a small MLP 192 -> 128 -> 128 ->
  * 3 (ReLU) predicts the three objective deltas of a candidate from local
  * features and is trained on the deltas that dsm_eval_partial computes
- * exactly; the exact evaluation stays the judge of every accepted change.
+ * exactly; the exact evaluation still decides every accepted change.
  * Matrix products run as BF16 matrix-core instructions with FP32 accumulation;
  * master weights and Adam state are FP32.
  *

@@ -1,8 +1,9 @@
 // Learned pre-screening of partial-evaluation candidates: a small MLP
 // (192 -> 128 -> 128 -> 3, ReLU) that predicts the objective deltas of a
 // single-point partial change from local features, trained on the exact deltas
-// the evaluator produces.  The exact evaluator remains the judge: screening only
-// decides which candidate is evaluated and whether it is evaluated at all.
+// the evaluator produces.  Acceptance still rests on the exact evaluator:
+// screening only chooses which candidate is evaluated and whether it is
+// evaluated at all.
 //
 // All matrix products run on gfx950 matrix cores: v_mfma_f32_16x16x32_bf16
 // (BF16 operands, FP32 accumulation).  Weights are kept in FP32 (master copy,
