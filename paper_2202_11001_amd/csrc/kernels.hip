@@ -887,7 +887,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // dissimilarity, writes per-tetrahedron terms, and in partial mode the
 // normalised sums over each group in ascending tetrahedron order.
 __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
-  __shared__ double s_terms[2][3][64];
   const double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
   const int lane = threadIdx.x;
@@ -914,10 +913,13 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
     a.flags[oi] = fl;
     if (a.vcount) a.vcount[oi] = cnt;
   }
+  // one lane per affected tetrahedron; the per-tetrahedron terms are summed
+  // over the wave in a fixed butterfly order (every lane ends with the same sum)
   const double* sims = simws + oi * a.nver * a.maxA;
   double accn[3] = {0, 0, 0}, acco[3] = {0, 0, 0};
   for (int base = 0; base < na; base += 64) {
     const int i = base + lane;
+    double tn[3] = {0, 0, 0}, to[3] = {0, 0, 0};
     for (int v = 0; v < a.nver; ++v) {
       double term[3] = {0, 0, 0};
       if (i < na) {
@@ -946,26 +948,18 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
           o[2] = term[2];
         }
       }
-      for (int c = 0; c < 3; ++c) s_terms[v][c][lane] = term[c];
+      for (int c = 0; c < 3; ++c) (v == 0 ? tn : to)[c] = term[c];
     }
-    __syncthreads();
-    if (a.partial && lane < 6) {
-      const int c = lane % 3;
-      const bool old = lane >= 3;
-      const int n = min(64, na - base);
-      double acc = 0.0;
-      if (!old) {
-        for (int k = 0; k < n; ++k) acc += s_terms[0][c][k];
-        accn[c] += acc;
-      } else if (a.nver == 2) {
-        for (int k = 0; k < n; ++k) acc += s_terms[1][c][k];
-        acco[c] += acc;
-      } else {
-        for (int k = 0; k < n; ++k) acc += a.terms_in[((size_t)s * pr.T + group_tet(a, g, base + k)) * 3 + c];
-        acco[c] += acc;
+    if (a.partial) {
+      if (a.nver == 1 && i < na) {  // current terms from the cache
+        const double* src = a.terms_in + ((size_t)s * pr.T + group_tet(a, g, i)) * 3;
+        for (int c = 0; c < 3; ++c) to[c] = src[c];
+      }
+      for (int c = 0; c < 3; ++c) {
+        accn[c] += wave_sum(tn[c]);
+        acco[c] += wave_sum(to[c]);
       }
     }
-    __syncthreads();
   }
   if (a.partial && lane < 6) {
     const int c = lane % 3;
