@@ -517,15 +517,19 @@ __device__ __forceinline__ void sweep_one(const WaveRows& wr, const SampleCtx& s
   sum = t;
 }
 
-__device__ __forceinline__ double len_mm(const double sp[3], const double a[3], const double b[3]) {
-  const double dx = (a[0] - b[0]) * sp[0], dy = (a[1] - b[1]) * sp[1], dz = (a[2] - b[2]) * sp[2];
+// Length in mm of b - a (voxel units, float or double components; float
+// components are widened exactly).
+template <class A, class B>
+__device__ __forceinline__ double len_mm(const double sp[3], const A a[3], const B b[3]) {
+  const double dx = ((double)a[0] - (double)b[0]) * sp[0], dy = ((double)a[1] - (double)b[1]) * sp[1],
+               dz = ((double)a[2] - (double)b[2]) * sp[2];
   return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
 // Sec. 2.3.2: deformation term of one tetrahedron (edges weighted 1/k_e, plus
 // the spoke from each vertex to the centroid of its opposite face); squared
 // length differences in mm between the two grids.
-__device__ double deformation_term(const DevProblem& pr, int t, const double S[4][3], const double Tg[4][3]) {
+__device__ double deformation_term(const DevProblem& pr, int t, const float S[4][3], const float Tg[4][3]) {
   const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
   double acc = 0.0;
   for (int e = 0; e < 6; ++e) {
@@ -537,8 +541,8 @@ __device__ double deformation_term(const DevProblem& pr, int t, const double S[4
     for (int r = 0; r < 4; ++r)
       if (r != q)
         for (int c = 0; c < 3; ++c) {
-          cs[c] += S[r][c];
-          ct[c] += Tg[r][c];
+          cs[c] += (double)S[r][c];
+          ct[c] += (double)Tg[r][c];
         }
     for (int c = 0; c < 3; ++c) {
       cs[c] /= 3.0;
@@ -553,21 +557,24 @@ __device__ double deformation_term(const DevProblem& pr, int t, const double S[4
 // Sec. 2.3.3: guidance points of image g inside tetrahedron (grid g) are mapped
 // into the other image and contribute the squared mm distance to the nearest
 // point of the same correspondence there.
-__device__ double guidance_term(const DevProblem& pr, const double L[2][4][3], const double V[2][4][3]) {
+__device__ double guidance_term(const DevProblem& pr, const float V[2][4][3]) {
   double acc = 0.0;
   for (int g = 0; g < 2; ++g) {
     if (pr.ng[g] == 0) continue;
-    const double vol = orient(L[g][0], L[g][1], L[g][2], L[g][3]);
+    double L[4][3];  // lattice coordinates of grid g's vertices (exact)
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 3; ++c) L[q][c] = ((double)V[g][q][c] + 0.5) * kLat;
+    const double vol = orient(L[0], L[1], L[2], L[3]);
     if (!(vol > 0.0)) continue;
     Faces f;
-    make_faces(L[g], f);
+    make_faces(L, f);
     for (int i = 0; i < pr.ng[g]; ++i) {
       const double U[3] = {pr.gpt[g][3 * i], pr.gpt[g][3 * i + 1], pr.gpt[g][3 * i + 2]};
       double o[4];
       if (!inside(f, U, o)) continue;
       double x[3] = {0, 0, 0};
       for (int q = 0; q < 4; ++q)
-        for (int c = 0; c < 3; ++c) x[c] += o[q] / vol * V[1 - g][q][c];
+        for (int c = 0; c < 3; ++c) x[c] += o[q] / vol * (double)V[1 - g][q][c];
       double best = INFINITY;
       const int corr = pr.gcorr[g][i];
       for (int j = 0; j < pr.ng[1 - g]; ++j) {
@@ -929,20 +936,21 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
         const int t = group_tet(a, g, i);
         const int4 tv = pr.tets[t];
         const int vid[4] = {tv.x, tv.y, tv.z, tv.w};
-        double L[2][4][3], V[2][4][3];
+        float V[2][4][3];
         unsigned bad = 0u;
         for (int gr = 0; gr < 2; ++gr)
           for (int q = 0; q < 4; ++q) {
             const float* src = vertex_src(a, s, g, v, vid[q], gr);
             for (int c = 0; c < 3; ++c) {
+              double u;
               V[gr][q][c] = src[c];
-              bad |= lattice_of(src[c], pr.D[c], L[gr][q][c]);
+              bad |= lattice_of(src[c], pr.D[c], u);
             }
           }
         if (!bad) {
           term[0] = sims[(size_t)v * a.maxA + i];
           term[1] = deformation_term(pr, t, V[0], V[1]);
-          term[2] = guidance_term(pr, L, V);
+          term[2] = guidance_term(pr, V);
         }
         if (v == 0 && a.terms_out) {
           double* o = a.terms_out + ((size_t)s * pr.T + t) * 3;
@@ -973,9 +981,13 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_finish(EvalArgs a) { finish_body(a, blockIdx.x); }
+// FP64 geometry per lane: the 3-wave target (at most 168 VGPRs, a few 8-byte
+// spills) ran the finish kernels 20 % faster than 2 waves without spills.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_finish(EvalArgs a) {
+  finish_body(a, blockIdx.x);
+}
 
-__global__ __launch_bounds__(64) void k_finish_batch(const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_finish_batch(const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off,
                                                      int n_jobs) {
   int j = 0;
   while (j + 1 < n_jobs && wg_off[j + 1] <= (int)blockIdx.x) ++j;
