@@ -44,7 +44,7 @@ void release(dsm_problem* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   void* bufs[] = {p->d_img, p->d_raw, p->d_tets, p->d_tet_w, p->d_star_off, p->d_star, p->d_gpt, p->d_gcorr,
-                  p->d_aff, p->d_aff_cnt, p->d_terms, p->d_simws, p->d_ident, p->d_cflags, p->d_ccount};
+                  p->d_aff, p->d_aff_cnt, p->d_order, p->d_terms, p->d_simws, p->d_ident, p->d_cflags, p->d_ccount};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -217,6 +217,7 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
     DSM_TRY(hipMemcpy(p->d_gcorr, gc.data(), sizeof(int) * gc.size(), hipMemcpyHostToDevice), "copy correspondences");
   DSM_TRY(dev_alloc(&p->d_aff, (size_t)std::max(1, p->max_F) * p->maxA), "hipMalloc affected sets");
   DSM_TRY(dev_alloc(&p->d_aff_cnt, (size_t)std::max(1, p->max_F)), "hipMalloc affected counts");
+  DSM_TRY(dev_alloc(&p->d_order, (size_t)std::max(1, p->max_F)), "hipMalloc element order");
   DSM_TRY(dev_alloc(&p->d_terms, (size_t)p->max_S * tp.T * 3), "hipMalloc term workspace");
   DSM_TRY(dev_alloc(&p->d_ident, p->identity.size()), "hipMalloc undeformed grid");
   DSM_TRY(hipMemcpy(p->d_ident, p->identity.data(), sizeof(float) * p->identity.size(), hipMemcpyHostToDevice),
@@ -393,6 +394,7 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
     return fail(DSM_ERR_ARG, "null argument");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_affected(p->dev, F, fos_off, fos_pts, p->max_pts, p->maxA, p->d_aff, p->d_aff_cnt, st);
+  if (e == hipSuccess && F <= kOrderMax) e = launch_order(F, p->d_aff_cnt, p->d_order, st);
   if (e != hipSuccess) return hip_fail(e, "affected-set launch");
   EvalArgs a{};
   a.pr = p->dev;
@@ -405,6 +407,7 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
   a.cand = cand;
   a.aff = p->d_aff;
   a.aff_cnt = p->d_aff_cnt;
+  a.order = F <= kOrderMax ? p->d_order : nullptr;
   a.maxA = p->maxA;
   a.nver = tet_terms_in ? 1 : 2;
   a.terms_in = tet_terms_in;
@@ -541,7 +544,9 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
   if (!b || (n_jobs > 0 && !jobs) || n_jobs < 0) return fail(DSM_ERR_ARG, "null argument");
   if (n_jobs > b->max_jobs) return fail(DSM_ERR_CAPACITY, "n_jobs = %d exceeds max_jobs = %d", n_jobs, b->max_jobs);
   std::vector<EvalArgs> args(n_jobs);
-  std::vector<int> off(n_jobs + 1, 0), foff(n_jobs + 1, 0);  // workgroup offsets: sweep, finish
+  // sweep: per-XCD slot offsets (a job of n workgroups takes ceil(n / 8) slots
+  // on each of the 8 XCDs); finish: workgroup offsets
+  std::vector<int> off(n_jobs + 1, 0), foff(n_jobs + 1, 0);
   size_t lds = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const dsm_partial_job& q = jobs[j];
@@ -564,6 +569,7 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
     a.cand = q.cand;
     a.aff = p->d_aff;
     a.aff_cnt = p->d_aff_cnt;
+    a.order = q.F <= kOrderMax ? p->d_order : nullptr;
     a.maxA = p->maxA;
     a.nver = q.tet_terms_in ? 1 : 2;
     a.terms_in = q.tet_terms_in;
@@ -577,7 +583,7 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
     a.nchunk = p->nchunk;
     a.cflags = p->d_cflags;
     a.ccount = p->d_ccount;
-    off[j + 1] = off[j] + q.S * q.F * a.nchunk;
+    off[j + 1] = off[j] + (q.S * q.F * a.nchunk + 7) / 8;
     foff[j + 1] = foff[j] + q.S * q.F;
     lds = std::max(lds, eval_lds_bytes(kMaxChunk, a.nver));
   }
@@ -585,9 +591,11 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   for (int j = 0; j < n_jobs && e == hipSuccess; ++j)
-    if (jobs[j].S > 0 && jobs[j].F > 0)
+    if (jobs[j].S > 0 && jobs[j].F > 0) {
       e = launch_affected(args[j].pr, jobs[j].F, jobs[j].fos_off, jobs[j].fos_pts, jobs[j].problem->max_pts,
                           args[j].maxA, args[j].aff ? jobs[j].problem->d_aff : nullptr, jobs[j].problem->d_aff_cnt, st);
+      if (e == hipSuccess && args[j].order) e = launch_order(jobs[j].F, jobs[j].problem->d_aff_cnt, jobs[j].problem->d_order, st);
+    }
   if (e != hipSuccess) return hip_fail(e, "affected-set launch");
   if (b->pending && (e = hipEventSynchronize(b->copied)) != hipSuccess) return hip_fail(e, "job table wait");
   memcpy(b->h_jobs, args.data(), sizeof(EvalArgs) * n_jobs);

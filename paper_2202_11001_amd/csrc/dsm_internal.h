@@ -76,6 +76,7 @@ struct EvalArgs {
   const float* cand;     // [S][fos_off[G]][2][3]
   const int* aff;        // [G][maxA] affected tetrahedra, ascending
   const int* aff_cnt;    // [G], -1 = malformed element
+  const int* order;      // [G] order of the elements over the XCDs (partial), or null
   int maxA;
   int nver;              // 1: candidate only; 2: candidate and current recomputed
   const double* terms_in;  // [S][T][3] cache of current terms or null
@@ -110,8 +111,15 @@ hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* fl
 hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
                            int maxA, int* aff, int* aff_cnt, hipStream_t stream);
 hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end, hipStream_t stream);
-// wg_off_dev [2][n_jobs + 1]: workgroup offsets of the jobs in the sweep, then in the finishing kernel
-hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, int total_finish,
+// Orders the G elements of a partial launch so that the XCDs' contiguous
+// ranges carry similar work (costs from the affected counts).  Only for
+// G <= kOrderMax; larger launches use a fixed interleaved order.
+constexpr int kOrderMax = 4096;
+hipError_t launch_order(int G, const int* aff_cnt, int* order, hipStream_t stream);
+// wg_off_dev [2][n_jobs + 1]: the jobs' per-XCD slot offsets in the sweep (a
+// job of n workgroups takes ceil(n / 8) slots on each XCD; per_xcd slots in
+// all), then their workgroup offsets in the finishing kernel (total_finish)
+hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int per_xcd, int total_finish,
                              size_t lds, hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
@@ -143,6 +151,7 @@ struct dsm_problem {
   int* d_gcorr = nullptr;
   int* d_aff = nullptr;         // [max_F][maxA]
   int* d_aff_cnt = nullptr;     // [max_F]
+  int* d_order = nullptr;       // [max_F] element order of the last partial launch
   double* d_terms = nullptr;    // [max_S][T][3] workspace for full evaluation
   double* d_simws = nullptr;    // swept dissimilarity per (solution, group, version, tetrahedron)
   size_t simws_len = 0;

@@ -109,6 +109,22 @@ __device__ __forceinline__ int xcd_logical(int bid, int n) {
   return x * q + min(x, r) + k;
 }
 
+// Element order of a single-problem partial launch: every eighth element,
+// starting from 0, then from 1, and so on.  The logical workgroup space is
+// element-major and each XCD takes a contiguous range of it, so in mesh order
+// the XCDs holding the border layers (whose points have smaller stars) would
+// finish early; interleaved, every XCD takes elements from the whole mesh.
+// Returns the element at position gp of that order, for G elements.
+__device__ __forceinline__ int interleaved_group(int gp, int G) {
+  int r = 0, base = 0;
+  for (; r < 7; ++r) {
+    const int cnt = (G - r + 7) >> 3;  // elements g < G with g % 8 == r
+    if (gp < base + cnt) break;
+    base += cnt;
+  }
+  return ((gp - base) << 3) + r;
+}
+
 // Makes LDS writes of some lanes visible to the other lanes of the same wave
 // (and keeps the compiler from moving LDS accesses across this point).
 __device__ __forceinline__ void wave_sync() {
@@ -663,16 +679,18 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 // simws[((s*G + g)*nver + v)*maxA + i].  Workgroups are numbered (group, chunk,
 // solution) with the solution fastest, so the workgroups resident on an XCD
 // sweep the same few tetrahedra of many solutions and share their image
-// region in L2.  Partial mode also writes the chunk's constraint flags and
+// region in L2; with `interleave` the groups follow interleaved_group's order.
+// Partial mode also writes the chunk's constraint flags and
 // candidate voxel count to cflags / ccount [S][G][nchunk]; k_finish combines
 // them.
 template <int PARTIAL>
-__device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsigned char* smem) {
+__device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsigned char* smem, bool interleave) {
   double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   const int nchunk = PARTIAL ? a.nchunk : 1;
-  const int g = logical / (a.S * nchunk), rem = logical - g * (a.S * nchunk);
+  const int gl = logical / (a.S * nchunk), rem = logical - gl * (a.S * nchunk);
+  const int g = PARTIAL && a.order ? a.order[gl] : (interleave ? interleaved_group(gl, a.G) : gl);
   const int c = rem / a.S, s = rem - c * a.S;
   const int nver = a.nver;
   const EvalLayout Lay = eval_layout(kMaxChunk, nver);
@@ -873,22 +891,32 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
 template <int PARTIAL>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_sweep(EvalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G * (PARTIAL ? a.nchunk : 1)), smem);
+  sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G * (PARTIAL ? a.nchunk : 1)), smem, PARTIAL != 0);
 }
 
-// Several problems in one launch: workgroup -> job by the job table's
-// workgroup offsets (the XCD mapping is applied to the concatenated list).
+// Several problems in one launch.  Each job's workgroup range is split into 8
+// equal contiguous parts, part x running on XCD x (hardware workgroup ids go
+// round-robin over the XCDs): xcd_off[j] is the first per-XCD slot of job j,
+// and a job with n workgroups takes ceil(n / 8) slots on every XCD, the
+// surplus slots exiting at once.  So every XCD gets an eighth of every job
+// (jobs of very different tetrahedron sizes would otherwise load the XCDs
+// unevenly), and within a part the workgroups of one element's solutions stay
+// together.  Elements follow interleaved_group's order within a job.
 // Arguments read through the job table take more registers than kernel
 // arguments; the 7-wave target (at most 72 VGPRs, one 8-byte spill in the
 // set-up) runs small problems 5 % faster than 6 waves without spills.
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_batch(
-    const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off, int n_jobs, int total) {
+    const EvalArgs* __restrict__ jobs, const int* __restrict__ xcd_off, int n_jobs) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lg = xcd_logical(blockIdx.x, total);
+  const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
   int j = 0;
-  while (j + 1 < n_jobs && wg_off[j + 1] <= lg) ++j;
+  while (j + 1 < n_jobs && xcd_off[j + 1] <= k) ++j;
   j = uniform(j);
-  sweep_body<1>(jobs[j], lg - wg_off[j], smem);
+  const EvalArgs& a = jobs[j];
+  const int n8 = uniform(xcd_off[j + 1] - xcd_off[j]);
+  const int logical = x * n8 + (k - uniform(xcd_off[j]));
+  if (logical >= a.S * a.G * a.nchunk) return;
+  sweep_body<1>(a, logical, smem, true);
 }
 
 // ------------------------------------------------------------ finishing kernel
@@ -1199,6 +1227,50 @@ hipError_t launch_fold(const DevProblem& pr, int S, const float* X, uint32_t* fl
   return e;
 }
 
+// Element order of a partial launch (G <= kOrderMax): the elements sorted by
+// their number of affected tetrahedra, descending (ties by index), are dealt
+// to the 8 XCDs in rounds of 8 in alternating direction (0..7, 7..0, ...); the
+// order lists XCD 0's elements, then XCD 1's, and so on.  Each XCD's
+// contiguous range of the element-major workgroup space then holds elements of
+// similar total cost.  Bitonic sort of (cost, index) keys in LDS, one
+// workgroup.
+__global__ __launch_bounds__(1024) void k_order(int G, const int* __restrict__ aff_cnt, int* __restrict__ order) {
+  __shared__ unsigned long long key[kOrderMax];
+  const int t = threadIdx.x;
+  int n = 1;
+  while (n < G) n <<= 1;
+  for (int i = t; i < n; i += 1024)
+    key[i] = i < G ? ((unsigned long long)(0xffffffffu - (unsigned)max(aff_cnt[i], 0)) << 32) | (unsigned)i : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= n; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < n; i += 1024) {
+        const int l = i ^ j;
+        if (l > i) {
+          const unsigned long long u = key[i], v = key[l];
+          if ((u > v) == ((i & k) == 0)) {
+            key[i] = v;
+            key[l] = u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const int nb = G >> 4, rem = G & 15;
+  for (int i = t; i < G; i += 1024) {
+    const int r = i & 15, x = r < 8 ? r : 15 - r;
+    int start = 0;  // elements dealt to the XCDs before x
+    for (int y = 0; y < x; ++y) start += 2 * nb + (y < rem ? 1 : 0) + (15 - y < rem ? 1 : 0);
+    order[start + (i >> 4) * 2 + (r >= 8 ? 1 : 0)] = (int)(unsigned)(key[i] & 0xffffffffull);
+  }
+}
+
+hipError_t launch_order(int G, const int* aff_cnt, int* order, hipStream_t stream) {
+  if (G <= 0 || G > kOrderMax) return hipSuccess;
+  k_order<<<1, 1024, 0, stream>>>(G, aff_cnt, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
                            int maxA, int* aff, int* aff_cnt, hipStream_t stream) {
   k_affected<<<(F + 63) / 64, 64, 0, stream>>>(pr, F, fos_off, fos_pts, max_pts, maxA, aff, aff_cnt);
@@ -1221,10 +1293,10 @@ hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end
   return hipGetLastError();
 }
 
-hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int total, int total_finish,
+hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int per_xcd, int total_finish,
                              size_t lds, hipStream_t stream) {
-  if (total <= 0) return hipSuccess;
-  k_sweep_batch<<<(unsigned)total, kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs, total);
+  if (per_xcd <= 0) return hipSuccess;
+  k_sweep_batch<<<(unsigned)(8 * per_xcd), kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_finish_batch<<<(unsigned)total_finish, 64, 0, stream>>>(jobs_dev, wg_off_dev + (n_jobs + 1), n_jobs);
