@@ -355,6 +355,35 @@ dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int3
                                  float sigma, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
                                  void* stream);
 
+/* Distribution estimation of RV-GOMEA, the optimiser Sec. 2.2 builds on: its
+ * partial changes draw a FOS element's variables from a normal distribution
+ * estimated on selected solutions.  For single-point elements fos_pts dev [F]
+ * the variables are the point's 6 coordinates (source x y z, target x y z);
+ * coordinates pinned to the box are not variables.  Writes mean dev [F][6]
+ * (float64) over the solutions sel dev [n_sel] of X dev [S][2][P][3] (indices
+ * outside [0, S) are skipped) and chol dev [F][21] (float64): the lower
+ * Cholesky factor, row r holding columns 0..r, of the maximum-likelihood
+ * covariance (divisor: the number of solutions used) of the free coordinates;
+ * pinned rows and columns are 0, and a non-positive pivot (rank-deficient
+ * selection) gives a zero column.  An element with no valid solution or an
+ * invalid point gets zeros.  Errors: DSM_ERR_ARG (null pointers, negative
+ * sizes). */
+dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X, int32_t n_sel, const int32_t* sel,
+                                      int32_t F, const int32_t* fos_pts, double* mean, double* chol, void* stream);
+
+/* Candidates cand dev [S][F][K][2][3] drawn from the estimated distributions:
+ * mean + sqrt(mult[f]) L z on the free coordinates of point fos_pts[f], z
+ * standard normal from the same counter-based generator as
+ * dsm_sample_candidates (6 draws per candidate; counter + *counter_dev when
+ * counter_dev is given); pinned coordinates keep the solution's value; the
+ * result is clamped to the image box and rounded to the 1/128-voxel lattice
+ * (half to even).  mult dev [F] (float) are the distribution multipliers.  An
+ * invalid point gives NaN candidates (flagged non-finite by the evaluator).
+ * Errors: DSM_ERR_ARG. */
+dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
+                                const double* mean, const double* chol, const float* mult, uint64_t seed,
+                                uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream);
+
 /* Sec. 2.4 grid refinement for multi-resolution runs: each cube of both grids
  * is split into 8 cubes by points at the middle of every cube edge, the middle
  * of every face and the cube centre (face middles and centres are means of the

@@ -63,6 +63,109 @@ __global__ void k_sample(DevProblem pr, int S, const float* __restrict__ X, int 
   cand[e] = (float)v;
 }
 
+// ------------------------------------------------ estimated distributions
+// RV-GOMEA, on which Sec. 2.2 builds, draws the variables of a FOS element
+// from a normal distribution estimated on selected solutions of the
+// population.  For a single-point element the variables are the point's 6
+// coordinates (source grid x y z, target grid x y z); coordinates pinned to
+// the box (border points) are not variables.
+
+// Per element f: mean [F][6] of the point's coordinates over the solutions
+// sel[0..n_sel) (indices outside [0, S) are skipped), and chol [F][21], the
+// lower Cholesky factor (rows 0..5, row r holding columns 0..r) of their
+// maximum-likelihood covariance (divisor: the number of solutions used)
+// restricted to the free coordinates; pinned rows and columns are 0, and a
+// pivot that is not positive (a rank-deficient selection) gives a zero
+// column.  Sums run over sel in order, in FP64.
+__global__ void k_estimate(DevProblem pr, int S, const float* __restrict__ X, int n_sel, const int* __restrict__ sel,
+                           int F, const int* __restrict__ pts, double* __restrict__ mean, double* __restrict__ chol) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  double* mu = mean + (size_t)f * 6;
+  double* L = chol + (size_t)f * 21;
+  for (int c = 0; c < 6; ++c) mu[c] = 0.0;
+  for (int c = 0; c < 21; ++c) L[c] = 0.0;
+  const int p = pts[f];
+  if (p < 0 || p >= pr.P || n_sel < 1) return;
+  const int idx[3] = {p % pr.n[0], (p / pr.n[0]) % pr.n[1], p / (pr.n[0] * pr.n[1])};
+  bool fr[6];
+  for (int c = 0; c < 6; ++c) fr[c] = idx[c % 3] > 0 && idx[c % 3] < pr.n[c % 3] - 1;
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  int n = 0;
+  for (int i = 0; i < n_sel; ++i) {
+    const int si = sel[i];
+    if (si < 0 || si >= S) continue;
+    const float* x = X + (size_t)si * 6 * pr.P;
+    for (int c = 0; c < 6; ++c) m[c] += (double)x[((size_t)(c / 3) * pr.P + p) * 3 + c % 3];
+    ++n;
+  }
+  if (n == 0) return;
+  for (int c = 0; c < 6; ++c) m[c] /= n;
+  double C[21] = {0};
+  for (int i = 0; i < n_sel; ++i) {
+    const int si = sel[i];
+    if (si < 0 || si >= S) continue;
+    const float* x = X + (size_t)si * 6 * pr.P;
+    double d[6];
+    for (int c = 0; c < 6; ++c) d[c] = fr[c] ? (double)x[((size_t)(c / 3) * pr.P + p) * 3 + c % 3] - m[c] : 0.0;
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c <= r; ++c) C[r * (r + 1) / 2 + c] += d[r] * d[c];
+  }
+  for (int c = 0; c < 21; ++c) C[c] /= n;
+  double l[21] = {0};
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c <= r; ++c) {
+      double v = C[r * (r + 1) / 2 + c];
+      for (int t = 0; t < c; ++t) v -= l[r * (r + 1) / 2 + t] * l[c * (c + 1) / 2 + t];
+      if (c == r)
+        l[r * (r + 1) / 2 + r] = v > 0.0 ? sqrt(v) : 0.0;
+      else {
+        const double dc = l[c * (c + 1) / 2 + c];
+        l[r * (r + 1) / 2 + c] = dc > 0.0 ? v / dc : 0.0;
+      }
+    }
+  for (int c = 0; c < 6; ++c) mu[c] = m[c];
+  for (int c = 0; c < 21; ++c) L[c] = l[c];
+}
+
+// cand [S][F][K][2][3]: mean + sqrt(mult[f]) L z on the free coordinates of
+// single point pts[f], z ~ N(0, I) from the counter-based generator (6 draws
+// per candidate, counters as in k_sample); pinned coordinates keep the
+// solution's value; clamped to the image box and rounded to the 1/128-voxel
+// lattice (half to even).
+__global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ pts, int K,
+                             const double* __restrict__ mean, const double* __restrict__ chol,
+                             const float* __restrict__ mult, unsigned long long seed, unsigned long long counter,
+                             const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (counter_dev) counter += *counter_dev;
+  if (row >= (int64_t)S * F * K) return;
+  const int f = (int)((row / K) % F);
+  const int s = (int)(row / ((int64_t)F * K));
+  const int p = pts[f];
+  float* out = cand + row * 6;
+  if (p < 0 || p >= pr.P) {
+    for (int c = 0; c < 6; ++c) out[c] = NAN;  // flagged as non-finite by the evaluator
+    return;
+  }
+  const double* mu = mean + (size_t)f * 6;
+  const double* L = chol + (size_t)f * 21;
+  const double sc = sqrt((double)mult[f]);
+  double z[6];
+  for (int c = 0; c < 6; ++c) z[c] = normal(seed, counter * 0x100000000ull + (unsigned long long)(row * 6 + c));
+  const int idx[3] = {p % pr.n[0], (p / pr.n[0]) % pr.n[1], p / (pr.n[0] * pr.n[1])};
+  for (int c = 0; c < 6; ++c) {
+    const int g = c / 3, a = c % 3;
+    double v = X[(((size_t)s * 2 + g) * pr.P + p) * 3 + a];
+    if (idx[a] > 0 && idx[a] < pr.n[a] - 1) {
+      double w = 0.0;
+      for (int t = 0; t <= c; ++t) w += L[c * (c + 1) / 2 + t] * z[t];
+      v = fmin(fmax(mu[c] + sc * w, -0.5), pr.D[a] - 0.5);
+    }
+    out[c] = (float)(rint((v + 0.5) * kLat) / kLat - 0.5);
+  }
+}
+
 // Accept / apply one colour class of single-point elements.
 __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, const int* __restrict__ pts,
                          const float* __restrict__ cand, const double* __restrict__ part_old,
@@ -151,6 +254,28 @@ dsm_status dsm_sample_candidates(dsm_problem* p, int32_t S, const float* X, int3
   k_sample<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(p->dev, S, X, F, fos_pts, K, sigma, seed,
                                                                        counter, (const unsigned long long*)counter_dev,
                                                                        cand);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X, int32_t n_sel, const int32_t* sel,
+                                      int32_t F, const int32_t* fos_pts, double* mean, double* chol, void* stream) {
+  if (!p || S < 0 || F < 0 || n_sel < 0) return DSM_ERR_ARG;
+  if (F == 0) return DSM_OK;  // empty buffers may be null
+  if (!fos_pts || !mean || !chol || (n_sel > 0 && (!X || !sel))) return DSM_ERR_ARG;
+  k_estimate<<<(unsigned)((F + 63) / 64), 64, 0, (hipStream_t)stream>>>(p->dev, S, X, n_sel, sel, F, fos_pts, mean,
+                                                                        chol);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
+                                const double* mean, const double* chol, const float* mult, uint64_t seed,
+                                uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream) {
+  if (!p || S < 0 || F < 0 || K < 1) return DSM_ERR_ARG;
+  const int64_t n = (int64_t)S * F * K;
+  if (n == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !fos_pts || !mean || !chol || !mult || !cand) return DSM_ERR_ARG;
+  k_sample_est<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+      p->dev, S, X, F, fos_pts, K, mean, chol, mult, seed, counter, (const unsigned long long*)counter_dev, cand);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 

@@ -81,6 +81,8 @@ def lib():
             "dsm_problem_timing_read": ([V, V, I, V], I),
             "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_estimate_distributions": ([V, I, V, I, V, I, V, V, V, V], I),
+            "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
             "dsm_batch_destroy": ([V], I),
@@ -284,6 +286,30 @@ class Problem:
             out = torch.empty(shape, dtype=torch.float32, device=X.device)
         _check(lib().dsm_sample_candidates(self._h, S, _dptr(X), F, _dptr(pts), int(K), float(sigma), int(seed),
                                            int(counter), _dptr(counter_dev), _dptr(out), _stream(stream)))
+        return out
+
+    def estimate_distributions(self, X, sel, pts, stream=None):
+        """(mean [F][6], lower Cholesky factor [F][21]) float64 of the single
+        points pts [F] over the selected solutions sel [n] (int32) of X."""
+        torch = _torch()
+        F = pts.shape[0]
+        mean = torch.empty((F, 6), dtype=torch.float64, device=X.device)
+        chol = torch.empty((F, 21), dtype=torch.float64, device=X.device)
+        _check(lib().dsm_estimate_distributions(self._h, X.shape[0], _dptr(X), sel.shape[0], _dptr(sel), F, _dptr(pts),
+                                                _dptr(mean), _dptr(chol), _stream(stream)))
+        return mean, chol
+
+    def sample_estimated(self, X, pts, K, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None):
+        """Candidates [S][F][K][2][3] (K > 1) or [S][F][2][3] (K == 1) drawn from
+        N(mean, mult * L L^T) on the free coordinates (mult float32 [F])."""
+        torch = _torch()
+        S, F = X.shape[0], pts.shape[0]
+        if out is None:
+            shape = (S, F, 2, 3) if K == 1 else (S, F, K, 2, 3)
+            out = torch.empty(shape, dtype=torch.float32, device=X.device)
+        _check(lib().dsm_sample_estimated(self._h, S, _dptr(X), F, _dptr(pts), int(K), _dptr(mean), _dptr(chol),
+                                          _dptr(mult), int(seed), int(counter), _dptr(counter_dev), _dptr(out),
+                                          _stream(stream)))
         return out
 
     def accept(self, X, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,

@@ -11,8 +11,17 @@ the update of coordinates, term cache and objectives all run in the library's
 kernels.  The elitist archive (non-dominated objective vectors) and the
 hypervolume are kept on the host.
 
-This is not RV-GOMEA: candidates are isotropic Gaussian moves, not samples of
-an estimated distribution.
+Candidates are isotropic Gaussian moves around the current position
+(``sampler="isotropic"``), or (``sampler="estimated"``) samples of a normal
+distribution per point estimated on the selected solutions, as RV-GOMEA's
+partial changes draw them: each generation selects the ``tau`` fraction of the
+population with the fewest dominating solutions (ties: smallest sum of range-
+normalised objectives), estimates per point the mean and full covariance of
+its 6 coordinates on the GPU, and samples N(mean, c L L^T) with a per-point
+multiplier c that grows by 1/0.9 after a generation in which the point's change
+was accepted by some solution and shrinks by 0.9 otherwise (within [0.05, 10]).
+Clustering, anticipated mean shift and the full multiplier schedule of
+RV-GOMEA are not built.
 """
 from __future__ import annotations
 
@@ -122,7 +131,7 @@ class Optimiser:
     host work.  Eager and graph generations give bit-identical results."""
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
-                 keep_solutions=False):
+                 keep_solutions=False, sampler="isotropic", tau=0.35):
         import torch
         self.torch = torch
         self.p = problem
@@ -157,6 +166,15 @@ class Optimiser:
         self._graph = None
         self._graph_sur = None
         self._outs = None
+        if sampler not in ("isotropic", "estimated"):
+            raise ValueError(f"unknown sampler {sampler!r}")
+        self.sampler = sampler
+        if sampler == "estimated":
+            if self.use_graph:
+                raise ValueError("the estimated sampler runs eagerly (its selection needs the current objectives)")
+            self.tau = float(tau)
+            self.mult = [torch.ones(len(c), dtype=torch.float32, device=dev) for c in self.classes]
+            self._dist = None
 
     @property
     def counter(self):
@@ -178,11 +196,10 @@ class Optimiser:
         for c, (pts, off) in enumerate(zip(self.classes, self.offs)):
             F = pts.shape[0]
             if surrogate is None:
-                cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
+                cand = self._sample(c, pts, 1)
                 mask = None
             else:
-                candK = self.p.sample_candidates(self.X, pts, self.K, self.sigma, self.seed, c + 1,
-                                                 counter_dev=self.counter_dev)
+                candK = self._sample(c, pts, self.K)
                 _, mask, _, cand = surrogate.screen(self.p, self.X, pts, candK, obj=self.obj, archive=self.arch_dev)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
                                                      tet_terms_new=self.terms_cand, mask=mask)
@@ -197,10 +214,34 @@ class Optimiser:
         self.counter_dev += 8
         return outs
 
+    def _sample(self, c, pts, K):
+        if self.sampler == "isotropic":
+            return self.p.sample_candidates(self.X, pts, K, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
+        mean, chol = self._dist[c]
+        return self.p.sample_estimated(self.X, pts, K, mean, chol, self.mult[c], self.seed, c + 1,
+                                       counter_dev=self.counter_dev)
+
+    def select(self):
+        """Indices (int32, device) of the tau fraction of the population with the
+        fewest dominating solutions; ties by the smallest sum of objectives
+        normalised to the population's range."""
+        torch = self.torch
+        o = self.obj
+        le = (o[None, :, :] <= o[:, None, :]).all(-1)
+        lt = (o[None, :, :] < o[:, None, :]).any(-1)
+        dominated_by = (le & lt).sum(1).to(torch.float64)
+        lo, hi = o.min(0).values, o.max(0).values
+        nrm = ((o - lo) / torch.clamp(hi - lo, min=1e-300)).sum(1)
+        n = max(1, int(round(self.tau * self.S)))
+        return torch.argsort(dominated_by * 4.0 + nrm, stable=True)[:n].to(torch.int32).contiguous()
+
     def generation(self, surrogate=None, log=None):
         """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
         torch = self.torch
         self._load_archive()
+        if self.sampler == "estimated":
+            sel = self.select()
+            self._dist = [self.p.estimate_distributions(self.X, sel, pts) for pts in self.classes]
         if self.use_graph and self.collect is None:
             if self._graph is None or self._graph_sur is not surrogate:
                 # warm up once on a side stream, then capture
@@ -215,6 +256,11 @@ class Optimiser:
             outs = self._outs
         else:
             outs = self._steps(surrogate)
+        if self.sampler == "estimated":
+            for c, (_, acc, *_) in enumerate(outs):
+                hit = acc.any(dim=0)
+                self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
+                                           torch.clamp(self.mult[c] * 0.9, min=0.05))
         n_exact = sum(self.S * acc.shape[1] if mask is None else int(mask.sum().item()) for mask, acc, *_ in outs)
         n_acc = sum(int(acc.sum().item()) for _, acc, *_ in outs)
         if self.keep_solutions:
@@ -242,12 +288,12 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
-        K=4, target_hv=None, log_every=0, graph=False):
+        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
-    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph)
+    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate

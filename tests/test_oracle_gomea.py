@@ -1,0 +1,80 @@
+"""Pins of the distribution-estimation reference (oracle/gomea_ref.py) against
+hand-computed values, numpy's Cholesky and the defining identities."""
+import numpy as np
+
+from oracle import gomea_ref as G
+
+MESH = (4, 4, 3)
+P = 48
+INTERIOR = 1 + 4 * (1 + 4 * 1)  # (1, 1, 1)
+CORNER = 0
+FACE = 1 + 4 * 1  # (1, 1, 0): z pinned
+
+
+def _population(S, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(10.0, 2.0, size=(S, 2, P, 3)).astype(np.float32)
+
+
+def test_free_axes():
+    assert G.free_axes(INTERIOR, MESH).all()
+    assert not G.free_axes(CORNER, MESH).any()
+    assert list(G.free_axes(FACE, MESH)) == [True, True, False, True, True, False]
+
+
+def test_hand_computed_mean_and_covariance():
+    X = np.zeros((3, 2, P, 3), dtype=np.float32)
+    X[:, 0, INTERIOR, 0] = [0.0, 1.0, 2.0]   # source x: mean 1, variance 2/3
+    X[:, 1, INTERIOR, 2] = [4.0, 4.0, 7.0]   # target z: mean 5, variance 2
+    mean, cov, chol = G.estimate(X, [0, 1, 2], [INTERIOR], MESH)
+    assert np.allclose(mean[0], [1, 0, 0, 0, 0, 5])
+    want = np.zeros((6, 6))
+    want[0, 0] = 2.0 / 3.0
+    want[5, 5] = 2.0
+    want[0, 5] = want[5, 0] = ((-1) * (-1) + 0 * (-1) + 1 * 2) / 3.0  # = 1
+    assert np.allclose(cov[0], want)
+    L = chol[0]
+    assert np.allclose(L @ L.T, want)
+    assert np.allclose(L[0, 0], np.sqrt(2.0 / 3.0)) and np.allclose(L[5, 0], 1.0 / np.sqrt(2.0 / 3.0))
+
+
+def test_positive_definite_case_matches_numpy_cholesky():
+    X = _population(40, seed=1)
+    mean, cov, chol = G.estimate(X, list(range(0, 40, 2)), [INTERIOR], MESH)
+    x = np.array([np.concatenate([X[s, 0, INTERIOR], X[s, 1, INTERIOR]]) for s in range(0, 40, 2)], dtype=np.float64)
+    assert np.allclose(mean[0], x.mean(axis=0))
+    assert np.allclose(cov[0], np.cov(x.T, bias=True))
+    assert np.allclose(chol[0], np.linalg.cholesky(np.cov(x.T, bias=True)))
+
+
+def test_rank_deficient_and_pinned():
+    X = _population(10, seed=2)
+    # 3 solutions: rank <= 2 covariance; the factor still reproduces it
+    _, cov, chol = G.estimate(X, [1, 4, 7], [INTERIOR], MESH)
+    assert np.allclose(chol[0] @ chol[0].T, cov[0], atol=1e-12)
+    assert np.all(np.triu(chol[0], 1) == 0)
+    # identical solutions: zero covariance and factor
+    Y = np.repeat(X[:1], 4, axis=0)
+    mean, cov, chol = G.estimate(Y, [0, 1, 2, 3], [INTERIOR], MESH)
+    assert np.allclose(mean[0], np.concatenate([X[0, 0, INTERIOR], X[0, 1, INTERIOR]]))
+    assert np.all(cov[0] == 0) and np.all(chol[0] == 0)
+    # a face point: the pinned z rows and columns are zero
+    _, cov, chol = G.estimate(X, list(range(10)), [FACE], MESH)
+    for c in (2, 5):
+        assert np.all(cov[0][c] == 0) and np.all(cov[0][:, c] == 0) and np.all(chol[0][:, c] == 0)
+    assert np.allclose(chol[0] @ chol[0].T, cov[0])
+
+
+def test_out_of_range_selection_is_skipped():
+    X = _population(6, seed=3)
+    a = G.estimate(X, [0, 2, 4], [INTERIOR], MESH)
+    b = G.estimate(X, [0, -1, 2, 6, 4, 99], [INTERIOR], MESH)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_packed_lower_layout():
+    L = np.tril(np.arange(36, dtype=float).reshape(6, 6))
+    packed = G.packed_lower(L)
+    assert len(packed) == 21
+    assert packed[0] == L[0, 0] and list(packed[1:3]) == [L[1, 0], L[1, 1]] and packed[20] == L[5, 5]
