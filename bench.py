@@ -249,6 +249,28 @@ def surrogate_run(gp, X, G, train_generations, name):
     print(json.dumps(res), flush=True)
 
 
+def sampler_run(gp, X, G, name):
+    """G generations with isotropic Gaussian candidates around the current
+    position vs G generations whose candidates are drawn from per-point normal
+    distributions estimated on the selected solutions (RV-GOMEA's partial
+    changes; tau = 0.35, adaptive multipliers), both eager from the same
+    population; hypervolume of the elitist archive against a reference point
+    fixed by the initial population."""
+    import torch
+    from paper_2202_11001_amd import optimizer as O
+    Xd = torch.from_numpy(X).to("cuda:0")
+    out = {"workload": name, "generations": G}
+    for sampler in ("isotropic", "estimated"):
+        log(f"{sampler} sampler: {G} generations")
+        lg, opt, _ = O.run(gp, Xd, G, sigma=1.0, seed=5, log_every=10, sampler=sampler)
+        out[sampler] = {"final_hv": lg.hypervolume[-1], "seconds": lg.seconds[-1], "hv": lg.hypervolume,
+                        "t": lg.seconds, "accepted": lg.accepted, "archive": lg.archive_size[-1]}
+        if sampler == "estimated":
+            m = torch.cat(opt.mult)
+            out[sampler]["multiplier"] = {"min": float(m.min()), "median": float(m.median()), "max": float(m.max())}
+    print(json.dumps(out), flush=True)
+
+
 def uneven_batch(steps=3, warmup=1):
     """Several registration problems of uneven size in one fused launch per
     pyramid level: the 12 problems of workloads.UNEVEN_PROBLEMS at the 2x
@@ -438,6 +460,8 @@ def main():
     ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
                     help="plain vs surrogate-screened optimiser runs of G generations (hypervolume protocol)")
     ap.add_argument("--train-generations", type=int, default=30)
+    ap.add_argument("--sampler-run", type=int, default=0, metavar="G",
+                    help="G generations with isotropic vs estimated-distribution candidates (reported separately)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -473,6 +497,9 @@ def main():
         return gp.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0
 
     X = w.population(reject=reject)
+    if args.sampler_run:
+        sampler_run(gp, X, args.sampler_run, w.name)
+        return
     if args.surrogate_run:
         surrogate_run(gp, X, args.surrogate_run, args.train_generations, w.name)
         return
