@@ -71,6 +71,34 @@ def merge_archive(archive, new):
     return out[np.lexsort(out.T[::-1])]
 
 
+def merge_archive_device(arch, n, new):
+    """merge_archive on the device: arch float64 [capacity][3] holds the
+    archive in rows 0..n-1 (+inf after), new [m][3]; the non-dominated rows of
+    both (duplicates kept once) are written back to arch in lexicographic order,
+    the remaining rows set to +inf.  Returns their number."""
+    import torch
+    pts = torch.cat([arch[:n], new.to(torch.float64)])
+    M = pts.shape[0]
+    idx = torch.arange(M, device=pts.device)
+    keep = torch.empty(M, dtype=torch.bool, device=pts.device)
+    for b in range(0, M, 2048):
+        blk = pts[b:b + 2048]
+        le = (pts[None, :, :] <= blk[:, None, :]).all(-1)
+        lt = (pts[None, :, :] < blk[:, None, :]).any(-1)
+        eq = (pts[None, :, :] == blk[:, None, :]).all(-1)
+        earlier = idx[None, :] < idx[b:b + 2048, None]
+        keep[b:b + 2048] = ~(le & lt).any(1) & ~(eq & earlier).any(1)
+    out = pts[keep]
+    for c in (2, 1, 0):  # lexicographic: stable sorts from the last key
+        out = out[torch.argsort(out[:, c], stable=True)]
+    k = out.shape[0]
+    if k > arch.shape[0]:
+        raise ValueError(f"archive of {k} points exceeds the capacity {arch.shape[0]}")
+    arch[:k] = out
+    arch[k:] = float("inf")
+    return k
+
+
 def merge_archive_with(archive, archive_X, new, new_X):
     """merge_archive that carries a payload row (e.g. the solution) with every
     objective vector; among equal vectors the archived one is kept."""
@@ -151,18 +179,21 @@ class Optimiser:
         self.obj = obj
         self.keep_solutions = bool(keep_solutions)
         self.archive_X = None  # with keep_solutions: the solution of every archive row (host)
+        self.capacity = int(archive_capacity)
+        # elitist archive: on the host with keep_solutions, else on the device
+        # (arch_dev rows 0..n_arch-1, +inf after) with a host copy made on demand
+        self.arch_dev = torch.full((self.capacity, 3), float("inf"), dtype=torch.float64, device=dev)
+        self._archive = None
         if self.keep_solutions:
-            self.archive, self.archive_X = merge_archive_with(np.zeros((0, 3)), None, obj.cpu().numpy(),
-                                                              self.X.cpu().numpy())
+            self._archive, self.archive_X = merge_archive_with(np.zeros((0, 3)), None, obj.cpu().numpy(),
+                                                               self.X.cpu().numpy())
         else:
-            self.archive = nondominated(obj.cpu().numpy())
+            self.n_arch = merge_archive_device(self.arch_dev, 0, obj)
         self.ref = 1.1 * obj.cpu().numpy().max(axis=0)
         self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
         # sampler counter: generation g uses counters 8 g + 1 ... 8 g + 8
         self.counter_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.use_graph = bool(graph)
-        self.capacity = int(archive_capacity)
-        self.arch_dev = torch.full((self.capacity, 3), float("inf"), dtype=torch.float64, device=dev)
         self._graph = None
         self._graph_sur = None
         self._outs = None
@@ -180,7 +211,16 @@ class Optimiser:
     def counter(self):
         return int(self.counter_dev.item())
 
+    @property
+    def archive(self):
+        """The elitist archive's objective vectors (host, lexicographic order)."""
+        if self._archive is None:
+            self._archive = self.arch_dev[:self.n_arch].cpu().numpy()
+        return self._archive
+
     def _load_archive(self):
+        if not self.keep_solutions:
+            return  # the device archive is current
         n = len(self.archive)
         if n > self.capacity:
             raise ValueError(f"archive of {n} points exceeds the capacity {self.capacity}")
@@ -264,10 +304,11 @@ class Optimiser:
         n_exact = sum(self.S * acc.shape[1] if mask is None else int(mask.sum().item()) for mask, acc, *_ in outs)
         n_acc = sum(int(acc.sum().item()) for _, acc, *_ in outs)
         if self.keep_solutions:
-            self.archive, self.archive_X = merge_archive_with(self.archive, self.archive_X, self.obj.cpu().numpy(),
-                                                              self.X.cpu().numpy())
+            self._archive, self.archive_X = merge_archive_with(self._archive, self.archive_X, self.obj.cpu().numpy(),
+                                                               self.X.cpu().numpy())
         else:
-            self.archive = merge_archive(self.archive, self.obj.cpu().numpy())
+            self.n_arch = merge_archive_device(self.arch_dev, self.n_arch, self.obj)
+            self._archive = None
         return n_exact, n_acc
 
     def hypervolume(self):
