@@ -8,8 +8,9 @@ or K candidates of which the surrogate picks one and decides whether to
 evaluate it exactly (screened); exact partial evaluation, acceptance (feasible
 and improving: Pareto improvement or not dominated by the elitist archive) and
 the update of coordinates, term cache and objectives all run in the library's
-kernels.  The elitist archive (non-dominated objective vectors) and the
-hypervolume are kept on the host.
+kernels.  The elitist archive (non-dominated objective vectors) is merged on
+the device after every generation (on the host when its solutions are kept
+too); the hypervolume is computed on the host.
 
 Candidates are isotropic Gaussian moves around the current position
 (``sampler="isotropic"``), or (``sampler="estimated"``) samples of a normal
