@@ -412,6 +412,19 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
                       double* terms_cache, double* obj, int32_t n_archive, const double* archive, uint8_t* accepted,
                       void* stream);
 
+/* dsm_accept for elements of any number of points (e.g. the paper's per-cube
+ * tetrahedron elements, Sec. 2.2): element f has the points
+ * fos_pts[fos_off[f] .. fos_off[f+1]) and its candidate coordinates are
+ * cand dev [S][fos_off[F]][2][3], the layout of dsm_eval_partial.  The
+ * elements of one call must have pairwise disjoint affected tetrahedra.  An
+ * accepted change writes all of its points and copies the candidate terms of
+ * the union of their stars. */
+dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_off,
+                               const int32_t* fos_pts, const float* cand, const double* part_old,
+                               const double* part_new, const uint32_t* flags, const double* terms_cand,
+                               double* terms_cache, double* obj, int32_t n_archive, const double* archive,
+                               uint8_t* accepted, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -167,8 +167,8 @@ __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, 
 }
 
 // Accept / apply one colour class of single-point elements.
-__global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, const int* __restrict__ pts,
-                         const float* __restrict__ cand, const double* __restrict__ part_old,
+__global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, const int* __restrict__ off,
+                         const int* __restrict__ pts, const float* __restrict__ cand, const double* __restrict__ part_old,
                          const double* __restrict__ part_new, const uint32_t* __restrict__ flags,
                          const double* __restrict__ terms_cand, double* __restrict__ cache,
                          const double* __restrict__ obj, int n_arch, const double* __restrict__ arch,
@@ -204,11 +204,18 @@ __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, con
   }
   if (accepted) accepted[e] = acc ? 1 : 0;
   if (!acc) return;
-  const int p = pts[f];
-  for (int c = 0; c < 6; ++c) X[(((size_t)s * 2 + c / 3) * pr.P + p) * 3 + c % 3] = cand[(size_t)e * 6 + c];
-  for (int j = pr.star_off[p]; j < pr.star_off[p + 1]; ++j) {
-    const size_t t = (size_t)s * pr.T + pr.star[j];
-    for (int o = 0; o < 3; ++o) cache[t * 3 + o] = terms_cand[t * 3 + o];
+  // the element's points: pts[off[f] .. off[f+1]) with candidates at
+  // [s][off[F]][2][3], or the single point pts[f] without off
+  const int j0 = off ? off[f] : f, j1 = off ? off[f + 1] : f + 1, n = off ? off[F] : F;
+  for (int j = j0; j < j1; ++j) {
+    const int p = pts[j];
+    if (p < 0 || p >= pr.P) continue;  // such elements are flagged by the evaluator
+    for (int c = 0; c < 6; ++c)
+      X[(((size_t)s * 2 + c / 3) * pr.P + p) * 3 + c % 3] = cand[((size_t)s * n + j) * 6 + c];
+    for (int k = pr.star_off[p]; k < pr.star_off[p + 1]; ++k) {
+      const size_t t = (size_t)s * pr.T + pr.star[k];
+      for (int o = 0; o < 3; ++o) cache[t * 3 + o] = terms_cand[t * 3 + o];
+    }
   }
 }
 
@@ -299,8 +306,26 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
     return DSM_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (F > 0)
-    k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, fos_pts, cand, part_old, part_new, flags, terms_cand,
-                                                   terms_cache, obj, n_archive, archive, accepted);
+    k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, nullptr, fos_pts, cand, part_old, part_new, flags,
+                                                   terms_cand, terms_cache, obj, n_archive, archive, accepted);
+  if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
+  return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_off,
+                               const int32_t* fos_pts, const float* cand, const double* part_old,
+                               const double* part_new, const uint32_t* flags, const double* terms_cand,
+                               double* terms_cache, double* obj, int32_t n_archive, const double* archive,
+                               uint8_t* accepted, void* stream) {
+  if (!p || S < 0 || F < 0 || n_archive < 0 || (n_archive > 0 && !archive) || S > p->max_S) return DSM_ERR_ARG;
+  if (S == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !terms_cache || !obj ||
+      (F > 0 && (!fos_off || !fos_pts || !cand || !part_old || !part_new || !flags || !terms_cand)))
+    return DSM_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (F > 0)
+    k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, fos_off, fos_pts, cand, part_old, part_new, flags,
+                                                   terms_cand, terms_cache, obj, n_archive, archive, accepted);
   if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
   return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }

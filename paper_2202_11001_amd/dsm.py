@@ -84,6 +84,7 @@ def lib():
             "dsm_estimate_distributions": ([V, I, V, I, V, I, V, V, V, V], I),
             "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
+            "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
             "dsm_batch_destroy": ([V], I),
             "dsm_eval_partial_batch": ([V, I, V, V], I),
@@ -318,6 +319,16 @@ class Problem:
         _check(lib().dsm_accept(self._h, X.shape[0], _dptr(X), pts.shape[0], _dptr(pts), _dptr(cand),
                                 _dptr(part_old), _dptr(part_new), _dptr(flags), _dptr(terms_cand), _dptr(terms_cache),
                                 _dptr(obj), na, _dptr(archive), _dptr(accepted), _stream(stream)))
+
+    def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
+                        accepted=None, stream=None):
+        """accept for elements of several points (CSR off [F+1], pts), candidates
+        in the partial-evaluation layout [S][off[F]][2][3]."""
+        na = 0 if archive is None else archive.shape[0]
+        _check(lib().dsm_accept_elements(self._h, X.shape[0], _dptr(X), off.shape[0] - 1, _dptr(off), _dptr(pts),
+                                         _dptr(cand), _dptr(part_old), _dptr(part_new), _dptr(flags),
+                                         _dptr(terms_cand), _dptr(terms_cache), _dptr(obj), na, _dptr(archive),
+                                         _dptr(accepted), _stream(stream)))
 
     @property
     def pitch(self):

@@ -42,6 +42,16 @@ def parity_classes(mesh):
     return [np.nonzero(cls == c)[0].astype(np.int32) for c in range(8)]
 
 
+def cube_classes(mesh):
+    """Cube indices of the 27 classes of equal (i, j, k) mod 3.  The stars of
+    the corners of two cubes of one class share no tetrahedron, so changes to
+    one tetrahedron per cube of a class are independent."""
+    nx, ny, nz = (int(n) - 1 for n in mesh)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cls = ((i % 3) + 3 * (j % 3) + 9 * (k % 3)).ravel()
+    return [c for c in (np.nonzero(cls == q)[0].astype(np.int64) for q in range(27)) if len(c)]
+
+
 def nondominated(points):
     """Rows of `points` (minimisation) not dominated by another row; duplicates kept once."""
     pts = np.unique(np.asarray(points, dtype=np.float64), axis=0)
@@ -160,7 +170,7 @@ class Optimiser:
     host work.  Eager and graph generations give bit-identical results."""
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
-                 keep_solutions=False, sampler="isotropic", tau=0.35):
+                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point"):
         import torch
         self.torch = torch
         self.p = problem
@@ -170,8 +180,22 @@ class Optimiser:
         self.seed = int(seed)
         self.K = int(K)
         dev = X.device
-        self.classes = [torch.from_numpy(c).to(dev) for c in parity_classes(problem.mesh)]
-        self.offs = [torch.arange(len(c) + 1, dtype=torch.int32, device=dev) for c in self.classes]
+        if fos not in ("point", "tetrahedron"):
+            raise ValueError(f"unknown FOS {fos!r}")
+        self.fos = fos
+        if fos == "point":
+            self.classes = [torch.from_numpy(c).to(dev) for c in parity_classes(problem.mesh)]
+            self.offs = [torch.arange(len(c) + 1, dtype=torch.int32, device=dev) for c in self.classes]
+        else:
+            # the paper's FOS (Sec. 2.2): per cube one of its 6 tetrahedra, drawn
+            # anew every generation; classes of cubes 3 apart run in parallel
+            if graph:
+                raise ValueError("the tetrahedron FOS runs eagerly (its elements are drawn every generation)")
+            self.cube_classes = cube_classes(problem.mesh)
+            self.tets = np.asarray(problem.topology()["tets"], dtype=np.int32)
+            self.generation_index = 0
+            self.classes = None  # drawn per generation
+            self.mult_pt = torch.ones(problem.P, dtype=torch.float32, device=dev)
         self.cache = torch.empty((self.S, problem.T, 3), dtype=torch.float64, device=dev)
         self.terms_cand = torch.zeros_like(self.cache)
         obj, flags = problem.eval_full(self.X, tet_terms=self.cache)
@@ -194,6 +218,7 @@ class Optimiser:
         self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
         # sampler counter: generation g uses counters 8 g + 1 ... 8 g + 8
         self.counter_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.n_classes = 8 if fos == "point" else len(self.cube_classes)
         self.use_graph = bool(graph)
         self._graph = None
         self._graph_sur = None
@@ -205,7 +230,8 @@ class Optimiser:
             if self.use_graph:
                 raise ValueError("the estimated sampler runs eagerly (its selection needs the current objectives)")
             self.tau = float(tau)
-            self.mult = [torch.ones(len(c), dtype=torch.float32, device=dev) for c in self.classes]
+            if fos == "point":
+                self.mult = [torch.ones(len(c), dtype=torch.float32, device=dev) for c in self.classes]
             self._dist = None
 
     @property
@@ -229,10 +255,50 @@ class Optimiser:
         if n:
             self.arch_dev[:n].copy_(self.torch.from_numpy(np.ascontiguousarray(self.archive)))
 
+    def _tet_steps(self, surrogate):
+        """One generation of the paper's FOS: per class of cubes, one random
+        tetrahedron per cube, its 4 points sampled together (isotropic, or from
+        the per-point estimated distributions), evaluated and accepted."""
+        torch = self.torch
+        if surrogate is not None or self.collect is not None:
+            raise ValueError("screening and training-row collection support single-point elements only")
+        dev = self.X.device
+        rng = np.random.default_rng([self.seed, self.generation_index])
+        self.generation_index += 1
+        sel = self.select() if self.sampler == "estimated" else None
+        outs = []
+        for c, cubes in enumerate(self.cube_classes):
+            r = rng.integers(0, 6, size=len(cubes))
+            pts_h = self.tets[6 * cubes + r].reshape(-1).astype(np.int32)
+            pts = torch.from_numpy(pts_h).to(dev)
+            off = torch.from_numpy((4 * np.arange(len(cubes) + 1)).astype(np.int32)).to(dev)
+            if self.sampler == "isotropic":
+                cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
+            else:
+                mean, chol = self.p.estimate_distributions(self.X, sel, pts)
+                mult = self.mult_pt[pts.to(torch.int64)].contiguous()
+                cand = self.p.sample_estimated(self.X, pts, 1, mean, chol, mult, self.seed, c + 1,
+                                               counter_dev=self.counter_dev)
+            old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
+                                                     tet_terms_new=self.terms_cand)
+            acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
+            self.p.accept_elements(self.X, off, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
+                                   archive=self.arch_dev, accepted=acc)
+            if self.sampler == "estimated":
+                hit = acc.any(dim=0).repeat_interleave(4)
+                idx = pts.to(torch.int64)
+                m = self.mult_pt[idx]
+                self.mult_pt[idx] = torch.where(hit, torch.clamp(m / 0.9, max=10.0), torch.clamp(m * 0.9, min=0.05))
+            outs.append((None, acc, cand, old, new, flags))
+        self.counter_dev += self.n_classes
+        return outs
+
     def _steps(self, surrogate):
         """The 8 class steps of one generation, enqueued on the current stream
         without host synchronisation; returns per class (mask or None, accepted)."""
         torch = self.torch
+        if self.fos == "tetrahedron":
+            return self._tet_steps(surrogate)
         outs = []
         for c, (pts, off) in enumerate(zip(self.classes, self.offs)):
             F = pts.shape[0]
@@ -280,7 +346,7 @@ class Optimiser:
         """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
         torch = self.torch
         self._load_archive()
-        if self.sampler == "estimated":
+        if self.sampler == "estimated" and self.fos == "point":
             sel = self.select()
             self._dist = [self.p.estimate_distributions(self.X, sel, pts) for pts in self.classes]
         if self.use_graph and self.collect is None:
@@ -297,7 +363,7 @@ class Optimiser:
             outs = self._outs
         else:
             outs = self._steps(surrogate)
-        if self.sampler == "estimated":
+        if self.sampler == "estimated" and self.fos == "point":
             for c, (_, acc, *_) in enumerate(outs):
                 hit = acc.any(dim=0)
                 self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
@@ -330,12 +396,12 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
-        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35):
+        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point"):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
-    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau)
+    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate

@@ -215,3 +215,82 @@ def test_device_archive_merge_equals_host():
         got = arch_dev[:n].cpu().numpy()
         np.testing.assert_array_equal(got, host)
         assert torch.all(torch.isinf(arch_dev[n:]))
+
+
+def test_accept_tetrahedron_elements():
+    """Elements of 4 points (one tetrahedron per cube of one class of cubes 3
+    apart): accepted changes move all 4 points, the kept objectives and term
+    cache equal a fresh full evaluation, and single-point elements through the
+    CSR entry point give the same result as the single-point one."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    S = X.shape[0]
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    Xd = _t(X)
+    cache = torch.empty((S, gp.T, 3), dtype=torch.float64, device=DEV)
+    obj, _ = gp.eval_full(Xd, tet_terms=cache)
+    arch = _t(O.nondominated(obj.cpu().numpy()))
+    cubes = O.cube_classes(w.mesh)[0]
+    tets = gp.topology()["tets"]
+    r = np.random.default_rng(9).integers(0, 6, size=len(cubes))
+    pts_h = tets[6 * cubes + r].reshape(-1).astype(np.int32)
+    off_h = (4 * np.arange(len(cubes) + 1)).astype(np.int32)
+    pts, off = _t(pts_h), _t(off_h)
+    _say(f"accept {len(cubes)} tetrahedron elements")
+    cand = gp.sample_candidates(Xd, pts, 1, 1.5, 5, 1)
+    terms_cand = torch.zeros_like(cache)
+    old, new, fl, _ = gp.eval_partial(Xd, off, pts, cand, tet_terms_in=cache, tet_terms_new=terms_cand)
+    acc = torch.empty((S, len(cubes)), dtype=torch.uint8, device=DEV)
+    X1 = Xd.clone()
+    gp.accept_elements(X1, off, pts, cand, old, new, fl, terms_cand, cache, obj, archive=arch, accepted=acc)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy().astype(bool)
+    assert 0 < got.sum() < got.size
+    Xn, cn = X1.cpu().numpy(), cand.cpu().numpy()
+    for s in range(S):
+        for f in range(len(cubes)):
+            for j in range(off_h[f], off_h[f + 1]):
+                p = pts_h[j]
+                want = cn[s, j] if got[s, f] else X[s, :, p]
+                assert np.array_equal(Xn[s, :, p], want)
+    cache2 = torch.empty_like(cache)
+    obj2, fl2 = gp.eval_full(X1, tet_terms=cache2)
+    assert int((fl2 != 0).sum()) == 0
+    np.testing.assert_allclose(obj.cpu().numpy(), obj2.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(cache.cpu().numpy(), cache2.cpu().numpy(), rtol=1e-4, atol=1e-7)
+    # single-point elements: the CSR entry point equals the single-point one
+    cls = _t(O.parity_classes(w.mesh)[1])
+    F = cls.shape[0]
+    off1 = _t(np.arange(F + 1, dtype=np.int32))
+    cache_a = torch.empty_like(cache)
+    obj_a, _ = gp.eval_full(Xd, tet_terms=cache_a)
+    cache_b, obj_b = cache_a.clone(), obj_a.clone()
+    c1 = gp.sample_candidates(Xd, cls, 1, 2.0, 6, 2)
+    tc = torch.zeros_like(cache)
+    o1, n1, f1, _ = gp.eval_partial(Xd, off1, cls, c1, tet_terms_in=cache_a, tet_terms_new=tc)
+    Xa, Xb = Xd.clone(), Xd.clone()
+    aa = torch.empty((S, F), dtype=torch.uint8, device=DEV)
+    ab = torch.empty_like(aa)
+    gp.accept(Xa, cls, c1, o1, n1, f1, tc, cache_a, obj_a, archive=arch, accepted=aa)
+    gp.accept_elements(Xb, off1, cls, c1, o1, n1, f1, tc, cache_b, obj_b, archive=arch, accepted=ab)
+    for a, b in ((Xa, Xb), (cache_a, cache_b), (obj_a, obj_b), (aa, ab)):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("sampler", ["isotropic", "estimated"])
+def test_optimiser_tetrahedron_fos(sampler):
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    Xd = _t(X)
+    _say(f"6 generations, tetrahedron FOS, {sampler} sampler")
+    log, opt, _ = O.run(gp, Xd, 6, sigma=w.sigma_cand, seed=4, sampler=sampler, fos="tetrahedron")
+    assert log.hypervolume[-1] > log.hypervolume[0] and sum(log.accepted) > 0
+    assert int((gp.fold_check(opt.X) != 0).sum().item()) == 0
+    obj, flags = gp.eval_full(opt.X)
+    assert int((flags != 0).sum().item()) == 0
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    with pytest.raises(ValueError):
+        O.Optimiser(gp, Xd, fos="tetrahedron", graph=True)
