@@ -249,25 +249,35 @@ def surrogate_run(gp, X, G, train_generations, name):
     print(json.dumps(res), flush=True)
 
 
-def sampler_run(gp, X, G, name):
+def sampler_run(gp, X, G, name, w):
     """G generations with isotropic Gaussian candidates around the current
     position vs G generations whose candidates are drawn from per-point normal
     distributions estimated on the selected solutions (RV-GOMEA's partial
-    changes; tau = 0.35, adaptive multipliers), both eager from the same
-    population; hypervolume of the elitist archive against a reference point
-    fixed by the initial population."""
+    changes; tau = 0.35, adaptive multipliers), for single-point elements and
+    for the paper's FOS (one random tetrahedron per cube, 4 points changed
+    together), all eager from the same population; hypervolume of the elitist
+    archive against a reference point fixed by the initial population."""
     import torch
+    from paper_2202_11001_amd import dsm
     from paper_2202_11001_amd import optimizer as O
     Xd = torch.from_numpy(X).to("cuda:0")
+    gp4 = dsm.Problem.from_workload(w, max_fos_points=4)
     out = {"workload": name, "generations": G}
-    for sampler in ("isotropic", "estimated"):
-        log(f"{sampler} sampler: {G} generations")
-        lg, opt, _ = O.run(gp, Xd, G, sigma=1.0, seed=5, log_every=10, sampler=sampler)
-        out[sampler] = {"final_hv": lg.hypervolume[-1], "seconds": lg.seconds[-1], "hv": lg.hypervolume,
-                        "t": lg.seconds, "accepted": lg.accepted, "archive": lg.archive_size[-1]}
-        if sampler == "estimated":
-            m = torch.cat(opt.mult)
-            out[sampler]["multiplier"] = {"min": float(m.min()), "median": float(m.median()), "max": float(m.max())}
+    for fos, prob in (("point", gp), ("tetrahedron", gp4)):
+        for sampler in ("isotropic", "estimated"):
+            key = f"{fos}/{sampler}"
+            log(f"{key}: {G} generations")
+            lg, opt, _ = O.run(prob, Xd, G, sigma=1.0, seed=5, log_every=10, sampler=sampler, fos=fos)
+            arch = np.asarray(opt.archive)
+            pop = opt.obj.cpu().numpy()
+            out[key] = {"final_hv": lg.hypervolume[-1], "seconds": lg.seconds[-1], "hv": lg.hypervolume,
+                        "t": lg.seconds, "accepted": lg.accepted, "exact": lg.exact_evals,
+                        "archive": lg.archive_size[-1],
+                        "archive_inside_reference": float(np.mean(np.all(arch < opt.ref, axis=1))),
+                        "population_objectives_over_reference_median": (np.median(pop, axis=0) / opt.ref).tolist()}
+            if sampler == "estimated":
+                m = torch.cat(opt.mult) if fos == "point" else opt.mult_pt
+                out[key]["multiplier"] = {"min": float(m.min()), "median": float(m.median()), "max": float(m.max())}
     print(json.dumps(out), flush=True)
 
 
@@ -498,7 +508,7 @@ def main():
 
     X = w.population(reject=reject)
     if args.sampler_run:
-        sampler_run(gp, X, args.sampler_run, w.name)
+        sampler_run(gp, X, args.sampler_run, w.name, w)
         return
     if args.surrogate_run:
         surrogate_run(gp, X, args.surrogate_run, args.train_generations, w.name)
