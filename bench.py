@@ -254,8 +254,8 @@ def sampler_run(gp, X, G, name, w):
     position vs G generations whose candidates are drawn from per-point normal
     distributions estimated on the selected solutions (RV-GOMEA's partial
     changes; tau = 0.35, adaptive multipliers), for single-point elements and
-    for the paper's FOS (one random tetrahedron per cube, 4 points changed
-    together), all eager from the same population; hypervolume of the elitist
+    for the paper's FOS (one random tetrahedron per cube, its 4 points drawn
+    jointly), all eager from the same population; hypervolume of the elitist
     archive against a reference point fixed by the initial population."""
     import torch
     from paper_2202_11001_amd import dsm
@@ -276,7 +276,7 @@ def sampler_run(gp, X, G, name, w):
                         "archive_inside_reference": float(np.mean(np.all(arch < opt.ref, axis=1))),
                         "population_objectives_over_reference_median": (np.median(pop, axis=0) / opt.ref).tolist()}
             if sampler == "estimated":
-                m = torch.cat(opt.mult) if fos == "point" else opt.mult_pt
+                m = torch.cat(opt.mult) if fos == "point" else opt.mult_cube
                 out[key]["multiplier"] = {"min": float(m.min()), "median": float(m.median()), "max": float(m.max())}
     print(json.dumps(out), flush=True)
 

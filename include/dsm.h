@@ -384,6 +384,30 @@ dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32
                                 const double* mean, const double* chol, const float* mult, uint64_t seed,
                                 uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream);
 
+/* dsm_estimate_distributions for elements of up to 4 points (e.g. the paper's
+ * per-cube tetrahedra), jointly: the variables of element f are the
+ * coordinates of its points fos_pts[fos_off[f] .. fos_off[f+1]), 6 per point
+ * in order (source x y z, target x y z).  mean dev [F][24] and chol dev
+ * [F][300] (float64; row r of the lower factor holds columns 0..r) over the
+ * solutions sel dev [n_sel] of X (indices outside [0, S) skipped); rows and
+ * columns of pinned coordinates and of unused variables are 0.  Elements with
+ * no point, more than 4 points, an invalid point or malformed offsets get
+ * zeros.  Errors: DSM_ERR_ARG. */
+dsm_status dsm_estimate_elements(dsm_problem* p, int32_t S, const float* X, int32_t n_sel, const int32_t* sel, int32_t F,
+                                 const int32_t* fos_off, const int32_t* fos_pts, double* mean, double* chol,
+                                 void* stream);
+
+/* Candidates cand dev [S][fos_off[F]][2][3] (the layout of dsm_eval_partial)
+ * drawn per solution and element from N(mean, mult[f] L L^T) on the element's
+ * free variables (24 counter-based standard normal draws per solution and
+ * element); pinned coordinates keep the solution's value; clamped to the box
+ * and rounded to the lattice.  Elements rejected by dsm_estimate_elements get
+ * NaN candidates (flagged non-finite by the evaluator); elements with
+ * malformed offsets are not written.  Errors: DSM_ERR_ARG. */
+dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                               const int32_t* fos_pts, const double* mean, const double* chol, const float* mult,
+                               uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream);
+
 /* Sec. 2.4 grid refinement for multi-resolution runs: each cube of both grids
  * is split into 8 cubes by points at the middle of every cube edge, the middle
  * of every face and the cube centre (face middles and centres are means of the

@@ -72,5 +72,38 @@ def estimate(X, sel, pts, mesh):
 
 
 def packed_lower(L):
-    """The 21 entries of a lower-triangular 6x6 matrix, row r holding columns 0..r."""
-    return np.concatenate([L[r, :r + 1] for r in range(6)])
+    """The entries of a lower-triangular n x n matrix, row r holding columns
+    0..r (21 for n = 6, 300 for n = 24)."""
+    return np.concatenate([L[r, :r + 1] for r in range(L.shape[0])])
+
+
+MAX_POINTS = 4
+MAX_VARS = 6 * MAX_POINTS
+
+
+def estimate_elements(X, sel, off, pts, mesh):
+    """Joint distributions of elements of up to 4 points (CSR off, pts): the
+    variables of element f are its points' coordinates in order, 6 per point.
+    Returns (mean [F][24], covariance [F][24][24], Cholesky factor [F][24][24]),
+    zero for variables beyond 6 x (number of points), for pinned coordinates,
+    and for elements with no point, more than 4, or an invalid point."""
+    F = len(off) - 1
+    P = X.shape[2]
+    mean = np.zeros((F, MAX_VARS))
+    cov = np.zeros((F, MAX_VARS, MAX_VARS))
+    chol = np.zeros((F, MAX_VARS, MAX_VARS))
+    for f in range(F):
+        ps = list(pts[off[f]:off[f + 1]])
+        if not 1 <= len(ps) <= MAX_POINTS or any(not 0 <= p < P for p in ps):
+            continue
+        xs = [coordinates(X, sel, p) for p in ps]
+        if len(xs[0]) == 0:
+            continue
+        x = np.concatenate(xs, axis=1)  # [n][6 * len(ps)]
+        free = np.concatenate([free_axes(p, mesh) for p in ps])
+        nv = x.shape[1]
+        m = x.mean(axis=0)
+        d = (x - m) * free
+        C = d.T @ d / len(x)
+        mean[f, :nv], cov[f, :nv, :nv], chol[f, :nv, :nv] = m, C, cholesky_semidefinite(C)
+    return mean, cov, chol

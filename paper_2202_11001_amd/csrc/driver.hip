@@ -166,6 +166,131 @@ __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, 
   }
 }
 
+// Multi-point elements (such as the paper's per-cube tetrahedra): the
+// variables of element f are the coordinates of its points
+// fos_pts[fos_off[f] .. fos_off[f+1]) in order, 6 per point (source x y z,
+// target x y z), at most kEstPoints points.  The distribution is estimated
+// over all of them jointly (full covariance).
+constexpr int kEstPoints = 4, kEstVars = 6 * kEstPoints, kEstTri = kEstVars * (kEstVars + 1) / 2;
+
+// One 64-thread workgroup per element: mean [F][kEstVars] and the lower
+// Cholesky factor chol [F][kEstTri] (row r holding columns 0..r) of the
+// maximum-likelihood covariance of the free variables over the solutions
+// sel[0..n_sel) (indices outside [0, S) skipped); rows and columns of pinned
+// coordinates, and of variables beyond 6 x (number of points), are 0; a
+// non-positive pivot gives a zero column.  Elements with no point, more than
+// kEstPoints points or an invalid point get zeros.
+__global__ __launch_bounds__(64) void k_estimate_el(DevProblem pr, int S, const float* __restrict__ X, int n_sel,
+                                                    const int* __restrict__ sel, int F, const int* __restrict__ off,
+                                                    const int* __restrict__ pts, double* __restrict__ mean,
+                                                    double* __restrict__ chol) {
+  __shared__ double s_mu[kEstVars];
+  __shared__ double s_C[kEstTri];
+  __shared__ int s_ok;
+  const int f = blockIdx.x, t = threadIdx.x;
+  double* mu = mean + (size_t)f * kEstVars;
+  double* L = chol + (size_t)f * kEstTri;
+  for (int i = t; i < kEstVars; i += 64) mu[i] = 0.0;
+  for (int i = t; i < kEstTri; i += 64) L[i] = 0.0;
+  const int b = off[f], np = off[f + 1] - b;
+  if (t == 0) {
+    int ok = b >= 0 && np >= 1 && np <= kEstPoints && b + np <= off[F];
+    for (int k = 0; ok && k < np; ++k) ok = pts[b + k] >= 0 && pts[b + k] < pr.P;
+    s_ok = ok;
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  const int nv = 6 * np;
+  int n = 0;  // solutions used
+  for (int i = 0; i < n_sel; ++i) n += sel[i] >= 0 && sel[i] < S;
+  if (n == 0) return;
+  // variable v: point v / 6, coordinate v % 6; free unless pinned to the box
+  auto coord = [&](int si, int v) {
+    const int p = pts[b + v / 6], c = v % 6;
+    return (double)X[(((size_t)si * 2 + c / 3) * pr.P + p) * 3 + c % 3];
+  };
+  auto is_free = [&](int v) {
+    const int p = pts[b + v / 6], a = v % 3;
+    const int idx = a == 0 ? p % pr.n[0] : (a == 1 ? (p / pr.n[0]) % pr.n[1] : p / (pr.n[0] * pr.n[1]));
+    return idx > 0 && idx < pr.n[a] - 1;
+  };
+  if (t < nv) {
+    double m = 0.0;
+    for (int i = 0; i < n_sel; ++i)
+      if (sel[i] >= 0 && sel[i] < S) m += coord(sel[i], t);
+    s_mu[t] = m / n;
+  }
+  __syncthreads();
+  for (int e = t; e < nv * (nv + 1) / 2; e += 64) {
+    int r = 0;
+    while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    const int c = e - r * (r + 1) / 2;
+    double acc = 0.0;
+    if (is_free(r) && is_free(c))
+      for (int i = 0; i < n_sel; ++i)
+        if (sel[i] >= 0 && sel[i] < S) acc += (coord(sel[i], r) - s_mu[r]) * (coord(sel[i], c) - s_mu[c]);
+    s_C[e] = acc / n;
+  }
+  __syncthreads();
+  if (t == 0) {  // in place: s_C becomes the factor
+    for (int r = 0; r < nv; ++r)
+      for (int c = 0; c <= r; ++c) {
+        double v = s_C[r * (r + 1) / 2 + c];
+        for (int k = 0; k < c; ++k) v -= s_C[r * (r + 1) / 2 + k] * s_C[c * (c + 1) / 2 + k];
+        if (c == r)
+          s_C[r * (r + 1) / 2 + r] = v > 0.0 ? sqrt(v) : 0.0;
+        else {
+          const double d = s_C[c * (c + 1) / 2 + c];
+          s_C[r * (r + 1) / 2 + c] = d > 0.0 ? v / d : 0.0;
+        }
+      }
+  }
+  __syncthreads();
+  if (t < nv) mu[t] = s_mu[t];
+  for (int e = t; e < nv * (nv + 1) / 2; e += 64) L[e] = s_C[e];
+}
+
+// cand [S][fos_off[F]][2][3] for multi-point elements: mean + sqrt(mult[f]) L z
+// on the element's free variables, z ~ N(0, I) (kEstVars draws per solution
+// and element, counters as in k_sample); pinned coordinates keep the
+// solution's value; clamped to the box and rounded to the lattice.  Elements
+// that k_estimate_el rejects get NaN candidates.
+__global__ void k_sample_el(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ off,
+                            const int* __restrict__ pts, const double* __restrict__ mean,
+                            const double* __restrict__ chol, const float* __restrict__ mult,
+                            unsigned long long seed, unsigned long long counter,
+                            const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (counter_dev) counter += *counter_dev;
+  if (row >= (int64_t)S * F) return;
+  const int s = (int)(row / F), f = (int)(row % F);
+  const int b = off[f], np = off[f + 1] - b, total = off[F];
+  if (b < 0 || np < 0 || b + np > total) return;  // malformed offsets: nothing of this element to write
+  bool ok = np >= 1 && np <= kEstPoints;
+  for (int k = 0; ok && k < np; ++k) ok = pts[b + k] >= 0 && pts[b + k] < pr.P;
+  if (!ok) {
+    for (int k = 0; k < np; ++k)
+      for (int c = 0; c < 6; ++c) cand[((size_t)s * total + b + k) * 6 + c] = NAN;
+    return;
+  }
+  const double* mu = mean + (size_t)f * kEstVars;
+  const double* L = chol + (size_t)f * kEstTri;
+  const double sc = sqrt((double)mult[f]);
+  double z[kEstVars];
+  for (int v = 0; v < 6 * np; ++v) z[v] = normal(seed, counter * 0x100000000ull + (unsigned long long)(row * kEstVars + v));
+  for (int v = 0; v < 6 * np; ++v) {
+    const int p = pts[b + v / 6], c = v % 6, g = c / 3, a = c % 3;
+    const int idx = a == 0 ? p % pr.n[0] : (a == 1 ? (p / pr.n[0]) % pr.n[1] : p / (pr.n[0] * pr.n[1]));
+    double x = X[(((size_t)s * 2 + g) * pr.P + p) * 3 + a];
+    if (idx > 0 && idx < pr.n[a] - 1) {
+      double w = 0.0;
+      for (int k = 0; k <= v; ++k) w += L[v * (v + 1) / 2 + k] * z[k];
+      x = fmin(fmax(mu[v] + sc * w, -0.5), pr.D[a] - 0.5);
+    }
+    cand[((size_t)s * total + b + v / 6) * 6 + c] = (float)(rint((x + 0.5) * kLat) / kLat - 0.5);
+  }
+}
+
 // Accept / apply one colour class of single-point elements.
 __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, const int* __restrict__ off,
                          const int* __restrict__ pts, const float* __restrict__ cand, const double* __restrict__ part_old,
@@ -283,6 +408,28 @@ dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32
   if (!X || !fos_pts || !mean || !chol || !mult || !cand) return DSM_ERR_ARG;
   k_sample_est<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
       p->dev, S, X, F, fos_pts, K, mean, chol, mult, seed, counter, (const unsigned long long*)counter_dev, cand);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_estimate_elements(dsm_problem* p, int32_t S, const float* X, int32_t n_sel, const int32_t* sel, int32_t F,
+                                 const int32_t* fos_off, const int32_t* fos_pts, double* mean, double* chol,
+                                 void* stream) {
+  if (!p || S < 0 || F < 0 || n_sel < 0) return DSM_ERR_ARG;
+  if (F == 0) return DSM_OK;  // empty buffers may be null
+  if (!fos_off || !fos_pts || !mean || !chol || (n_sel > 0 && (!X || !sel))) return DSM_ERR_ARG;
+  k_estimate_el<<<(unsigned)F, 64, 0, (hipStream_t)stream>>>(p->dev, S, X, n_sel, sel, F, fos_off, fos_pts, mean, chol);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                               const int32_t* fos_pts, const double* mean, const double* chol, const float* mult,
+                               uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream) {
+  if (!p || S < 0 || F < 0) return DSM_ERR_ARG;
+  const int64_t n = (int64_t)S * F;
+  if (n == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !fos_off || !fos_pts || !mean || !chol || !mult || !cand) return DSM_ERR_ARG;
+  k_sample_el<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+      p->dev, S, X, F, fos_off, fos_pts, mean, chol, mult, seed, counter, (const unsigned long long*)counter_dev, cand);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 

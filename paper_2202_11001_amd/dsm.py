@@ -83,6 +83,8 @@ def lib():
             "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_estimate_distributions": ([V, I, V, I, V, I, V, V, V, V], I),
             "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_estimate_elements": ([V, I, V, I, V, I, V, V, V, V, V], I),
+            "dsm_sample_elements": ([V, I, V, I, V, V, V, V, V, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
@@ -319,6 +321,28 @@ class Problem:
         _check(lib().dsm_accept(self._h, X.shape[0], _dptr(X), pts.shape[0], _dptr(pts), _dptr(cand),
                                 _dptr(part_old), _dptr(part_new), _dptr(flags), _dptr(terms_cand), _dptr(terms_cache),
                                 _dptr(obj), na, _dptr(archive), _dptr(accepted), _stream(stream)))
+
+    def estimate_elements(self, X, sel, off, pts, stream=None):
+        """Joint distributions of elements of up to 4 points (CSR off, pts):
+        (mean [F][24], lower Cholesky factor [F][300]) float64."""
+        torch = _torch()
+        F = off.shape[0] - 1
+        mean = torch.empty((F, 24), dtype=torch.float64, device=X.device)
+        chol = torch.empty((F, 300), dtype=torch.float64, device=X.device)
+        _check(lib().dsm_estimate_elements(self._h, X.shape[0], _dptr(X), sel.shape[0], _dptr(sel), F, _dptr(off),
+                                           _dptr(pts), _dptr(mean), _dptr(chol), _stream(stream)))
+        return mean, chol
+
+    def sample_elements(self, X, off, pts, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None):
+        """Candidates [S][len(pts)][2][3] drawn from the elements' joint distributions."""
+        torch = _torch()
+        S, F = X.shape[0], off.shape[0] - 1
+        if out is None:
+            out = torch.empty((S, pts.shape[0], 2, 3), dtype=torch.float32, device=X.device)
+        _check(lib().dsm_sample_elements(self._h, S, _dptr(X), F, _dptr(off), _dptr(pts), _dptr(mean), _dptr(chol),
+                                         _dptr(mult), int(seed), int(counter), _dptr(counter_dev), _dptr(out),
+                                         _stream(stream)))
+        return out
 
     def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
                         accepted=None, stream=None):

@@ -17,10 +17,12 @@ Candidates are isotropic Gaussian moves around the current position
 distribution per point estimated on the selected solutions, as RV-GOMEA's
 partial changes draw them: each generation selects the ``tau`` fraction of the
 population with the fewest dominating solutions (ties: smallest sum of range-
-normalised objectives), estimates per point the mean and full covariance of
-its 6 coordinates on the GPU, and samples N(mean, c L L^T) with a per-point
-multiplier c that grows by 1/0.9 after a generation in which the point's change
-was accepted by some solution and shrinks by 0.9 otherwise (within [0.05, 10]).
+normalised objectives), estimates per FOS element the mean and full covariance
+of its coordinates on the GPU (6 per point; the 4 points of a tetrahedron
+element jointly), and samples N(mean, c L L^T) with a multiplier c per point
+(per cube for tetrahedron elements) that grows by 1/0.9 after a generation in
+which the element's change was accepted by some solution and shrinks by 0.9
+otherwise (within [0.05, 10]).
 Clustering, anticipated mean shift and the full multiplier schedule of
 RV-GOMEA are not built.
 """
@@ -195,7 +197,8 @@ class Optimiser:
             self.tets = np.asarray(problem.topology()["tets"], dtype=np.int32)
             self.generation_index = 0
             self.classes = None  # drawn per generation
-            self.mult_pt = torch.ones(problem.P, dtype=torch.float32, device=dev)
+            n_cubes = int(np.prod([int(n) - 1 for n in problem.mesh]))
+            self.mult_cube = torch.ones(n_cubes, dtype=torch.float32, device=dev)  # per-cube multipliers
         self.cache = torch.empty((self.S, problem.T, 3), dtype=torch.float64, device=dev)
         self.terms_cand = torch.zeros_like(self.cache)
         obj, flags = problem.eval_full(self.X, tet_terms=self.cache)
@@ -258,7 +261,8 @@ class Optimiser:
     def _tet_steps(self, surrogate):
         """One generation of the paper's FOS: per class of cubes, one random
         tetrahedron per cube, its 4 points sampled together (isotropic, or from
-        the per-point estimated distributions), evaluated and accepted."""
+        the element's jointly estimated distribution with a per-cube
+        multiplier), evaluated and accepted."""
         torch = self.torch
         if surrogate is not None or self.collect is not None:
             raise ValueError("screening and training-row collection support single-point elements only")
@@ -272,23 +276,23 @@ class Optimiser:
             pts_h = self.tets[6 * cubes + r].reshape(-1).astype(np.int32)
             pts = torch.from_numpy(pts_h).to(dev)
             off = torch.from_numpy((4 * np.arange(len(cubes) + 1)).astype(np.int32)).to(dev)
+            cubes_d = torch.from_numpy(cubes).to(dev)
             if self.sampler == "isotropic":
                 cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
             else:
-                mean, chol = self.p.estimate_distributions(self.X, sel, pts)
-                mult = self.mult_pt[pts.to(torch.int64)].contiguous()
-                cand = self.p.sample_estimated(self.X, pts, 1, mean, chol, mult, self.seed, c + 1,
-                                               counter_dev=self.counter_dev)
+                mean, chol = self.p.estimate_elements(self.X, sel, off, pts)
+                mult = self.mult_cube[cubes_d].contiguous()
+                cand = self.p.sample_elements(self.X, off, pts, mean, chol, mult, self.seed, c + 1,
+                                              counter_dev=self.counter_dev)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
                                                      tet_terms_new=self.terms_cand)
             acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
             self.p.accept_elements(self.X, off, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
                                    archive=self.arch_dev, accepted=acc)
             if self.sampler == "estimated":
-                hit = acc.any(dim=0).repeat_interleave(4)
-                idx = pts.to(torch.int64)
-                m = self.mult_pt[idx]
-                self.mult_pt[idx] = torch.where(hit, torch.clamp(m / 0.9, max=10.0), torch.clamp(m * 0.9, min=0.05))
+                hit = acc.any(dim=0)
+                m = self.mult_cube[cubes_d]
+                self.mult_cube[cubes_d] = torch.where(hit, torch.clamp(m / 0.9, max=10.0), torch.clamp(m * 0.9, min=0.05))
             outs.append((None, acc, cand, old, new, flags))
         self.counter_dev += self.n_classes
         return outs

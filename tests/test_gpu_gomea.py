@@ -117,3 +117,65 @@ def test_optimiser_with_estimated_sampler():
     assert max(dom(i) for i in sel) <= min(dom(i) for i in rest)
     with pytest.raises(ValueError):
         O.Optimiser(gp, Xd, sampler="estimated", graph=True)
+
+
+def test_estimate_elements_matches_reference():
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    S = X.shape[0]
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    tets = gp.topology()["tets"]
+    cubes = O.cube_classes(w.mesh)[0]
+    r = np.random.default_rng(2).integers(0, 6, size=len(cubes))
+    pts = list(tets[6 * cubes + r].reshape(-1))
+    off = list(4 * np.arange(len(cubes) + 1))
+    # a one-point element, a 5-point one, one with an invalid point, an empty one
+    for extra in ([37], [1, 2, 3, 4, 5], [6, -1], []):
+        pts += extra
+        off.append(off[-1] + len(extra))
+    off, pts = np.array(off, dtype=np.int32), np.array(pts, dtype=np.int32)
+    sel = np.array(list(range(0, S, 2)) + [-3, S], dtype=np.int32)
+    _say(f"estimate {len(off) - 1} elements jointly")
+    mean, chol = gp.estimate_elements(_t(X), _t(sel), _t(off), _t(pts))
+    rmean, _, rchol = G.estimate_elements(X, sel, off, pts, w.mesh)
+    np.testing.assert_allclose(mean.cpu().numpy(), rmean, rtol=1e-12, atol=1e-12)
+    rpacked = np.array([G.packed_lower(L) for L in rchol])
+    np.testing.assert_allclose(chol.cpu().numpy(), rpacked, rtol=1e-8, atol=1e-10)
+    assert np.all(mean.cpu().numpy()[-3:] == 0) and np.all(chol.cpu().numpy()[-3:] == 0)
+
+
+def test_sample_elements_joint_distribution():
+    w = W.batched()
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    I = gp.topology()["identity"]
+    S = 4096
+    X = np.repeat(np.stack([I, I])[None], S, axis=0)
+    # one interior tetrahedron-like element of 4 points, one of them on a face (z pinned)
+    ps = np.array([1 + 5 * (2 + 5 * 2), 2 + 5 * (2 + 5 * 2), 2 + 5 * (3 + 5 * 2), 2 + 5 * (2 + 5 * 0)], dtype=np.int32)
+    off = np.array([0, 4], dtype=np.int32)
+    free = np.concatenate([G.free_axes(p, w.mesh) for p in ps])
+    rng = np.random.default_rng(8)
+    A = rng.normal(0, 0.6, (24, 24)) * free[:, None] * free[None, :]
+    C = A @ A.T + np.diag(0.2 * free)
+    L = G.cholesky_semidefinite(C)
+    mean = np.concatenate([np.concatenate([I[p], I[p]]) for p in ps]) + rng.uniform(-1, 1, 24) * free
+    mult = np.array([0.5], dtype=np.float32)
+    _say(f"sample {S} joint candidates")
+    cand = gp.sample_elements(_t(X), _t(off), _t(ps), _t(mean[None]), _t(G.packed_lower(L)[None]), _t(mult), 17, 2)
+    x = cand.cpu().numpy().reshape(S, 24).astype(np.float64)
+    cur = np.concatenate([np.concatenate([I[p], I[p]]) for p in ps])
+    assert np.all(x[:, ~free] == cur[~free])
+    assert np.all(np.rint((x + 0.5) * 128) == (x + 0.5) * 128)
+    fr = np.nonzero(free)[0]
+    Cm = mult[0] * C
+    sd = np.sqrt(np.diag(Cm))
+    assert np.all(np.abs(x[:, fr].mean(axis=0) - mean[fr]) < 5 * sd[fr] / np.sqrt(S) + 0.01)
+    emp = np.cov(x[:, fr].T, bias=True)
+    assert np.allclose(emp, Cm[np.ix_(fr, fr)], atol=0.1 * sd[fr].max() ** 2)
+    # a rejected element (5 points) gets NaN candidates
+    off5 = np.array([0, 5], dtype=np.int32)
+    p5 = np.array([ps[0], ps[1], ps[2], ps[3], 7], dtype=np.int32)
+    c5 = gp.sample_elements(_t(X[:2]), _t(off5), _t(p5), _t(np.zeros((1, 24))), _t(np.zeros((1, 300))),
+                            _t(mult), 1, 1)
+    assert torch.all(torch.isnan(c5))

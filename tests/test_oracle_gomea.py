@@ -78,3 +78,29 @@ def test_packed_lower_layout():
     packed = G.packed_lower(L)
     assert len(packed) == 21
     assert packed[0] == L[0, 0] and list(packed[1:3]) == [L[1, 0], L[1, 1]] and packed[20] == L[5, 5]
+
+
+def test_elements_reduce_to_points_and_are_joint():
+    X = _population(60, seed=5)
+    sel = list(range(0, 60, 2)) + list(range(1, 20, 2))  # 40 solutions: more than the 24 variables
+    # a one-point element equals the per-point estimate in the first 6 variables
+    pm, pc, pl = G.estimate(X, sel, [INTERIOR], MESH)
+    em, ec, el = G.estimate_elements(X, sel, np.array([0, 1]), np.array([INTERIOR]), MESH)
+    assert np.allclose(em[0, :6], pm[0]) and np.allclose(ec[0, :6, :6], pc[0]) and np.allclose(el[0, :6, :6], pl[0])
+    assert np.all(em[0, 6:] == 0) and np.all(el[0, 6:] == 0)
+    # a 4-point element: the diagonal blocks are the per-point covariances, the
+    # off-diagonal blocks the cross-covariances; numpy's covariance and factor
+    pts = np.array([INTERIOR, INTERIOR + 1, FACE, INTERIOR + 4])
+    em, ec, el = G.estimate_elements(X, sel, np.array([0, 4]), pts, MESH)
+    x = np.concatenate([G.coordinates(X, sel, p) for p in pts], axis=1)
+    free = np.concatenate([G.free_axes(p, MESH) for p in pts])
+    want = np.cov((x * free).T, bias=True)
+    assert np.allclose(ec[0], want)
+    for k, p in enumerate(pts):
+        assert np.allclose(ec[0, 6 * k:6 * k + 6, 6 * k:6 * k + 6], G.estimate(X, sel, [p], MESH)[1][0])
+    assert np.allclose(el[0] @ el[0].T, ec[0], atol=1e-10)
+    fr = np.nonzero(free)[0]
+    assert np.allclose(el[0][np.ix_(fr, fr)], np.linalg.cholesky(want[np.ix_(fr, fr)]))
+    # rejected elements: 5 points, an invalid point, no point
+    em, ec, el = G.estimate_elements(X, sel, np.array([0, 5, 6, 6]), np.array([1, 2, 3, 4, 5, -1]), MESH)
+    assert np.all(em == 0) and np.all(el == 0)
