@@ -712,6 +712,59 @@ void ref_normalisers(const ref_problem *p, double *out) {
   out[2] = norm_guid(p);
 }
 
+/* ------------------------------------------------------------------ transformation
+ * Sec. 2.1: the two grids define a piecewise-affine map between the images;
+ * each tetrahedron of one grid maps affinely onto the same tetrahedron of the
+ * other.  Sec. 3 (Fig. 2) shows its result as a transformed source image and a
+ * deformation vector field (DVF).  For every voxel v of image `own`, found in
+ * its tetrahedron of grid `own` with the exact test used for the objectives,
+ * x(v) = sum_q lambda_q(v) X_other[q] is the position it maps to in the other
+ * image (voxel units).  Outputs (either may be NULL):
+ *   dvf [V][3]  x(v) - v, in voxel units;
+ *   warped [V]  the other image sampled at x(v) (trilinear, clamped), i.e. for
+ *               own = 1 the transformed source image on the target grid.
+ * Voxels inside no tetrahedron (only possible for an infeasible pair) stay NaN.
+ * X2 is one solution [2][P][3]. */
+void ref_transform(const ref_problem *p, int own, const float *X2, double *dvf, double *warped) {
+  for (long v = 0; v < p->V; ++v) {
+    if (dvf)
+      for (int a = 0; a < 3; ++a) dvf[3 * v + a] = NAN;
+    if (warped) warped[v] = NAN;
+  }
+  const float *Xo = X2 + (size_t)own * 3 * p->P, *Xt = X2 + (size_t)(1 - own) * 3 * p->P;
+  for (int t = 0; t < p->T; ++t) {
+    double Lown[4][3], Vown[4][3], Loth[4][3], Xoth[4][3];
+    if (tet_vertices(p, Xo, t, Lown, Vown) || tet_vertices(p, Xt, t, Loth, Xoth)) continue;
+    double vol = orient3d(Lown[0], Lown[1], Lown[2], Lown[3]);
+    if (vol <= 0) continue;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      double mn = Lown[0][a], mx = Lown[0][a];
+      for (int q = 1; q < 4; ++q) {
+        if (Lown[q][a] < mn) mn = Lown[q][a];
+        if (Lown[q][a] > mx) mx = Lown[q][a];
+      }
+      vox_range(mn, mx, p->D[a], &lo[a], &hi[a]);
+    }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          double U[3] = {LAT * i + 64, LAT * j + 64, LAT * k + 64}, o[4];
+          if (!inside(Lown, U, o)) continue;
+          double x[3] = {0, 0, 0};
+          for (int q = 0; q < 4; ++q)
+            for (int a = 0; a < 3; ++a) x[a] += o[q] / vol * Xoth[q][a];
+          long v = i + (long)p->D[0] * (j + (long)p->D[1] * k);
+          if (dvf) {
+            dvf[3 * v + 0] = x[0] - i;
+            dvf[3 * v + 1] = x[1] - j;
+            dvf[3 * v + 2] = x[2] - k;
+          }
+          if (warped) warped[v] = trilinear(p, 1 - own, x, 0);
+        }
+  }
+}
+
 /* ------------------------------------------------------------------ refinement
  * Sec. 2.4 (grid multi-resolution): every cube of both grids is split into 8
  * cubes by adding a point in the middle of each cube edge, in the middle of

@@ -71,6 +71,8 @@ def lib():
         L.ref_trilinear.argtypes = [P, C.c_int, P, C.c_int]
         L.ref_refine.restype = None
         L.ref_refine.argtypes = [P, C.c_int, P, P]
+        L.ref_transform.restype = None
+        L.ref_transform.argtypes = [P, C.c_int, P, P, P]
         L.ref_literal_fold_check.restype = None
         L.ref_literal_fold_check.argtypes = [P, C.c_int, P, P]
         _lib = L
@@ -176,6 +178,17 @@ class Problem:
     def trilinear(self, grid, x, mask=False):
         x = np.ascontiguousarray(x, dtype=np.float64)
         return lib().ref_trilinear(self._h, int(grid), _p(x), int(mask))
+
+    def transform(self, own, X2):
+        """Sec. 2.1 / Fig. 2: (dvf [Dz][Dy][Dx][3], warped [Dz][Dy][Dx]) of one
+        solution X2 [2][P][3]: where each voxel of image `own` maps to in the
+        other image (displacement in voxel units), and the other image sampled
+        there (own = 1: the transformed source on the target grid)."""
+        X2 = np.ascontiguousarray(X2, dtype=np.float32)
+        dvf = np.zeros((self.V, 3))
+        warped = np.zeros(self.V)
+        lib().ref_transform(self._h, int(own), _p(X2), _p(dvf), _p(warped))
+        return dvf.reshape(self.shape + (3,)), warped.reshape(self.shape)
 
     # ---- objectives and constraints
     def fold_check(self, X):
