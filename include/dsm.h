@@ -233,6 +233,23 @@ dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t
  * exactly once. */
 dsm_status dsm_rasterize_owner(dsm_problem* p, const float* Xgrid, int32_t* owner, int32_t* overlap, void* stream);
 
+/* The registration result (Sec. 2.1: corresponding tetrahedra of the two
+ * grids define a piecewise-affine map; Sec. 3, Fig. 2 shows it as a
+ * transformed source image and a deformation vector field).  For one solution
+ * X dev [2][P][3] (the layout of one entry of a population) and every voxel v
+ * of image `own` (0 source, 1 target), x(v) is the point the map sends v's
+ * centre to in the other image: v is located in its tetrahedron of grid `own`
+ * by the exact voxel sets of the objectives and mapped with FP64 barycentric
+ * coordinates.  Writes, each output optional (NULL):
+ *   dvf    dev [Dz][Dy][Dx][3] f32, x(v) - v in voxel units (x, y, z);
+ *   warped dev [Dz][Dy][Dx] f32, the other image sampled at x(v) (trilinear,
+ *          clamped to the box): for own = 1 the transformed source image.
+ * Voxels in no tetrahedron, which a feasible solution cannot leave, are NaN;
+ * for a solution that folds the outputs are undefined.  Enqueued on `stream`;
+ * no allocation.  Errors: DSM_ERR_ARG (null problem or X, own not 0 or 1),
+ * DSM_ERR_DEVICE. */
+dsm_status dsm_transform(dsm_problem* p, int32_t own, const float* X, float* dvf, float* warped, void* stream);
+
 /* Measurement support.  dsm_problem_timing(p, capacity) with capacity > 0
  * creates `capacity` pairs of HIP events; each following dsm_eval_full /
  * dsm_eval_partial call records one pair around its voxel-sweep kernel on the

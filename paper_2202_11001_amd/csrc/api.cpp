@@ -641,6 +641,14 @@ dsm_status dsm_problem_timing_read(dsm_problem* p, float* ms, int32_t max_n, int
   return DSM_OK;
 }
 
+dsm_status dsm_transform(dsm_problem* p, int32_t own, const float* X, float* dvf, float* warped, void* stream) {
+  g_err.clear();
+  if (!p || !X) return fail(DSM_ERR_ARG, "null argument");
+  if (own != 0 && own != 1) return fail(DSM_ERR_ARG, "own %d is not 0 or 1", own);
+  const hipError_t e = launch_transform(p->dev, own, X, dvf, warped, (hipStream_t)stream);
+  return e == hipSuccess ? DSM_OK : hip_fail(e, "transform launch");
+}
+
 dsm_status dsm_rasterize_owner(dsm_problem* p, const float* Xgrid, int32_t* owner, int32_t* overlap, void* stream) {
   g_err.clear();
   if (!p || !Xgrid || !owner || !overlap) return fail(DSM_ERR_ARG, "null argument");

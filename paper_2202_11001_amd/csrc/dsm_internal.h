@@ -123,6 +123,10 @@ hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, in
                              size_t lds, hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
+// Piecewise-affine map of one solution X2 [2][P][3] at every voxel of image own:
+// displacement dvf [V][3] and the other image sampled there, warped [V] (either may be null).
+hipError_t launch_transform(const DevProblem& pr, int own, const float* X2, float* dvf, float* warped,
+                            hipStream_t stream);
 hipError_t launch_pack_bordered(const float* raw, float* out, int Dx, int Dy, int Dz, BorderedLayout bl,
                                 hipStream_t stream);
 size_t eval_lds_bytes(int maxA, int nver);

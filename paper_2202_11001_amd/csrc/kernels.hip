@@ -1170,6 +1170,111 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
   }
 }
 
+// Value of voxel (x, y, z) of a bordered z-pair image: the second half of
+// element (x + 1, y + 1, z).
+__device__ __forceinline__ double raw_voxel(const float* img, int ex, int exy, int x, int y, int z) {
+  return (double)img[2 * ((size_t)(x + 1) + (size_t)ex * (y + 1) + (size_t)exy * z) + 1];
+}
+
+// FP64 trilinear sample of a bordered image at voxel-unit position x, clamped
+// to [0, D-1] per axis (the resampling of the objectives, Sec. 2.3.1).
+__device__ double trilinear64(const DevProblem& pr, const float* img, const double x[3]) {
+  int i0[3];
+  double f[3];
+  for (int a = 0; a < 3; ++a) {
+    const double c = fmin(fmax(x[a], 0.0), (double)(pr.D[a] - 1));
+    int i = (int)floor(c);
+    if (i > pr.D[a] - 2) i = pr.D[a] - 2;
+    i0[a] = i;
+    f[a] = c - i;
+  }
+  double acc = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+        acc += w * raw_voxel(img, pr.ex, pr.exy, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+      }
+  return acc;
+}
+
+// The piecewise-affine map of one solution (Sec. 2.1) at every voxel of image
+// `own`: each tetrahedron of grid `own` rasterises its exact voxel set (the
+// same spans as the objectives) and maps every voxel centre with FP64
+// barycentric coordinates from exact orientations onto the same tetrahedron of
+// the other grid.  Writes the displacement (voxel units) and the other image
+// sampled there.  One workgroup per tetrahedron.
+__global__ __launch_bounds__(kWG) void k_transform(DevProblem pr, int own, const float* __restrict__ X2,
+                                                   float* dvf, float* warped) {
+  __shared__ WaveRows rows[kWaves];
+  __shared__ RasterTet rts[kWaves];
+  __shared__ float xs[2][12];
+  const int t = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int4 tv = pr.tets[t];
+  const int vid[4] = {tv.x, tv.y, tv.z, tv.w};
+  const float* Xo = X2 + (size_t)own * 3 * pr.P;
+  const float* Xt = X2 + (size_t)(1 - own) * 3 * pr.P;
+  double L[4][3], Lt[4][3], Xv[4][3];
+  unsigned bad = 0u;
+  for (int q = 0; q < 4; ++q)
+    for (int c = 0; c < 3; ++c) {
+      bad |= lattice_of(Xo[(size_t)vid[q] * 3 + c], pr.D[c], L[q][c]);
+      const float xt = Xt[(size_t)vid[q] * 3 + c];
+      bad |= lattice_of(xt, pr.D[c], Lt[q][c]);
+      Xv[q][c] = (double)xt;
+    }
+  const double vol = orient(L[0], L[1], L[2], L[3]);
+  if (bad || !(vol > 0.0)) return;
+  if (threadIdx.x < 24) {
+    const int g = threadIdx.x / 12, e = threadIdx.x % 12;
+    xs[g][e] = (g == 0 ? Xo : Xt)[(size_t)vid[e / 3] * 3 + e % 3];
+  }
+  __syncthreads();
+  RasterTet& rt = rts[wave];
+  setup_raster(xs[0], xs[1], pr.D, lane, rt);
+  const float* other = pr.img[1 - own];
+  const int nb = (rt.nrows + 63) >> 6;
+  for (int b = wave; b < nb; b += kWaves) {
+    WaveRows& wr = rows[wave];
+    int my_start;
+    const int nvox = build_rows(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
+    int carry = 0;
+    for (int q0 = 0; q0 < nvox; q0 += 64) {
+      wr.marker[lane] = 0;
+      wave_sync();
+      const unsigned pos = (unsigned)(my_start - q0);
+      if (pos < 64u) wr.marker[pos] = 1;
+      wave_sync();
+      const int mk = wr.marker[lane];
+      const unsigned long long M = __ballot(mk != 0);
+      const int r = carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)M, 0u)) +
+                    mk - 1;
+      carry += __popcll(M);
+      const int q = q0 + lane;
+      if (q < nvox) {
+        const int idx = __float_as_int(wr.row[r].rec.x) + q;
+        const int k = idx / pr.DxDy, rem = idx - k * pr.DxDy;
+        const int j = rem / pr.D[0], i = rem - j * pr.D[0];
+        const double U[3] = {kLat * i + 0.5 * kLat, kLat * j + 0.5 * kLat, kLat * k + 0.5 * kLat};
+        double x[3] = {0.0, 0.0, 0.0};
+        for (int v = 0; v < 4; ++v) {
+          double W[4][3];
+          for (int m = 0; m < 4; ++m)
+            for (int c = 0; c < 3; ++c) W[m][c] = m == v ? U[c] : L[m][c];
+          const double lam = orient(W[0], W[1], W[2], W[3]) / vol;
+          for (int c = 0; c < 3; ++c) x[c] += lam * Xv[v][c];
+        }
+        if (dvf) {
+          dvf[(size_t)idx * 3 + 0] = (float)(x[0] - i);
+          dvf[(size_t)idx * 3 + 1] = (float)(x[1] - j);
+          dvf[(size_t)idx * 3 + 2] = (float)(x[2] - k);
+        }
+        if (warped) warped[idx] = (float)trilinear64(pr, other, x);
+      }
+    }
+  }
+}
+
 // Bordered z-pair layout from an image [Dz][Dy][Dx]: element (x', y', z')
 // = (I[c(z'-1)][c(y'-1)][c(x'-1)], I[c(z')][c(y'-1)][c(x'-1)]); elements of a
 // row past x' = Dx + 1 (pitch padding) repeat the last voxel.
@@ -1313,6 +1418,26 @@ hipError_t launch_pack_bordered(const float* raw, float* out, int Dx, int Dy, in
   const int64_t n = bl.elements();
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
   k_pack_bordered<<<blocks, 256, 0, stream>>>(raw, out, Dx, Dy, Dz, bl);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform(const DevProblem& pr, int own, const float* X2, float* dvf, float* warped,
+                            hipStream_t stream) {
+  const int64_t V = (int64_t)pr.DxDy * pr.D[2];
+  const uint32_t nan_bits = 0x7fc00000u;
+  hipError_t e = hipSuccess;
+  if (dvf) {
+    k_fill_u32<<<(unsigned)std::min<int64_t>((3 * V + 255) / 256, 4096), 256, 0, stream>>>((uint32_t*)dvf, 3 * V,
+                                                                                          nan_bits);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (warped) {
+    k_fill_u32<<<(unsigned)std::min<int64_t>((V + 255) / 256, 4096), 256, 0, stream>>>((uint32_t*)warped, V,
+                                                                                      nan_bits);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (!dvf && !warped) return hipSuccess;
+  k_transform<<<pr.T, kWG, 0, stream>>>(pr, own, X2, dvf, warped);
   return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ def lib():
             "dsm_eval_full": ([V, I, V, V, V, V, V], I),
             "dsm_eval_partial": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_rasterize_owner": ([V, V, V, V, V], I),
+            "dsm_transform": ([V, I, V, V, V, V], I),
             "dsm_problem_timing": ([V, I], I),
             "dsm_problem_timing_read": ([V, V, I, V], I),
             "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
@@ -394,6 +395,17 @@ class Problem:
         n = C.c_int32()
         _check(lib().dsm_problem_timing_read(self._h, _np_ptr(ms), int(max_n), C.byref(n)))
         return ms[:n.value].astype(np.float64)
+
+    def transform(self, X2, own=1, dvf=True, warped=True, stream=None):
+        """(dvf [Dz][Dy][Dx][3] or None, warped [Dz][Dy][Dx] or None) of one
+        solution X2 [2][P][3] f32 on the device (``dsm_transform``)."""
+        torch = _torch()
+        Dx, Dy, Dz = self.dims
+        d = torch.empty((Dz, Dy, Dx, 3), dtype=torch.float32, device=X2.device) if dvf else None
+        w = torch.empty((Dz, Dy, Dx), dtype=torch.float32, device=X2.device) if warped else None
+        _check(lib().dsm_transform(self._h, int(own), _dptr(X2), _dptr(d) if d is not None else None,
+                                   _dptr(w) if w is not None else None, _stream(stream)))
+        return d, w
 
     def rasterize_owner(self, Xgrid, stream=None):
         torch = _torch()

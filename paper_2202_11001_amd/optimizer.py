@@ -290,7 +290,7 @@ class Optimiser:
             self.p.accept_elements(self.X, off, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
                                    archive=self.arch_dev, accepted=acc)
             if self.sampler == "estimated":
-                hit = acc.any(dim=0)
+                hit = (acc != 0).any(dim=0)
                 m = self.mult_cube[cubes_d]
                 self.mult_cube[cubes_d] = torch.where(hit, torch.clamp(m / 0.9, max=10.0), torch.clamp(m * 0.9, min=0.05))
             outs.append((None, acc, cand, old, new, flags))
@@ -369,7 +369,7 @@ class Optimiser:
             outs = self._steps(surrogate)
         if self.sampler == "estimated" and self.fos == "point":
             for c, (_, acc, *_) in enumerate(outs):
-                hit = acc.any(dim=0)
+                hit = (acc != 0).any(dim=0)
                 self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
                                            torch.clamp(self.mult[c] * 0.9, min=0.05))
         n_exact = sum(self.S * acc.shape[1] if mask is None else int(mask.sum().item()) for mask, acc, *_ in outs)

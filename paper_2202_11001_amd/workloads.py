@@ -321,6 +321,44 @@ def clinical(shape=(100, 512, 512), mesh=(10, 10, 6), S=512, seed=31, n_guid=20)
                     np.arange(n, dtype=np.int32), np.arange(n, dtype=np.int32))
 
 
+def phantom(shape=(50, 50, 50), mesh=(6, 6, 6), S=250, seed=41, half=15.0, depth=6.0, r_source=9.0,
+            r_target=5.0, n_guid=16):
+    """Replica of the synthetic problem of Sec. 3: a cube deformed in a
+    non-affine way, with a shrinking sphere at its centre.  The paper prints no
+    parameters; here the source holds an axis-aligned cube of half-width `half`
+    voxels (intensity 0.5) around a sphere of radius `r_source` (intensity 1);
+    in the target every face of the cube is pushed towards the centre by a 3-D
+    parabola, depth(u, v) = depth * max(0, 1 - (u^2 + v^2) / half^2) over face
+    coordinates (u, v) from the face centre, and the sphere has shrunk to
+    `r_target`.  Both images are blurred (sigma 1 voxel); background 0, empty
+    threshold 0.05; spacing 1 mm.  Guidance: `n_guid` points spread evenly over
+    the source sphere (a Fibonacci lattice) and the same directions on the
+    target sphere, one correspondence each."""
+    Dz, Dy, Dx = shape
+    x, y, z = _grid(shape)
+    c = np.array([(Dx - 1) / 2.0, (Dy - 1) / 2.0, (Dz - 1) / 2.0])
+    d = [x - c[0], y - c[1], z - c[2]]
+    r = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+    src = np.where(np.maximum.reduce([np.abs(a) for a in d]) <= half, 0.5, 0.0)
+    src[r <= r_source] = 1.0
+    inside = np.ones(shape, dtype=bool)
+    for a in range(3):
+        u, v = d[(a + 1) % 3], d[(a + 2) % 3]
+        inset = depth * np.maximum(0.0, 1.0 - (u ** 2 + v ** 2) / half ** 2)
+        inside &= np.abs(d[a]) <= half - inset
+    tgt = np.where(inside, 0.5, 0.0)
+    tgt[r <= r_target] = 1.0
+    k = np.arange(n_guid) + 0.5
+    polar = np.arccos(1.0 - 2.0 * k / n_guid)
+    azim = np.pi * (1.0 + 5.0 ** 0.5) * k
+    dirs = np.stack([np.cos(azim) * np.sin(polar), np.sin(azim) * np.sin(polar), np.cos(polar)], axis=1)
+    gm = snap(c + r_source * dirs)
+    gf = snap(c + r_target * dirs)
+    ids = np.arange(n_guid, dtype=np.int32)
+    return Workload(f"phantom-{Dx}x{Dy}x{Dz}", _blur(src, 1.0).astype(np.float32), _blur(tgt, 1.0).astype(np.float32),
+                    tuple(mesh), (1.0, 1.0, 1.0), 0.05, S, 1.0, 1.0, seed + 1, seed + 2, gm, gf, ids, ids.copy())
+
+
 def ramp(shape, coef=(0.01, 0.02, 0.03), offset=0.1):
     """Linear ramp image I(x, y, z) = offset + coef . (x, y, z) (float32)."""
     x, y, z = _grid(shape)
