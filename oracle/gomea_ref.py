@@ -107,3 +107,103 @@ def estimate_elements(X, sel, off, pts, mesh):
         C = d.T @ d / len(x)
         mean[f, :nv], cov[f, :nv, :nv], chol[f, :nv, :nv] = m, C, cholesky_semidefinite(C)
     return mean, cov, chol
+
+
+# --------------------------------------------------------------------- clustering
+#
+# The paper builds on MO-RV-GOMEA (Sec. 2.2), which clusters the selected
+# solutions in objective space each generation and estimates one distribution
+# per cluster and FOS element; every solution draws from the cluster nearest
+# to it.  The clustering is balanced k-leader-means, read here as:
+#   1. objectives normalised per objective to [0, 1] over the selection (a zero
+#      range divides by 1);
+#   2. k leaders by farthest-first traversal: the first is the selected solution
+#      with the largest normalised first objective, each next one the selected
+#      solution farthest (squared Euclidean distance) from its nearest leader;
+#   3. k-means from the leaders: assign every selected solution to its nearest
+#      mean, recompute each mean as the average of its solutions (kept if none),
+#      until no assignment changes (at most 50 rounds);
+#   4. cluster j = the c = min(n, ceil(2 n / k)) selected solutions nearest to
+#      mean j, nearest first (clusters may overlap);
+#   5. every population member is assigned to the nearest mean.
+# Ties go to the lower selection position / cluster index.  Sums run in
+# selection order, one addition at a time, so that a parallel implementation
+# that keeps this order reproduces every bit.
+
+MAX_CLUSTERS = 16
+MAX_CLUSTER_SELECTION = 2048
+
+
+def _d2(a, b):
+    d0, d1, d2 = a[0] - b[0], a[1] - b[1], a[2] - b[2]
+    return d0 * d0 + d1 * d1 + d2 * d2
+
+
+def cluster(obj, sel, k):
+    """(members [k][c] selection indices into the population, assign [S],
+    means [k][3] normalised) for objectives obj [S][3] and selection sel
+    (indices outside [0, S) dropped).  With fewer than k valid selected
+    solutions every output is -1 (means NaN)."""
+    obj = np.asarray(obj, dtype=np.float64)
+    S = obj.shape[0]
+    idx = [int(s) for s in sel if 0 <= s < S]
+    n = len(idx)
+    c = min(n, -(-2 * n // k)) if k > 0 else 0
+    if k < 1 or n < k:
+        return np.full((max(k, 0), max(c, 0)), -1, np.int32), np.full(S, -1, np.int32), np.full((max(k, 0), 3), np.nan)
+    lo = [min(obj[s, o] for s in idx) for o in range(3)]
+    hi = [max(obj[s, o] for s in idx) for o in range(3)]
+    rng = [hi[o] - lo[o] if hi[o] - lo[o] > 0 else 1.0 for o in range(3)]
+    norm = lambda s: [(obj[s, o] - lo[o]) / rng[o] for o in range(3)]
+    Y = [norm(s) for s in idx]
+    # farthest-first leaders
+    first = 0
+    for i in range(1, n):
+        if Y[i][0] > Y[first][0]:
+            first = i
+    leaders = [first]
+    near = [_d2(Y[i], Y[first]) for i in range(n)]
+    while len(leaders) < k:
+        far = 0
+        for i in range(1, n):
+            if near[i] > near[far]:
+                far = i
+        leaders.append(far)
+        near = [min(near[i], _d2(Y[i], Y[far])) for i in range(n)]
+    means = [list(Y[l]) for l in leaders]
+
+    def nearest(y):
+        best, bd = 0, _d2(y, means[0])
+        for j in range(1, k):
+            d = _d2(y, means[j])
+            if d < bd:
+                best, bd = j, d
+        return best
+
+    lab = [-1] * n
+    for _ in range(50):
+        new = [nearest(Y[i]) for i in range(n)]
+        if new == lab:
+            break
+        lab = new
+        for j in range(k):
+            acc, cnt = [0.0, 0.0, 0.0], 0
+            for i in range(n):
+                if lab[i] == j:
+                    for o in range(3):
+                        acc[o] += Y[i][o]
+                    cnt += 1
+            if cnt:
+                means[j] = [acc[o] / cnt for o in range(3)]
+    members = np.zeros((k, c), np.int32)
+    for j in range(k):
+        d = [_d2(Y[i], means[j]) for i in range(n)]
+        order = sorted(range(n), key=lambda i: (d[i], i))
+        members[j] = [idx[i] for i in order[:c]]
+    assign = np.array([nearest(norm(s)) for s in range(S)], np.int32)
+    return members, assign, np.array(means)
+
+
+def cluster_size(n_sel, k):
+    """Members per cluster, c = min(n, ceil(2 n / k))."""
+    return min(n_sel, -(-2 * n_sel // k))

@@ -104,3 +104,77 @@ def test_elements_reduce_to_points_and_are_joint():
     # rejected elements: 5 points, an invalid point, no point
     em, ec, el = G.estimate_elements(X, sel, np.array([0, 5, 6, 6]), np.array([1, 2, 3, 4, 5, -1]), MESH)
     assert np.all(em == 0) and np.all(el == 0)
+
+
+# ---------------------------------------------------------------- clustering
+
+def test_cluster_hand_computed():
+    # first objective 0, 2, 4, 8 -> normalised 0, .25, .5, 1 (exact); leaders 3 then 0;
+    # .5 is equally far from both leaders and joins cluster 0; means .75 and .125
+    obj = np.zeros((4, 3))
+    obj[:, 0] = [0, 2, 4, 8]
+    members, assign, means = G.cluster(obj, [0, 1, 2, 3], 2)
+    assert np.array_equal(assign, [1, 1, 0, 0])
+    assert np.allclose(means, [[0.75, 0, 0], [0.125, 0, 0]], rtol=0, atol=0)
+    # c = min(4, ceil(2 * 4 / 2)) = 4; equal distances keep selection order
+    assert members.tolist() == [[2, 3, 1, 0], [0, 1, 2, 3]]
+
+
+def _blobs(seed=0, n=20):
+    rng = np.random.default_rng(seed)
+    centres = np.array([[0, 0, 10], [10, 0, 0], [0, 10, 0]], float)
+    obj = np.concatenate([c + rng.normal(0, 0.5, (n, 3)) for c in centres])
+    return obj, np.repeat(np.arange(3), n)
+
+
+def test_cluster_separated_blobs():
+    obj, label = _blobs()
+    members, assign, means = G.cluster(obj, np.arange(60), 3)
+    assert members.shape == (3, 40)
+    # every cluster is one blob (plus the 20 nearest others), every solution joins its blob's cluster
+    for j in range(3):
+        blob = label[members[j, 0]]
+        assert set(np.nonzero(label == blob)[0]) <= set(members[j].tolist())
+        assert np.all(assign[label == blob] == j)
+    lo, hi = obj.min(axis=0), obj.max(axis=0)
+    for j in range(3):
+        blob = label[members[j, 0]]
+        assert np.allclose(means[j], ((obj[label == blob] - lo) / (hi - lo)).mean(axis=0), atol=1e-12)
+
+
+def test_cluster_invariants_random():
+    rng = np.random.default_rng(4)
+    obj = rng.uniform(0, 1, (90, 3)) ** np.array([1.0, 2.0, 0.5])
+    sel = rng.choice(90, 40, replace=False)
+    k = 4
+    members, assign, means = G.cluster(obj, sel, k)
+    c = G.cluster_size(40, k)
+    assert members.shape == (k, c) == (4, 20)
+    lo, hi = obj[sel].min(axis=0), obj[sel].max(axis=0)
+    Y = (obj - lo) / (hi - lo)
+    d = ((Y[:, None, :] - means[None]) ** 2).sum(axis=2)  # [S][k]
+    assert np.array_equal(assign, d.argmin(axis=1))
+    # k-means fixed point: each mean is the average of the selected solutions nearest to it
+    near = d[sel].argmin(axis=1)
+    for j in range(k):
+        assert np.allclose(means[j], Y[sel][near == j].mean(axis=0), atol=1e-12)
+        # cluster j: the c selected solutions nearest to mean j, nearest first
+        order = sel[np.argsort(d[sel, j], kind="stable")]
+        assert np.array_equal(members[j], order[:c])
+    # one cluster: every selected solution, nearest to the centroid first
+    m1, a1, mu1 = G.cluster(obj, sel, 1)
+    assert m1.shape == (1, 40) and set(m1[0].tolist()) == set(sel.tolist()) and np.all(a1 == 0)
+    assert np.allclose(mu1[0], Y[sel].mean(axis=0), atol=1e-12)
+
+
+def test_cluster_edge_cases():
+    obj, _ = _blobs(n=4)
+    a = G.cluster(obj, [0, 5, 9], 2)
+    b = G.cluster(obj, [-1, 0, 12, 5, 99, 9], 2)  # out-of-range indices are dropped
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    m, asg, mu = G.cluster(obj, [0, 5, -3], 3)  # 2 valid < k
+    assert np.all(m == -1) and np.all(asg == -1) and np.all(np.isnan(mu))
+    # identical objectives: zero ranges divide by 1, every solution ties to the first cluster
+    m, asg, mu = G.cluster(np.ones((6, 3)), np.arange(6), 2)
+    assert np.all(asg == 0) and m[0].tolist() == [0, 1, 2, 3, 4, 5]
