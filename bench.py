@@ -281,13 +281,14 @@ def sampler_run(gp, X, G, name, w):
     print(json.dumps(out), flush=True)
 
 
-def phantom_run(G1=300, G2=600, S1=250, S2=500):
+def phantom_run(G1=300, G2=600, S1=250, S2=500, clusters=1):
     """Sec. 3's synthetic experiment on the seeded replica phantom (a cube with
     parabolic intrusions on every face and a shrinking central sphere, guidance
     on the sphere): the paper's multi-resolution scheme (6^3 grids, population
     250, 300 generations, then 11^3 grids seeded from the approximation set,
     population 500, 600 generations), with its FOS (one random tetrahedron per
-    cube) and estimated distributions.  As in Fig. 2 the archived solution with
+    cube) and estimated distributions (optionally per cluster of the selection
+    in objective space).  As in Fig. 2 the archived solution with
     the lowest guidance error is selected; its transformation (dsm_transform)
     gives the transformed source and the DVF, summarised against the phantom's
     known surfaces."""
@@ -301,8 +302,9 @@ def phantom_run(G1=300, G2=600, S1=250, S2=500):
     gpc = dsm.Problem.from_workload(wc, max_fos_points=4)
     gpf = dsm.Problem.from_workload(wf, max_fos_points=4)
     X = wc.population(reject=lambda X: gpc.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0)
-    res = {"workload": wf.name, "phantom": {"half": 15.0, "depth": 6.0, "r_source": 9.0, "r_target": 5.0,
-                                            "guidance_pairs": int(len(wf.guid_moving))}}
+    res = {"workload": wf.name, "clusters": clusters,
+           "phantom": {"half": 15.0, "depth": 6.0, "r_source": 9.0, "r_target": 5.0,
+                       "guidance_pairs": int(len(wf.guid_moving))}}
 
     def level(name, opt, G):
         t0 = time.perf_counter()
@@ -312,22 +314,25 @@ def phantom_run(G1=300, G2=600, S1=250, S2=500):
             opt.generation()
             torch.cuda.synchronize()
             t_opt += time.perf_counter() - t1
-            if (g + 1) % 25 == 0 or g + 1 == G:
+            if (g + 1) % 50 == 0 or g + 1 == G:
                 hv.append((g + 1, opt.hypervolume()))
-                log(f"{name} gen {g + 1}: hv {hv[-1][1]:.6g} archive {len(opt.archive)} t {t_opt:.1f} s")
+                log(f"{name} gen {g + 1}: hv {hv[-1][1]:.6g} archive {opt.n_arch} t {t_opt:.1f} s")
+            elif (g + 1) % 25 == 0:
+                log(f"{name} gen {g + 1}: archive {opt.n_arch} t {t_opt:.1f} s")
         return {"mesh": list(opt.p.mesh), "S": opt.S, "generations": G, "seconds": t_opt,
                 "seconds_with_monitoring": time.perf_counter() - t0, "hv": hv, "archive": len(opt.archive)}
 
     oc = O.Optimiser(gpc, torch.from_numpy(X).to(dev), seed=41, keep_solutions=True, sampler="estimated",
-                     fos="tetrahedron")
+                     fos="tetrahedron", clusters=clusters, archive_capacity=1 << 16)
     res["coarse"] = level("coarse", oc, G1)
     Xf, rejected = O.seed_finer(oc, gpf, S2, seed=42)
     res["seed"] = {"S": S2, "rejected_draws": rejected, "coarse_archive": len(oc.archive)}
-    of = O.Optimiser(gpf, Xf, seed=43, keep_solutions=True, sampler="estimated", fos="tetrahedron")
+    of = O.Optimiser(gpf, Xf, seed=43, keep_solutions=True, sampler="estimated", fos="tetrahedron",
+                     clusters=clusters, archive_capacity=1 << 16)
     res["fine"] = level("fine", of, G2)
     arch = np.asarray(of.archive)
     best = int(np.argmin(arch[:, 2]))
-    Xb = torch.from_numpy(np.ascontiguousarray(of.archive_X[best])).to(dev)
+    Xb = of.arch_X_dev[best].contiguous()
     I = gpf.topology()["identity"]
     obj_id, _ = gpf.eval_full(torch.from_numpy(np.stack([I, I])[None]).to(dev))
     obj_b, fl_b = gpf.eval_full(Xb[None].contiguous())
@@ -569,6 +574,7 @@ def main():
                     help="G generations with isotropic vs estimated-distribution candidates (reported separately)")
     ap.add_argument("--phantom", type=int, nargs=2, default=None, metavar=("G1", "G2"),
                     help="synthetic-phantom registration: G1 coarse then G2 fine generations (reported separately)")
+    ap.add_argument("--clusters", type=int, default=1, help="clusters of the selection for --phantom")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -580,7 +586,7 @@ def main():
         multires(*args.multires)
         return
     if args.phantom:
-        phantom_run(*args.phantom)
+        phantom_run(*args.phantom, clusters=args.clusters)
         return
     if args.tet_fos:
         tetrahedron_fos_step()

@@ -396,10 +396,16 @@ dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X,
  * result is clamped to the image box and rounded to the 1/128-voxel lattice
  * (half to even).  mult dev [F] (float) are the distribution multipliers.  An
  * invalid point gives NaN candidates (flagged non-finite by the evaluator).
- * Errors: DSM_ERR_ARG. */
+ * Clusters (MO-RV-GOMEA, Sec. 2.2): with n_clusters distributions per element,
+ * mean [n_clusters][F][6], chol [n_clusters][F][21] and mult [n_clusters][F],
+ * solution s draws from those of cluster dev [S] entry cluster[s]; a cluster
+ * index outside [0, n_clusters) gives NaN candidates.  cluster NULL: every
+ * solution uses the first (n_clusters 1 for a single distribution).
+ * Errors: DSM_ERR_ARG (also n_clusters < 1). */
 dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
-                                const double* mean, const double* chol, const float* mult, uint64_t seed,
-                                uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream);
+                                const double* mean, const double* chol, const float* mult, int32_t n_clusters,
+                                const int32_t* cluster, uint64_t seed, uint64_t counter, const uint64_t* counter_dev,
+                                float* cand, void* stream);
 
 /* dsm_estimate_distributions for elements of up to 4 points (e.g. the paper's
  * per-cube tetrahedra), jointly: the variables of element f are the
@@ -423,7 +429,29 @@ dsm_status dsm_estimate_elements(dsm_problem* p, int32_t S, const float* X, int3
  * malformed offsets are not written.  Errors: DSM_ERR_ARG. */
 dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
                                const int32_t* fos_pts, const double* mean, const double* chol, const float* mult,
-                               uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream);
+                               int32_t n_clusters, const int32_t* cluster, uint64_t seed, uint64_t counter,
+                               const uint64_t* counter_dev, float* cand, void* stream);
+
+/* Balanced k-leader-means clustering of selected solutions in objective space
+ * (MO-RV-GOMEA, on which the optimisation of Sec. 2.2 builds): per generation
+ * one distribution per cluster and FOS element is estimated from the cluster's
+ * members, and each solution draws from its nearest cluster.  obj dev [S][3]
+ * f64 (finite), sel dev [n_sel] (indices outside [0, S) dropped, n valid
+ * remain), 1 <= k <= 16, n_sel <= 1024.  Steps: objectives normalised per
+ * objective to [0, 1] over the selection (zero range: divide by 1); leaders by
+ * farthest-first traversal from the largest normalised first objective; k-means
+ * from the leaders until no assignment changes (at most 50 rounds); cluster j
+ * = the c = min(n, ceil(2n/k)) selected solutions nearest to mean j, nearest
+ * first; ties to the lower selection position or cluster index; every sum in
+ * selection order, so the result is reproducible bit for bit.  Outputs:
+ * members dev [k][cmax] population indices with cmax = min(n_sel,
+ * ceil(2 n_sel / k)) (entries past c are -1); assign dev [S] nearest cluster of
+ * every solution; means dev [k][3] normalised means (may be NULL).  With n < k
+ * every member and assignment is -1 and the means NaN.  One workgroup on
+ * `stream`; no allocation.  Errors: DSM_ERR_ARG (sizes, k, null pointers),
+ * DSM_ERR_CAPACITY (n_sel > 1024), DSM_ERR_DEVICE. */
+dsm_status dsm_cluster_objectives(int32_t S, const double* obj, int32_t n_sel, const int32_t* sel, int32_t k,
+                                  int32_t* members, int32_t* assign, double* means, void* stream);
 
 /* Sec. 2.4 grid refinement for multi-resolution runs: each cube of both grids
  * is split into 8 cubes by points at the middle of every cube edge, the middle

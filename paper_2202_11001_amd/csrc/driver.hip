@@ -9,6 +9,7 @@
 // dominates the current solution or is not dominated by any member of the
 // elitist archive.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <math.h>
 
 #include "dsm_internal.h"
@@ -135,7 +136,8 @@ __global__ void k_estimate(DevProblem pr, int S, const float* __restrict__ X, in
 // lattice (half to even).
 __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ pts, int K,
                              const double* __restrict__ mean, const double* __restrict__ chol,
-                             const float* __restrict__ mult, unsigned long long seed, unsigned long long counter,
+                             const float* __restrict__ mult, int n_clusters, const int* __restrict__ cluster,
+                             unsigned long long seed, unsigned long long counter,
                              const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
   const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (counter_dev) counter += *counter_dev;
@@ -144,13 +146,15 @@ __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, 
   const int s = (int)(row / ((int64_t)F * K));
   const int p = pts[f];
   float* out = cand + row * 6;
-  if (p < 0 || p >= pr.P) {
+  const int cl = cluster ? cluster[s] : 0;
+  if (p < 0 || p >= pr.P || cl < 0 || cl >= n_clusters) {
     for (int c = 0; c < 6; ++c) out[c] = NAN;  // flagged as non-finite by the evaluator
     return;
   }
-  const double* mu = mean + (size_t)f * 6;
-  const double* L = chol + (size_t)f * 21;
-  const double sc = sqrt((double)mult[f]);
+  const size_t d = (size_t)cl * F + f;  // distribution of the solution's cluster
+  const double* mu = mean + d * 6;
+  const double* L = chol + d * 21;
+  const double sc = sqrt((double)mult[d]);
   double z[6];
   for (int c = 0; c < 6; ++c) z[c] = normal(seed, counter * 0x100000000ull + (unsigned long long)(row * 6 + c));
   const int idx[3] = {p % pr.n[0], (p / pr.n[0]) % pr.n[1], p / (pr.n[0] * pr.n[1])};
@@ -257,8 +261,8 @@ __global__ __launch_bounds__(64) void k_estimate_el(DevProblem pr, int S, const 
 // that k_estimate_el rejects get NaN candidates.
 __global__ void k_sample_el(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ off,
                             const int* __restrict__ pts, const double* __restrict__ mean,
-                            const double* __restrict__ chol, const float* __restrict__ mult,
-                            unsigned long long seed, unsigned long long counter,
+                            const double* __restrict__ chol, const float* __restrict__ mult, int n_clusters,
+                            const int* __restrict__ cluster, unsigned long long seed, unsigned long long counter,
                             const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
   const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (counter_dev) counter += *counter_dev;
@@ -266,16 +270,18 @@ __global__ void k_sample_el(DevProblem pr, int S, const float* __restrict__ X, i
   const int s = (int)(row / F), f = (int)(row % F);
   const int b = off[f], np = off[f + 1] - b, total = off[F];
   if (b < 0 || np < 0 || b + np > total) return;  // malformed offsets: nothing of this element to write
-  bool ok = np >= 1 && np <= kEstPoints;
+  const int cl = cluster ? cluster[s] : 0;
+  bool ok = np >= 1 && np <= kEstPoints && cl >= 0 && cl < n_clusters;
   for (int k = 0; ok && k < np; ++k) ok = pts[b + k] >= 0 && pts[b + k] < pr.P;
   if (!ok) {
     for (int k = 0; k < np; ++k)
       for (int c = 0; c < 6; ++c) cand[((size_t)s * total + b + k) * 6 + c] = NAN;
     return;
   }
-  const double* mu = mean + (size_t)f * kEstVars;
-  const double* L = chol + (size_t)f * kEstTri;
-  const double sc = sqrt((double)mult[f]);
+  const size_t d = (size_t)cl * F + f;  // distribution of the solution's cluster
+  const double* mu = mean + d * kEstVars;
+  const double* L = chol + d * kEstTri;
+  const double sc = sqrt((double)mult[d]);
   double z[kEstVars];
   for (int v = 0; v < 6 * np; ++v) z[v] = normal(seed, counter * 0x100000000ull + (unsigned long long)(row * kEstVars + v));
   for (int v = 0; v < 6 * np; ++v) {
@@ -369,6 +375,211 @@ __global__ void k_refine(int nx, int ny, int nz, int S, const float* __restrict_
   for (int d = 0; d < 3; ++d) y[d] = (float)(rint(u[d] * 0.125) / kLat - 0.5);
 }
 
+// ---------------------------------------------------------------- clustering
+// Balanced k-leader-means of the selected solutions in objective space (the
+// clustering of MO-RV-GOMEA, on which the paper's optimiser builds, Sec. 2.2):
+// normalisation over the selection, farthest-first leaders, k-means from the
+// leaders, each cluster the c nearest selected solutions, every solution
+// assigned to its nearest mean.  One workgroup; every floating-point step runs
+// in a fixed order without contraction (sums in selection order by one thread
+// per cluster and objective), so the result does not depend on the schedule.
+constexpr int kClusterWG = 1024, kClusterWaves = kClusterWG / 64;
+
+__device__ __forceinline__ double dist2(const double* a, const double* b) {
+#pragma clang fp contract(off)
+  const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+  return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+__device__ __forceinline__ int nearest_mean(const double* y, const double (*mu)[3], int k) {
+  int best = 0;
+  double bd = dist2(y, mu[0]);
+  for (int j = 1; j < k; ++j) {
+    const double d = dist2(y, mu[j]);
+    if (d < bd) {
+      best = j;
+      bd = d;
+    }
+  }
+  return best;
+}
+
+// Index of the largest v[0..n) (lowest index among equals), for all threads.
+__device__ int block_argmax(const double* v, int n, double* wv, int* wi, int* out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double bv = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int i = tid; i < n; i += kClusterWG)
+    if (v[i] > bv) {  // increasing i: an equal later value never replaces
+      bv = v[i];
+      bi = i;
+    }
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ov = __shfl_xor(bv, m);
+    const int oi = __shfl_xor(bi, m);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    wv[wave] = bv;
+    wi[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double b = wv[0];
+    int i0 = wi[0];
+    for (int w = 1; w < kClusterWaves; ++w)
+      if (wv[w] > b || (wv[w] == b && wi[w] < i0)) {
+        b = wv[w];
+        i0 = wi[w];
+      }
+    *out = i0;
+  }
+  __syncthreads();
+  return *out;
+}
+
+__global__ __launch_bounds__(kClusterWG) void k_cluster(int S, const double* __restrict__ obj, int n_sel,
+                                                        const int* __restrict__ sel, int k, int cmax,
+                                                        int* __restrict__ members, int* __restrict__ assign,
+                                                        double* __restrict__ means_out) {
+#pragma clang fp contract(off)
+  __shared__ int s_idx[kClusterSelMax];
+  __shared__ double s_Y[kClusterSelMax][3];
+  __shared__ double s_d[kClusterSelMax];
+  __shared__ int s_lab[kClusterSelMax];
+  __shared__ double s_mu[kClusterMax][3];
+  __shared__ int s_lead[kClusterMax];
+  __shared__ double s_lo[3], s_rng[3];
+  __shared__ double s_red[kClusterWaves][6];
+  __shared__ int s_wcnt[kClusterWaves];
+  __shared__ double s_wv[kClusterWaves];
+  __shared__ int s_wi[kClusterWaves];
+  __shared__ int s_n, s_arg;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // valid selected solutions, compacted in selection order
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  for (int base = 0; base < n_sel; base += kClusterWG) {
+    const int i = base + tid;
+    const int s = i < n_sel ? sel[i] : -1;
+    const bool v = s >= 0 && s < S;
+    const unsigned long long m = __ballot(v);
+    const int pre = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    if (lane == 0) s_wcnt[wave] = __popcll(m);
+    __syncthreads();
+    int off = s_n;
+    for (int w = 0; w < wave; ++w) off += s_wcnt[w];
+    if (v) s_idx[off + pre] = s;
+    __syncthreads();
+    if (tid == 0) {
+      int t = s_n;
+      for (int w = 0; w < kClusterWaves; ++w) t += s_wcnt[w];
+      s_n = t;
+    }
+    __syncthreads();
+  }
+  const int n = s_n;
+  const int c = min(n, (2 * n + k - 1) / k);
+  for (int e = tid; e < k * cmax; e += kClusterWG)
+    if (n < k || e % cmax >= c) members[e] = -1;
+  if (n < k) {
+    for (int s = tid; s < S; s += kClusterWG) assign[s] = -1;
+    if (means_out && tid < 3 * k) means_out[tid] = NAN;
+    return;
+  }
+  // per-objective range over the selection (min and max are order-free)
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = tid; i < n; i += kClusterWG)
+    for (int o = 0; o < 3; ++o) {
+      const double x = obj[(size_t)s_idx[i] * 3 + o];
+      lo[o] = fmin(lo[o], x);
+      hi[o] = fmax(hi[o], x);
+    }
+  for (int m = 32; m >= 1; m >>= 1)
+    for (int o = 0; o < 3; ++o) {
+      lo[o] = fmin(lo[o], __shfl_xor(lo[o], m));
+      hi[o] = fmax(hi[o], __shfl_xor(hi[o], m));
+    }
+  if (lane == 0)
+    for (int o = 0; o < 3; ++o) {
+      s_red[wave][o] = lo[o];
+      s_red[wave][3 + o] = hi[o];
+    }
+  __syncthreads();
+  if (tid < 3) {
+    double a = s_red[0][tid], b = s_red[0][3 + tid];
+    for (int w = 1; w < kClusterWaves; ++w) {
+      a = fmin(a, s_red[w][tid]);
+      b = fmax(b, s_red[w][3 + tid]);
+    }
+    s_lo[tid] = a;
+    s_rng[tid] = b - a > 0.0 ? b - a : 1.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kClusterWG)
+    for (int o = 0; o < 3; ++o) s_Y[i][o] = (obj[(size_t)s_idx[i] * 3 + o] - s_lo[o]) / s_rng[o];
+  __syncthreads();
+  // farthest-first leaders
+  for (int i = tid; i < n; i += kClusterWG) s_d[i] = s_Y[i][0];
+  __syncthreads();
+  int lead = block_argmax(s_d, n, s_wv, s_wi, &s_arg);
+  if (tid == 0) s_lead[0] = lead;
+  for (int i = tid; i < n; i += kClusterWG) s_d[i] = dist2(s_Y[i], s_Y[lead]);
+  __syncthreads();
+  for (int l = 1; l < k; ++l) {
+    lead = block_argmax(s_d, n, s_wv, s_wi, &s_arg);
+    if (tid == 0) s_lead[l] = lead;
+    for (int i = tid; i < n; i += kClusterWG) s_d[i] = fmin(s_d[i], dist2(s_Y[i], s_Y[lead]));
+    __syncthreads();
+  }
+  if (tid < 3 * k) s_mu[tid / 3][tid % 3] = s_Y[s_lead[tid / 3]][tid % 3];
+  for (int i = tid; i < n; i += kClusterWG) s_lab[i] = -1;
+  __syncthreads();
+  // k-means from the leaders
+  for (int it = 0; it < kClusterRounds; ++it) {
+    int changed = 0;
+    for (int i = tid; i < n; i += kClusterWG) {
+      const int j = nearest_mean(s_Y[i], s_mu, k);
+      changed |= j != s_lab[i];
+      s_lab[i] = j;
+    }
+    if (!__syncthreads_or(changed)) break;
+    if (tid < 3 * k) {
+      const int j = tid / 3, o = tid % 3;
+      double acc = 0.0;
+      int cnt = 0;
+      for (int i = 0; i < n; ++i)
+        if (s_lab[i] == j) {
+          acc += s_Y[i][o];
+          ++cnt;
+        }
+      if (cnt) s_mu[j][o] = acc / cnt;
+    }
+    __syncthreads();
+  }
+  // cluster j: the c selected solutions nearest to mean j (rank by distance, then position)
+  for (int j = 0; j < k; ++j) {
+    for (int i = tid; i < n; i += kClusterWG) s_d[i] = dist2(s_Y[i], s_mu[j]);
+    __syncthreads();
+    for (int i = tid; i < n; i += kClusterWG) {
+      const double di = s_d[i];
+      int rank = 0;
+      for (int m = 0; m < n; ++m) rank += s_d[m] < di || (s_d[m] == di && m < i);
+      if (rank < c) members[(size_t)j * cmax + rank] = s_idx[i];
+    }
+    __syncthreads();
+  }
+  for (int s = tid; s < S; s += kClusterWG) {
+    double y[3];
+    for (int o = 0; o < 3; ++o) y[o] = (obj[(size_t)s * 3 + o] - s_lo[o]) / s_rng[o];
+    assign[s] = nearest_mean(y, s_mu, k);
+  }
+  if (means_out && tid < 3 * k) means_out[tid] = s_mu[tid / 3][tid % 3];
+}
+
 }  // namespace
 }  // namespace dsm
 
@@ -400,14 +611,16 @@ dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X,
 }
 
 dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
-                                const double* mean, const double* chol, const float* mult, uint64_t seed,
-                                uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream) {
+                                const double* mean, const double* chol, const float* mult, int32_t n_clusters,
+                                const int32_t* cluster, uint64_t seed, uint64_t counter, const uint64_t* counter_dev,
+                                float* cand, void* stream) {
   if (!p || S < 0 || F < 0 || K < 1) return DSM_ERR_ARG;
   const int64_t n = (int64_t)S * F * K;
   if (n == 0) return DSM_OK;  // empty buffers may be null
-  if (!X || !fos_pts || !mean || !chol || !mult || !cand) return DSM_ERR_ARG;
+  if (!X || !fos_pts || !mean || !chol || !mult || !cand || n_clusters < 1) return DSM_ERR_ARG;
   k_sample_est<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-      p->dev, S, X, F, fos_pts, K, mean, chol, mult, seed, counter, (const unsigned long long*)counter_dev, cand);
+      p->dev, S, X, F, fos_pts, K, mean, chol, mult, n_clusters, cluster, seed, counter,
+      (const unsigned long long*)counter_dev, cand);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 
@@ -423,13 +636,26 @@ dsm_status dsm_estimate_elements(dsm_problem* p, int32_t S, const float* X, int3
 
 dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
                                const int32_t* fos_pts, const double* mean, const double* chol, const float* mult,
-                               uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand, void* stream) {
+                               int32_t n_clusters, const int32_t* cluster, uint64_t seed, uint64_t counter,
+                               const uint64_t* counter_dev, float* cand, void* stream) {
   if (!p || S < 0 || F < 0) return DSM_ERR_ARG;
   const int64_t n = (int64_t)S * F;
   if (n == 0) return DSM_OK;  // empty buffers may be null
-  if (!X || !fos_off || !fos_pts || !mean || !chol || !mult || !cand) return DSM_ERR_ARG;
+  if (!X || !fos_off || !fos_pts || !mean || !chol || !mult || !cand || n_clusters < 1) return DSM_ERR_ARG;
   k_sample_el<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-      p->dev, S, X, F, fos_off, fos_pts, mean, chol, mult, seed, counter, (const unsigned long long*)counter_dev, cand);
+      p->dev, S, X, F, fos_off, fos_pts, mean, chol, mult, n_clusters, cluster, seed, counter,
+      (const unsigned long long*)counter_dev, cand);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_cluster_objectives(int32_t S, const double* obj, int32_t n_sel, const int32_t* sel, int32_t k,
+                                  int32_t* members, int32_t* assign, double* means, void* stream) {
+  if (S < 0 || n_sel < 0 || k < 1 || k > kClusterMax) return DSM_ERR_ARG;
+  if (n_sel > kClusterSelMax) return DSM_ERR_CAPACITY;
+  const int cmax = std::min<int>(n_sel, (2 * n_sel + k - 1) / k);
+  if ((S > 0 && (!obj || !assign)) || (n_sel > 0 && !sel) || (cmax > 0 && !members)) return DSM_ERR_ARG;
+  if (S == 0 && cmax == 0 && !means) return DSM_OK;  // nothing to write
+  k_cluster<<<1, kClusterWG, 0, (hipStream_t)stream>>>(S, obj, n_sel, sel, k, cmax, members, assign, means);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 

@@ -13,6 +13,9 @@ namespace dsm {
 constexpr int kWG = 256;          // threads per workgroup of the evaluation kernels
 constexpr int kWaves = kWG / 64;  // wave64 waves per workgroup
 constexpr double kLat = 128.0;    // lattice steps per voxel
+// Clustering in objective space: at most kClusterMax clusters over at most
+// kClusterSelMax selected solutions, at most kClusterRounds k-means rounds.
+constexpr int kClusterMax = 16, kClusterSelMax = 1024, kClusterRounds = 50;
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
 constexpr int kPartChunk = 8;     // affected tetrahedra per workgroup in partial evaluation
 constexpr int kMaxChunk = kFullChunk > kPartChunk ? kFullChunk : kPartChunk;

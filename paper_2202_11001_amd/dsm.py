@@ -83,9 +83,10 @@ def lib():
             "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_estimate_distributions": ([V, I, V, I, V, I, V, V, V, V], I),
-            "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, I, V, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_estimate_elements": ([V, I, V, I, V, I, V, V, V, V, V], I),
-            "dsm_sample_elements": ([V, I, V, I, V, V, V, V, V, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_sample_elements": ([V, I, V, I, V, V, V, V, V, I, V, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_cluster_objectives": ([I, V, I, V, I, V, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
@@ -147,6 +148,23 @@ def refine_population(mesh_coarse, Xc, out=None, stream=None):
     return out
 
 
+def cluster_objectives(obj, sel, k, stream=None):
+    """Balanced k-leader-means clustering of the selected solutions sel [n]
+    int32 in objective space obj [S][3] float64 (``dsm_cluster_objectives``):
+    (members [k][cmax] int32, assign [S] int32, means [k][3] float64)."""
+    torch = _torch()
+    if obj.dtype != torch.float64 or obj.dim() != 2 or obj.shape[1] != 3 or sel.dtype != torch.int32:
+        raise ValueError("cluster_objectives: obj float64 [S][3] and sel int32 [n] expected")
+    S, n = obj.shape[0], sel.shape[0]
+    cmax = min(n, -(-2 * n // k)) if k > 0 else 0
+    members = torch.empty((max(k, 0), cmax), dtype=torch.int32, device=obj.device)
+    assign = torch.empty(S, dtype=torch.int32, device=obj.device)
+    means = torch.empty((max(k, 0), 3), dtype=torch.float64, device=obj.device)
+    _check(lib().dsm_cluster_objectives(S, _dptr(obj), n, _dptr(sel), int(k), _dptr(members) if cmax else None,
+                                        _dptr(assign) if S else None, _dptr(means), _stream(stream)))
+    return members, assign, means
+
+
 def mesh_topology(mesh, dims=None):
     """Host-only topology: dict of counts, tets [T][4], star_off, star, identity [P][3]."""
     L = lib()
@@ -167,6 +185,19 @@ def mesh_topology(mesh, dims=None):
 def _torch():
     import torch
     return torch
+
+
+def _check_dist(mean, chol, mult, cluster, S, n_dist, n_var, n_tri):
+    """Host-side shape and dtype checks of per-element distributions before a
+    sampler launch reads them: mean float64 [n_dist][n_var], chol float64
+    [n_dist][n_tri], mult float32 [n_dist], cluster int32 [S] or None."""
+    torch = _torch()
+    for name, t, dt, n in (("mean", mean, torch.float64, n_dist * n_var), ("chol", chol, torch.float64, n_dist * n_tri),
+                           ("mult", mult, torch.float32, n_dist)):
+        if t.dtype != dt or t.numel() != n:
+            raise ValueError(f"{name}: expected {dt} with {n} elements, got {t.dtype} with {t.numel()}")
+    if cluster is not None and (cluster.dtype != torch.int32 or cluster.numel() != S):
+        raise ValueError(f"cluster: expected int32 [{S}]")
 
 
 def _dptr(t):
@@ -296,6 +327,8 @@ class Problem:
         """(mean [F][6], lower Cholesky factor [F][21]) float64 of the single
         points pts [F] over the selected solutions sel [n] (int32) of X."""
         torch = _torch()
+        if sel.dtype != torch.int32 or X.dtype != torch.float32:
+            raise ValueError("X float32 and sel int32 expected")
         F = pts.shape[0]
         mean = torch.empty((F, 6), dtype=torch.float64, device=X.device)
         chol = torch.empty((F, 21), dtype=torch.float64, device=X.device)
@@ -303,17 +336,22 @@ class Problem:
                                                 _dptr(mean), _dptr(chol), _stream(stream)))
         return mean, chol
 
-    def sample_estimated(self, X, pts, K, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None):
+    def sample_estimated(self, X, pts, K, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None,
+                         cluster=None):
         """Candidates [S][F][K][2][3] (K > 1) or [S][F][2][3] (K == 1) drawn from
-        N(mean, mult * L L^T) on the free coordinates (mult float32 [F])."""
+        N(mean, mult * L L^T) on the free coordinates (mult float32 [F]); with
+        ``cluster`` [S] int32, mean/chol/mult hold one distribution per cluster
+        ([C][F][...]) and solution s uses cluster[s]."""
         torch = _torch()
         S, F = X.shape[0], pts.shape[0]
         if out is None:
             shape = (S, F, 2, 3) if K == 1 else (S, F, K, 2, 3)
             out = torch.empty(shape, dtype=torch.float32, device=X.device)
+        nc = max(1, mean.numel() // max(1, 6 * F))
+        _check_dist(mean, chol, mult, cluster, S, nc * F, 6, 21)
         _check(lib().dsm_sample_estimated(self._h, S, _dptr(X), F, _dptr(pts), int(K), _dptr(mean), _dptr(chol),
-                                          _dptr(mult), int(seed), int(counter), _dptr(counter_dev), _dptr(out),
-                                          _stream(stream)))
+                                          _dptr(mult), nc, _dptr(cluster), int(seed), int(counter),
+                                          _dptr(counter_dev), _dptr(out), _stream(stream)))
         return out
 
     def accept(self, X, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
@@ -327,6 +365,8 @@ class Problem:
         """Joint distributions of elements of up to 4 points (CSR off, pts):
         (mean [F][24], lower Cholesky factor [F][300]) float64."""
         torch = _torch()
+        if sel.dtype != torch.int32 or X.dtype != torch.float32:
+            raise ValueError("X float32 and sel int32 expected")
         F = off.shape[0] - 1
         mean = torch.empty((F, 24), dtype=torch.float64, device=X.device)
         chol = torch.empty((F, 300), dtype=torch.float64, device=X.device)
@@ -334,15 +374,20 @@ class Problem:
                                            _dptr(pts), _dptr(mean), _dptr(chol), _stream(stream)))
         return mean, chol
 
-    def sample_elements(self, X, off, pts, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None):
-        """Candidates [S][len(pts)][2][3] drawn from the elements' joint distributions."""
+    def sample_elements(self, X, off, pts, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None,
+                        cluster=None):
+        """Candidates [S][len(pts)][2][3] drawn from the elements' joint
+        distributions; with ``cluster`` [S] int32 the distributions are per
+        cluster ([C][F][...]) and solution s uses cluster[s]."""
         torch = _torch()
         S, F = X.shape[0], off.shape[0] - 1
         if out is None:
             out = torch.empty((S, pts.shape[0], 2, 3), dtype=torch.float32, device=X.device)
+        nc = max(1, mean.numel() // max(1, 24 * F))
+        _check_dist(mean, chol, mult, cluster, S, nc * F, 24, 300)
         _check(lib().dsm_sample_elements(self._h, S, _dptr(X), F, _dptr(off), _dptr(pts), _dptr(mean), _dptr(chol),
-                                         _dptr(mult), int(seed), int(counter), _dptr(counter_dev), _dptr(out),
-                                         _stream(stream)))
+                                         _dptr(mult), nc, _dptr(cluster), int(seed), int(counter),
+                                         _dptr(counter_dev), _dptr(out), _stream(stream)))
         return out
 
     def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,

@@ -84,11 +84,13 @@ def merge_archive(archive, new):
     return out[np.lexsort(out.T[::-1])]
 
 
-def merge_archive_device(arch, n, new):
+def merge_archive_device(arch, n, new, arch_X=None, new_X=None):
     """merge_archive on the device: arch float64 [capacity][3] holds the
     archive in rows 0..n-1 (+inf after), new [m][3]; the non-dominated rows of
     both (duplicates kept once) are written back to arch in lexicographic order,
-    the remaining rows set to +inf.  Returns their number."""
+    the remaining rows set to +inf.  With a payload (arch_X [capacity][...]
+    holding the archived rows' solutions, new_X [m][...]) the solutions move
+    with their rows.  Returns their number."""
     import torch
     pts = torch.cat([arch[:n], new.to(torch.float64)])
     M = pts.shape[0]
@@ -101,13 +103,15 @@ def merge_archive_device(arch, n, new):
         eq = (pts[None, :, :] == blk[:, None, :]).all(-1)
         earlier = idx[None, :] < idx[b:b + 2048, None]
         keep[b:b + 2048] = ~(le & lt).any(1) & ~(eq & earlier).any(1)
-    out = pts[keep]
+    rows = idx[keep]
     for c in (2, 1, 0):  # lexicographic: stable sorts from the last key
-        out = out[torch.argsort(out[:, c], stable=True)]
-    k = out.shape[0]
+        rows = rows[torch.argsort(pts[rows, c], stable=True)]
+    k = rows.shape[0]
     if k > arch.shape[0]:
         raise ValueError(f"archive of {k} points exceeds the capacity {arch.shape[0]}")
-    arch[:k] = out
+    if arch_X is not None:
+        arch_X[:k] = torch.cat([arch_X[:n], new_X])[rows]
+    arch[:k] = pts[rows]
     arch[k:] = float("inf")
     return k
 
@@ -172,7 +176,7 @@ class Optimiser:
     host work.  Eager and graph generations give bit-identical results."""
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
-                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point"):
+                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1):
         import torch
         self.torch = torch
         self.p = problem
@@ -198,7 +202,7 @@ class Optimiser:
             self.generation_index = 0
             self.classes = None  # drawn per generation
             n_cubes = int(np.prod([int(n) - 1 for n in problem.mesh]))
-            self.mult_cube = torch.ones(n_cubes, dtype=torch.float32, device=dev)  # per-cube multipliers
+            self.n_cubes = n_cubes
         self.cache = torch.empty((self.S, problem.T, 3), dtype=torch.float64, device=dev)
         self.terms_cand = torch.zeros_like(self.cache)
         obj, flags = problem.eval_full(self.X, tet_terms=self.cache)
@@ -206,17 +210,15 @@ class Optimiser:
             raise ValueError("initial population is infeasible")
         self.obj = obj
         self.keep_solutions = bool(keep_solutions)
-        self.archive_X = None  # with keep_solutions: the solution of every archive row (host)
         self.capacity = int(archive_capacity)
-        # elitist archive: on the host with keep_solutions, else on the device
-        # (arch_dev rows 0..n_arch-1, +inf after) with a host copy made on demand
+        # elitist archive on the device: arch_dev rows 0..n_arch-1 (+inf after),
+        # with keep_solutions the solution of every row in arch_X_dev; host
+        # copies are made on demand
         self.arch_dev = torch.full((self.capacity, 3), float("inf"), dtype=torch.float64, device=dev)
+        self.arch_X_dev = torch.empty((self.capacity,) + tuple(X.shape[1:]), dtype=X.dtype, device=dev) \
+            if self.keep_solutions else None
         self._archive = None
-        if self.keep_solutions:
-            self._archive, self.archive_X = merge_archive_with(np.zeros((0, 3)), None, obj.cpu().numpy(),
-                                                               self.X.cpu().numpy())
-        else:
-            self.n_arch = merge_archive_device(self.arch_dev, 0, obj)
+        self.n_arch = merge_archive_device(self.arch_dev, 0, obj, self.arch_X_dev, self.X)
         self.ref = 1.1 * obj.cpu().numpy().max(axis=0)
         self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
         # sampler counter: generation g uses counters 8 g + 1 ... 8 g + 8
@@ -229,12 +231,19 @@ class Optimiser:
         if sampler not in ("isotropic", "estimated"):
             raise ValueError(f"unknown sampler {sampler!r}")
         self.sampler = sampler
+        self.k = int(clusters)
+        if not 1 <= self.k <= 16 or (self.k > 1 and sampler != "estimated"):
+            raise ValueError("clusters: 1 to 16, more than 1 only with the estimated sampler")
+        self._assign = None  # cluster of every solution (device int32) when k > 1
         if sampler == "estimated":
             if self.use_graph:
                 raise ValueError("the estimated sampler runs eagerly (its selection needs the current objectives)")
             self.tau = float(tau)
+            # distribution multipliers per cluster and element (per cube for the tetrahedron FOS)
             if fos == "point":
-                self.mult = [torch.ones(len(c), dtype=torch.float32, device=dev) for c in self.classes]
+                self.mult = [torch.ones((self.k, len(c)), dtype=torch.float32, device=dev) for c in self.classes]
+            else:
+                self.mult_cube = torch.ones((self.k, self.n_cubes), dtype=torch.float32, device=dev)
             self._dist = None
 
     @property
@@ -248,15 +257,10 @@ class Optimiser:
             self._archive = self.arch_dev[:self.n_arch].cpu().numpy()
         return self._archive
 
-    def _load_archive(self):
-        if not self.keep_solutions:
-            return  # the device archive is current
-        n = len(self.archive)
-        if n > self.capacity:
-            raise ValueError(f"archive of {n} points exceeds the capacity {self.capacity}")
-        self.arch_dev[n:].fill_(float("inf"))
-        if n:
-            self.arch_dev[:n].copy_(self.torch.from_numpy(np.ascontiguousarray(self.archive)))
+    @property
+    def archive_X(self):
+        """With keep_solutions: the solution of every archive row (host copy), else None."""
+        return None if self.arch_X_dev is None else self.arch_X_dev[:self.n_arch].cpu().numpy()
 
     def _tet_steps(self, surrogate):
         """One generation of the paper's FOS: per class of cubes, one random
@@ -269,7 +273,7 @@ class Optimiser:
         dev = self.X.device
         rng = np.random.default_rng([self.seed, self.generation_index])
         self.generation_index += 1
-        sel = self.select() if self.sampler == "estimated" else None
+        members = self._cluster() if self.sampler == "estimated" else None
         outs = []
         for c, cubes in enumerate(self.cube_classes):
             r = rng.integers(0, 6, size=len(cubes))
@@ -280,19 +284,22 @@ class Optimiser:
             if self.sampler == "isotropic":
                 cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
             else:
-                mean, chol = self.p.estimate_elements(self.X, sel, off, pts)
-                mult = self.mult_cube[cubes_d].contiguous()
+                est = [self.p.estimate_elements(self.X, m, off, pts) for m in members]
+                mean = torch.stack([e[0] for e in est]).contiguous()
+                chol = torch.stack([e[1] for e in est]).contiguous()
+                mult = self.mult_cube[:, cubes_d].contiguous()
                 cand = self.p.sample_elements(self.X, off, pts, mean, chol, mult, self.seed, c + 1,
-                                              counter_dev=self.counter_dev)
+                                              counter_dev=self.counter_dev, cluster=self._assign)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
                                                      tet_terms_new=self.terms_cand)
             acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
             self.p.accept_elements(self.X, off, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
                                    archive=self.arch_dev, accepted=acc)
             if self.sampler == "estimated":
-                hit = (acc != 0).any(dim=0)
-                m = self.mult_cube[cubes_d]
-                self.mult_cube[cubes_d] = torch.where(hit, torch.clamp(m / 0.9, max=10.0), torch.clamp(m * 0.9, min=0.05))
+                hit = self._hits(acc)
+                m = self.mult_cube[:, cubes_d]
+                self.mult_cube[:, cubes_d] = torch.where(hit, torch.clamp(m / 0.9, max=10.0),
+                                                         torch.clamp(m * 0.9, min=0.05))
             outs.append((None, acc, cand, old, new, flags))
         self.counter_dev += self.n_classes
         return outs
@@ -330,7 +337,27 @@ class Optimiser:
             return self.p.sample_candidates(self.X, pts, K, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
         mean, chol = self._dist[c]
         return self.p.sample_estimated(self.X, pts, K, mean, chol, self.mult[c], self.seed, c + 1,
-                                       counter_dev=self.counter_dev)
+                                       counter_dev=self.counter_dev, cluster=self._assign)
+
+    def _cluster(self):
+        """Selection, and with k > 1 clusters its balanced k-leader-means
+        clustering in objective space (MO-RV-GOMEA): the member lists whose
+        distributions are estimated, one per cluster; every solution samples
+        from its nearest cluster (self._assign)."""
+        sel = self.select()
+        if self.k == 1:
+            return [sel]
+        members, self._assign, _ = dsm.cluster_objectives(self.obj, sel, self.k)
+        return [members[j] for j in range(self.k)]
+
+    def _hits(self, acc):
+        """[k][F] bool: some solution of the cluster had element f accepted."""
+        torch = self.torch
+        a = (acc != 0).to(torch.float32)
+        if self.k == 1:
+            return (a.sum(dim=0) > 0)[None]
+        onehot = (self._assign[:, None] == torch.arange(self.k, device=acc.device)[None, :]).to(torch.float32)
+        return (onehot.T @ a) > 0
 
     def select(self):
         """Indices (int32, device) of the tau fraction of the population with the
@@ -349,10 +376,13 @@ class Optimiser:
     def generation(self, surrogate=None, log=None):
         """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
         torch = self.torch
-        self._load_archive()
         if self.sampler == "estimated" and self.fos == "point":
-            sel = self.select()
-            self._dist = [self.p.estimate_distributions(self.X, sel, pts) for pts in self.classes]
+            members = self._cluster()
+            self._dist = []
+            for pts in self.classes:
+                est = [self.p.estimate_distributions(self.X, m, pts) for m in members]
+                self._dist.append((torch.stack([e[0] for e in est]).contiguous(),
+                                   torch.stack([e[1] for e in est]).contiguous()))
         if self.use_graph and self.collect is None:
             if self._graph is None or self._graph_sur is not surrogate:
                 # warm up once on a side stream, then capture
@@ -369,17 +399,16 @@ class Optimiser:
             outs = self._steps(surrogate)
         if self.sampler == "estimated" and self.fos == "point":
             for c, (_, acc, *_) in enumerate(outs):
-                hit = (acc != 0).any(dim=0)
+                hit = self._hits(acc)
                 self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
                                            torch.clamp(self.mult[c] * 0.9, min=0.05))
-        n_exact = sum(self.S * acc.shape[1] if mask is None else int(mask.sum().item()) for mask, acc, *_ in outs)
-        n_acc = sum(int(acc.sum().item()) for _, acc, *_ in outs)
-        if self.keep_solutions:
-            self._archive, self.archive_X = merge_archive_with(self._archive, self.archive_X, self.obj.cpu().numpy(),
-                                                               self.X.cpu().numpy())
-        else:
-            self.n_arch = merge_archive_device(self.arch_dev, self.n_arch, self.obj)
-            self._archive = None
+        counts = torch.stack([acc.sum(dtype=torch.int64) for _, acc, *_ in outs] +
+                             [mask.sum(dtype=torch.int64) for mask, *_ in outs if mask is not None]).cpu().numpy()
+        n_acc = int(counts[:len(outs)].sum())
+        masked = iter(counts[len(outs):])
+        n_exact = sum(self.S * acc.shape[1] if mask is None else int(next(masked)) for mask, acc, *_ in outs)
+        self.n_arch = merge_archive_device(self.arch_dev, self.n_arch, self.obj, self.arch_X_dev, self.X)
+        self._archive = None
         return n_exact, n_acc
 
     def hypervolume(self):
@@ -400,12 +429,13 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
-        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point"):
+        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point", clusters=1):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
-    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos)
+    opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos,
+                    clusters=clusters)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate
@@ -441,10 +471,10 @@ def seed_finer(opt, problem_fine, S_fine, seed=0):
     problem's constraints are replaced by further draws; returns the device
     population and the number of draws rejected."""
     import torch
-    if opt.archive_X is None:
+    pool = opt.archive_X
+    if pool is None:
         raise ValueError("the coarse optimiser must keep its archive solutions (keep_solutions=True)")
     rng = np.random.default_rng(seed)
-    pool = opt.archive_X
     dev = opt.X.device
     out, rejected = [], 0
     need = S_fine

@@ -97,3 +97,19 @@ def test_host_topology_equals_oracle(mesh, dims):
     np.testing.assert_array_equal(tp["star"], st)
     np.testing.assert_array_equal(tp["identity"], rp.identity())
     np.testing.assert_array_equal(tp["identity"], W.regular_grid(dims, mesh))
+
+
+def test_distribution_arguments_checked_on_host():
+    """A sampler launch never reads a distribution of the wrong dtype or size."""
+    import torch
+    ok = (torch.zeros((2, 3, 6), dtype=torch.float64), torch.zeros((2, 3, 21), dtype=torch.float64),
+          torch.ones((2, 3), dtype=torch.float32))
+    dsm._check_dist(*ok, torch.zeros(5, dtype=torch.int32), 5, 6, 6, 21)
+    with pytest.raises(ValueError):
+        dsm._check_dist(ok[0].float(), ok[1], ok[2], None, 5, 6, 6, 21)
+    with pytest.raises(ValueError):
+        dsm._check_dist(ok[0], ok[1][:1], ok[2], None, 5, 6, 6, 21)
+    with pytest.raises(ValueError):
+        dsm._check_dist(*ok, torch.zeros(4, dtype=torch.int32), 5, 6, 6, 21)
+    with pytest.raises(ValueError):
+        dsm.cluster_objectives(torch.zeros((4, 3), dtype=torch.float32), torch.zeros(2, dtype=torch.int32), 2)

@@ -1,0 +1,129 @@
+"""GPU clustering in objective space (dsm_cluster_objectives) bit for bit
+against the FP64 reference oracle/gomea_ref.cluster, per-cluster sampling,
+and optimiser runs that sample from clustered distributions."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gomea_ref as G
+from paper_2202_11001_amd import optimizer as O
+from paper_2202_11001_amd import workloads as W
+from tests._common import feasible_population, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_11001_amd import dsm  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(f"[gpu-cluster] {msg}", file=sys.stderr, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _check(obj, sel, k):
+    obj = np.asarray(obj, dtype=np.float64)
+    sel = np.asarray(sel, dtype=np.int32)
+    _say(f"S {len(obj)} n_sel {len(sel)} k {k}")
+    m, a, mu = dsm.cluster_objectives(_t(obj), _t(sel), k)
+    rm, ra, rmu = G.cluster(obj, sel, k)
+    m, a, mu = m.cpu().numpy(), a.cpu().numpy(), mu.cpu().numpy()
+    cmax = min(len(sel), -(-2 * len(sel) // k))
+    want = np.full((k, cmax), -1, np.int32)
+    want[:, :rm.shape[1]] = rm
+    np.testing.assert_array_equal(m, want)
+    np.testing.assert_array_equal(a, ra)
+    np.testing.assert_array_equal(mu, rmu)  # same operations in the same order: equal bits (NaN == NaN here)
+
+
+def test_cluster_matches_reference_random():
+    rng = np.random.default_rng(1)
+    for S, n, k in ((500, 175, 5), (90, 40, 4), (37, 13, 13), (64, 64, 1), (3000, 1024, 16),
+                    (256, 90, 7)):
+        obj = rng.uniform(0, 1, (S, 3)) * np.array([0.1, 5.0, 30.0]) + np.array([0.02, 0.0, 1.0])
+        sel = rng.choice(S, n, replace=False)
+        _check(obj, sel, k)
+
+
+def test_cluster_matches_reference_ties_and_edges():
+    rng = np.random.default_rng(2)
+    # integer-valued objectives: many exact ties in distances and leaders
+    obj = rng.integers(0, 3, (64, 3)).astype(np.float64)
+    _check(obj, np.arange(64), 5)
+    _check(obj, rng.permutation(64)[:30], 3)
+    # identical objectives (zero ranges), one constant objective
+    _check(np.ones((10, 3)), np.arange(10), 2)
+    o = rng.uniform(0, 1, (50, 3))
+    o[:, 1] = 7.0
+    _check(o, np.arange(0, 50, 2), 4)
+    # out-of-range indices dropped (trailing member slots -1), fewer valid than k, empty selection
+    _check(o, np.array([0, -1, 3, 50, 9, 12, 99, 20]), 2)
+    _check(o, np.array([4, -2, 60]), 3)
+    _check(o, np.zeros(0, np.int32), 2)
+    # separated blobs
+    centres = np.array([[0, 0, 10], [10, 0, 0], [0, 10, 0]], float)
+    blobs = np.concatenate([c + rng.normal(0, 0.5, (20, 3)) for c in centres])
+    _check(blobs, np.arange(60), 3)
+    with pytest.raises(dsm.DsmError):
+        dsm.cluster_objectives(_t(o), _t(np.arange(10, dtype=np.int32)), 17)
+    with pytest.raises(dsm.DsmError):
+        dsm.cluster_objectives(_t(np.zeros((2000, 3))), _t(np.arange(1025, dtype=np.int32)), 4)
+
+
+def test_sampling_per_cluster():
+    """Zero covariance: every candidate is its cluster's mean (snapped); an
+    out-of-range cluster gives NaN."""
+    w = W.batched()
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    I = gp.topology()["identity"]
+    S = 8
+    X = _t(np.repeat(np.stack([I, I])[None], S, axis=0))
+    p = 1 + 5 * (2 + 5 * 2)  # interior point
+    pts = _t(np.array([p], np.int32))
+    base = np.concatenate([I[p], I[p]]).astype(np.float64)
+    mean = np.stack([base + 1.0, base - 2.0, base + 0.5])[:, None, :]  # [3][1][6]
+    chol = np.zeros((3, 1, 21))
+    mult = np.ones((3, 1), np.float32)
+    cl = np.array([0, 1, 2, 1, 0, 2, 2, 3], np.int32)  # the last one is out of range
+    cand = gp.sample_estimated(X, pts, 1, _t(mean), _t(chol), _t(mult), 5, 1, cluster=_t(cl)).cpu().numpy()
+    for s in range(S - 1):
+        np.testing.assert_array_equal(cand[s, 0].reshape(6), mean[cl[s], 0].astype(np.float32))
+    assert np.all(np.isnan(cand[S - 1]))
+    # joint 4-point elements
+    ps = np.array([p, p + 1, p + 5, p + 25], np.int32)
+    off = _t(np.array([0, 4], np.int32))
+    mu = np.stack([np.concatenate([np.concatenate([I[q], I[q]]) for q in ps]).astype(np.float64) + d
+                   for d in (1.0, -1.0, 0.25)])
+    cand = gp.sample_elements(X, off, _t(ps), _t(mu[:, None, :]), _t(np.zeros((3, 1, 300))), _t(mult), 5, 1,
+                              cluster=_t(cl)).cpu().numpy()
+    for s in range(S - 1):
+        np.testing.assert_array_equal(cand[s].reshape(24), mu[cl[s]].astype(np.float32))
+    assert np.all(np.isnan(cand[S - 1]))
+
+
+@pytest.mark.parametrize("fos", ["point", "tetrahedron"])
+def test_optimiser_with_clusters(fos):
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4 if fos == "tetrahedron" else 1)
+    _say(f"6 generations, {fos} FOS, 4 clusters")
+    log, opt, _ = O.run(gp, _t(X), 6, seed=3, sampler="estimated", fos=fos, clusters=4)
+    assert log.hypervolume[-1] > log.hypervolume[0] and sum(log.accepted) > 0
+    assert int((gp.fold_check(opt.X) != 0).sum().item()) == 0
+    obj, flags = gp.eval_full(opt.X)
+    assert int((flags != 0).sum().item()) == 0
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    a = opt._assign.cpu().numpy()
+    assert a.shape == (opt.S,) and a.min() >= 0 and a.max() < 4
+    with pytest.raises(ValueError):
+        O.Optimiser(gp, _t(X), clusters=2)  # clusters need the estimated sampler

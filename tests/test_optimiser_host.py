@@ -71,3 +71,24 @@ def test_merge_archive_with_payload_matches_plain_merge():
     np.testing.assert_array_equal(arch, O.nondominated(pts))
     for row, p in zip(arch, ap[:, 0].astype(int)):
         np.testing.assert_array_equal(pts[p], row)  # every kept row carries its own payload
+
+
+def test_device_merge_payload_matches_host_merge():
+    """merge_archive_device (run here on CPU tensors) carries each row's solution
+    exactly as the host merge does, over several generations with duplicates."""
+    import torch
+    rng = np.random.default_rng(11)
+    cap = 512
+    arch = torch.full((cap, 3), float("inf"), dtype=torch.float64)
+    arch_X = torch.zeros((cap, 2, 3), dtype=torch.float32)
+    n, h_arch, h_pay = 0, np.zeros((0, 3)), None
+    for g in range(6):
+        new = np.round(rng.random((64, 3)), 2)
+        if n:
+            new[:3] = arch[:3].numpy()  # duplicates of archived rows: the archived payload is kept
+        new_X = rng.random((64, 2, 3)).astype(np.float32)
+        n = O.merge_archive_device(arch, n, torch.from_numpy(new), arch_X, torch.from_numpy(new_X))
+        h_arch, h_pay = O.merge_archive_with(h_arch, h_pay, new, new_X)
+        np.testing.assert_array_equal(arch[:n].numpy(), h_arch)
+        np.testing.assert_array_equal(arch_X[:n].numpy(), h_pay)
+        assert torch.all(torch.isinf(arch[n:]))
