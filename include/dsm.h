@@ -401,11 +401,16 @@ dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X,
  * solution s draws from those of cluster dev [S] entry cluster[s]; a cluster
  * index outside [0, n_clusters) gives NaN candidates.  cluster NULL: every
  * solution uses the first (n_clusters 1 for a single distribution).
- * Errors: DSM_ERR_ARG (also n_clusters < 1). */
+ * Anticipated mean shift (RV-GOMEA): with shift dev [P][6] float64 (per grid
+ * point, source x y z then target x y z) and ams dev [S] uint8, a solution
+ * with ams[s] != 0 draws around mean + delta * mult * shift[p] on the free
+ * coordinates (delta is 2 in RV-GOMEA); shift NULL: no shift (ams unused).
+ * Errors: DSM_ERR_ARG (also n_clusters < 1, or shift without ams). */
 dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
                                 const double* mean, const double* chol, const float* mult, int32_t n_clusters,
-                                const int32_t* cluster, uint64_t seed, uint64_t counter, const uint64_t* counter_dev,
-                                float* cand, void* stream);
+                                const int32_t* cluster, const double* shift, const uint8_t* ams, double delta,
+                                uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
+                                void* stream);
 
 /* dsm_estimate_distributions for elements of up to 4 points (e.g. the paper's
  * per-cube tetrahedra), jointly: the variables of element f are the
@@ -426,11 +431,15 @@ dsm_status dsm_estimate_elements(dsm_problem* p, int32_t S, const float* X, int3
  * element); pinned coordinates keep the solution's value; clamped to the box
  * and rounded to the lattice.  Elements rejected by dsm_estimate_elements get
  * NaN candidates (flagged non-finite by the evaluator); elements with
- * malformed offsets are not written.  Errors: DSM_ERR_ARG. */
+ * malformed offsets are not written.  Clusters (n_clusters, cluster) and the
+ * anticipated mean shift (shift dev [P][6], ams dev [S], delta) as for
+ * dsm_sample_estimated, with the shift of each of the element's points.
+ * Errors: DSM_ERR_ARG. */
 dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
                                const int32_t* fos_pts, const double* mean, const double* chol, const float* mult,
-                               int32_t n_clusters, const int32_t* cluster, uint64_t seed, uint64_t counter,
-                               const uint64_t* counter_dev, float* cand, void* stream);
+                               int32_t n_clusters, const int32_t* cluster, const double* shift, const uint8_t* ams,
+                               double delta, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
+                               void* stream);
 
 /* Balanced k-leader-means clustering of selected solutions in objective space
  * (MO-RV-GOMEA, on which the optimisation of Sec. 2.2 builds): per generation

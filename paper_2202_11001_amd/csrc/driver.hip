@@ -137,6 +137,7 @@ __global__ void k_estimate(DevProblem pr, int S, const float* __restrict__ X, in
 __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ pts, int K,
                              const double* __restrict__ mean, const double* __restrict__ chol,
                              const float* __restrict__ mult, int n_clusters, const int* __restrict__ cluster,
+                             const double* __restrict__ shift, const unsigned char* __restrict__ ams, double delta,
                              unsigned long long seed, unsigned long long counter,
                              const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
   const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -164,7 +165,9 @@ __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, 
     if (idx[a] > 0 && idx[a] < pr.n[a] - 1) {
       double w = 0.0;
       for (int t = 0; t <= c; ++t) w += L[c * (c + 1) / 2 + t] * z[t];
-      v = fmin(fmax(mu[c] + sc * w, -0.5), pr.D[a] - 0.5);
+      double m = mu[c];
+      if (shift && ams[s]) m += delta * (double)mult[d] * shift[(size_t)p * 6 + c];  // anticipated mean shift
+      v = fmin(fmax(m + sc * w, -0.5), pr.D[a] - 0.5);
     }
     out[c] = (float)(rint((v + 0.5) * kLat) / kLat - 0.5);
   }
@@ -262,7 +265,8 @@ __global__ __launch_bounds__(64) void k_estimate_el(DevProblem pr, int S, const 
 __global__ void k_sample_el(DevProblem pr, int S, const float* __restrict__ X, int F, const int* __restrict__ off,
                             const int* __restrict__ pts, const double* __restrict__ mean,
                             const double* __restrict__ chol, const float* __restrict__ mult, int n_clusters,
-                            const int* __restrict__ cluster, unsigned long long seed, unsigned long long counter,
+                            const int* __restrict__ cluster, const double* __restrict__ shift,
+                            const unsigned char* __restrict__ ams, double delta, unsigned long long seed, unsigned long long counter,
                             const unsigned long long* __restrict__ counter_dev, float* __restrict__ cand) {
   const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (counter_dev) counter += *counter_dev;
@@ -291,7 +295,9 @@ __global__ void k_sample_el(DevProblem pr, int S, const float* __restrict__ X, i
     if (idx > 0 && idx < pr.n[a] - 1) {
       double w = 0.0;
       for (int k = 0; k <= v; ++k) w += L[v * (v + 1) / 2 + k] * z[k];
-      x = fmin(fmax(mu[v] + sc * w, -0.5), pr.D[a] - 0.5);
+      double m = mu[v];
+      if (shift && ams[s]) m += delta * (double)mult[d] * shift[(size_t)p * 6 + c];  // anticipated mean shift
+      x = fmin(fmax(m + sc * w, -0.5), pr.D[a] - 0.5);
     }
     cand[((size_t)s * total + b + v / 6) * 6 + c] = (float)(rint((x + 0.5) * kLat) / kLat - 0.5);
   }
@@ -612,14 +618,15 @@ dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X,
 
 dsm_status dsm_sample_estimated(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_pts, int32_t K,
                                 const double* mean, const double* chol, const float* mult, int32_t n_clusters,
-                                const int32_t* cluster, uint64_t seed, uint64_t counter, const uint64_t* counter_dev,
-                                float* cand, void* stream) {
+                                const int32_t* cluster, const double* shift, const uint8_t* ams, double delta,
+                                uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
+                                void* stream) {
   if (!p || S < 0 || F < 0 || K < 1) return DSM_ERR_ARG;
   const int64_t n = (int64_t)S * F * K;
   if (n == 0) return DSM_OK;  // empty buffers may be null
-  if (!X || !fos_pts || !mean || !chol || !mult || !cand || n_clusters < 1) return DSM_ERR_ARG;
+  if (!X || !fos_pts || !mean || !chol || !mult || !cand || n_clusters < 1 || (shift && !ams)) return DSM_ERR_ARG;
   k_sample_est<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-      p->dev, S, X, F, fos_pts, K, mean, chol, mult, n_clusters, cluster, seed, counter,
+      p->dev, S, X, F, fos_pts, K, mean, chol, mult, n_clusters, cluster, shift, ams, delta, seed, counter,
       (const unsigned long long*)counter_dev, cand);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
@@ -636,14 +643,16 @@ dsm_status dsm_estimate_elements(dsm_problem* p, int32_t S, const float* X, int3
 
 dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
                                const int32_t* fos_pts, const double* mean, const double* chol, const float* mult,
-                               int32_t n_clusters, const int32_t* cluster, uint64_t seed, uint64_t counter,
-                               const uint64_t* counter_dev, float* cand, void* stream) {
+                               int32_t n_clusters, const int32_t* cluster, const double* shift, const uint8_t* ams,
+                               double delta, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
+                               void* stream) {
   if (!p || S < 0 || F < 0) return DSM_ERR_ARG;
   const int64_t n = (int64_t)S * F;
   if (n == 0) return DSM_OK;  // empty buffers may be null
-  if (!X || !fos_off || !fos_pts || !mean || !chol || !mult || !cand || n_clusters < 1) return DSM_ERR_ARG;
+  if (!X || !fos_off || !fos_pts || !mean || !chol || !mult || !cand || n_clusters < 1 || (shift && !ams))
+    return DSM_ERR_ARG;
   k_sample_el<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-      p->dev, S, X, F, fos_off, fos_pts, mean, chol, mult, n_clusters, cluster, seed, counter,
+      p->dev, S, X, F, fos_off, fos_pts, mean, chol, mult, n_clusters, cluster, shift, ams, delta, seed, counter,
       (const unsigned long long*)counter_dev, cand);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }

@@ -83,9 +83,11 @@ def lib():
             "dsm_eval_partial_masked": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_sample_candidates": ([V, I, V, I, V, I, C.c_float, C.c_uint64, C.c_uint64, V, V, V], I),
             "dsm_estimate_distributions": ([V, I, V, I, V, I, V, V, V, V], I),
-            "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, I, V, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_sample_estimated": ([V, I, V, I, V, I, V, V, V, I, V, V, V, C.c_double, C.c_uint64, C.c_uint64, V,
+                                      V, V], I),
             "dsm_estimate_elements": ([V, I, V, I, V, I, V, V, V, V, V], I),
-            "dsm_sample_elements": ([V, I, V, I, V, V, V, V, V, I, V, C.c_uint64, C.c_uint64, V, V, V], I),
+            "dsm_sample_elements": ([V, I, V, I, V, V, V, V, V, I, V, V, V, C.c_double, C.c_uint64, C.c_uint64, V,
+                                     V, V], I),
             "dsm_cluster_objectives": ([I, V, I, V, I, V, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V], I),
@@ -198,6 +200,18 @@ def _check_dist(mean, chol, mult, cluster, S, n_dist, n_var, n_tri):
             raise ValueError(f"{name}: expected {dt} with {n} elements, got {t.dtype} with {t.numel()}")
     if cluster is not None and (cluster.dtype != torch.int32 or cluster.numel() != S):
         raise ValueError(f"cluster: expected int32 [{S}]")
+
+
+def _check_shift(shift, ams, S, P):
+    """Host-side checks of the anticipated-mean-shift arguments: shift float64
+    [P][6] with ams uint8 [S], or neither."""
+    torch = _torch()
+    if shift is None:
+        return
+    if shift.dtype != torch.float64 or shift.numel() != 6 * P:
+        raise ValueError(f"shift: expected float64 [{P}][6]")
+    if ams is None or ams.dtype != torch.uint8 or ams.numel() != S:
+        raise ValueError(f"ams: expected uint8 [{S}] with a shift")
 
 
 def _dptr(t):
@@ -337,21 +351,24 @@ class Problem:
         return mean, chol
 
     def sample_estimated(self, X, pts, K, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None,
-                         cluster=None):
+                         cluster=None, shift=None, ams=None, delta=2.0):
         """Candidates [S][F][K][2][3] (K > 1) or [S][F][2][3] (K == 1) drawn from
         N(mean, mult * L L^T) on the free coordinates (mult float32 [F]); with
         ``cluster`` [S] int32, mean/chol/mult hold one distribution per cluster
-        ([C][F][...]) and solution s uses cluster[s]."""
+        ([C][F][...]) and solution s uses cluster[s]; with ``shift`` [P][6]
+        float64 and ``ams`` [S] uint8 the flagged solutions draw around
+        mean + delta * mult * shift (anticipated mean shift)."""
         torch = _torch()
         S, F = X.shape[0], pts.shape[0]
+        _check_shift(shift, ams, S, self.P)
         if out is None:
             shape = (S, F, 2, 3) if K == 1 else (S, F, K, 2, 3)
             out = torch.empty(shape, dtype=torch.float32, device=X.device)
         nc = max(1, mean.numel() // max(1, 6 * F))
         _check_dist(mean, chol, mult, cluster, S, nc * F, 6, 21)
         _check(lib().dsm_sample_estimated(self._h, S, _dptr(X), F, _dptr(pts), int(K), _dptr(mean), _dptr(chol),
-                                          _dptr(mult), nc, _dptr(cluster), int(seed), int(counter),
-                                          _dptr(counter_dev), _dptr(out), _stream(stream)))
+                                          _dptr(mult), nc, _dptr(cluster), _dptr(shift), _dptr(ams), float(delta),
+                                          int(seed), int(counter), _dptr(counter_dev), _dptr(out), _stream(stream)))
         return out
 
     def accept(self, X, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
@@ -375,19 +392,21 @@ class Problem:
         return mean, chol
 
     def sample_elements(self, X, off, pts, mean, chol, mult, seed, counter, out=None, stream=None, counter_dev=None,
-                        cluster=None):
+                        cluster=None, shift=None, ams=None, delta=2.0):
         """Candidates [S][len(pts)][2][3] drawn from the elements' joint
         distributions; with ``cluster`` [S] int32 the distributions are per
-        cluster ([C][F][...]) and solution s uses cluster[s]."""
+        cluster ([C][F][...]) and solution s uses cluster[s]; ``shift``, ``ams``
+        and ``delta`` as for sample_estimated."""
         torch = _torch()
         S, F = X.shape[0], off.shape[0] - 1
+        _check_shift(shift, ams, S, self.P)
         if out is None:
             out = torch.empty((S, pts.shape[0], 2, 3), dtype=torch.float32, device=X.device)
         nc = max(1, mean.numel() // max(1, 24 * F))
         _check_dist(mean, chol, mult, cluster, S, nc * F, 24, 300)
         _check(lib().dsm_sample_elements(self._h, S, _dptr(X), F, _dptr(off), _dptr(pts), _dptr(mean), _dptr(chol),
-                                         _dptr(mult), nc, _dptr(cluster), int(seed), int(counter),
-                                         _dptr(counter_dev), _dptr(out), _stream(stream)))
+                                         _dptr(mult), nc, _dptr(cluster), _dptr(shift), _dptr(ams), float(delta),
+                                         int(seed), int(counter), _dptr(counter_dev), _dptr(out), _stream(stream)))
         return out
 
     def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,

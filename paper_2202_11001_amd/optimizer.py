@@ -176,7 +176,7 @@ class Optimiser:
     host work.  Eager and graph generations give bit-identical results."""
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
-                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1):
+                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1, ams=False):
         import torch
         self.torch = torch
         self.p = problem
@@ -235,6 +235,15 @@ class Optimiser:
         if not 1 <= self.k <= 16 or (self.k > 1 and sampler != "estimated"):
             raise ValueError("clusters: 1 to 16, more than 1 only with the estimated sampler")
         self._assign = None  # cluster of every solution (device int32) when k > 1
+        # anticipated mean shift (RV-GOMEA): per generation half of the solutions
+        # draw around mean + 2 c (mu_t - mu_{t-1}), mu the selection's point means
+        self.use_ams = bool(ams)
+        if self.use_ams and sampler != "estimated":
+            raise ValueError("the anticipated mean shift needs the estimated sampler")
+        self._gen = 0
+        self._point_mean = None
+        self._shift = None
+        self._ams = None
         if sampler == "estimated":
             if self.use_graph:
                 raise ValueError("the estimated sampler runs eagerly (its selection needs the current objectives)")
@@ -289,7 +298,8 @@ class Optimiser:
                 chol = torch.stack([e[1] for e in est]).contiguous()
                 mult = self.mult_cube[:, cubes_d].contiguous()
                 cand = self.p.sample_elements(self.X, off, pts, mean, chol, mult, self.seed, c + 1,
-                                              counter_dev=self.counter_dev, cluster=self._assign)
+                                              counter_dev=self.counter_dev, cluster=self._assign, shift=self._shift,
+                                              ams=self._ams)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
                                                      tet_terms_new=self.terms_cand)
             acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
@@ -337,7 +347,8 @@ class Optimiser:
             return self.p.sample_candidates(self.X, pts, K, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
         mean, chol = self._dist[c]
         return self.p.sample_estimated(self.X, pts, K, mean, chol, self.mult[c], self.seed, c + 1,
-                                       counter_dev=self.counter_dev, cluster=self._assign)
+                                       counter_dev=self.counter_dev, cluster=self._assign, shift=self._shift,
+                                       ams=self._ams)
 
     def _cluster(self):
         """Selection, and with k > 1 clusters its balanced k-leader-means
@@ -345,6 +356,13 @@ class Optimiser:
         distributions are estimated, one per cluster; every solution samples
         from its nearest cluster (self._assign)."""
         sel = self.select()
+        if self.use_ams:
+            all_pts = self.torch.arange(self.p.P, dtype=self.torch.int32, device=self.X.device)
+            mean = self.p.estimate_distributions(self.X, sel, all_pts)[0]
+            self._shift = None if self._point_mean is None else (mean - self._point_mean).contiguous()
+            self._point_mean = mean
+            half = np.random.default_rng([self.seed, self._gen, 7]).permutation(self.S) < self.S // 2
+            self._ams = self.torch.from_numpy(half.astype(np.uint8)).to(self.X.device)
         if self.k == 1:
             return [sel]
         members, self._assign, _ = dsm.cluster_objectives(self.obj, sel, self.k)
@@ -407,6 +425,7 @@ class Optimiser:
         n_acc = int(counts[:len(outs)].sum())
         masked = iter(counts[len(outs):])
         n_exact = sum(self.S * acc.shape[1] if mask is None else int(next(masked)) for mask, acc, *_ in outs)
+        self._gen += 1
         self.n_arch = merge_archive_device(self.arch_dev, self.n_arch, self.obj, self.arch_X_dev, self.X)
         self._archive = None
         return n_exact, n_acc
@@ -429,13 +448,14 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
-        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point", clusters=1):
+        K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point", clusters=1,
+        ams=False):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
     opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos,
-                    clusters=clusters)
+                    clusters=clusters, ams=ams)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate

@@ -127,3 +127,61 @@ def test_optimiser_with_clusters(fos):
     assert a.shape == (opt.S,) and a.min() >= 0 and a.max() < 4
     with pytest.raises(ValueError):
         O.Optimiser(gp, _t(X), clusters=2)  # clusters need the estimated sampler
+
+
+def test_anticipated_mean_shift_sampling():
+    """Zero covariance: a flagged solution's candidate is mean + delta * mult *
+    shift on the free coordinates, an unflagged one the mean; pinned coordinates
+    keep the solution's value."""
+    w = W.batched()
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    I = gp.topology()["identity"]
+    S = 6
+    X = _t(np.repeat(np.stack([I, I])[None], S, axis=0))
+    p = 1 + 5 * (2 + 5 * 2)          # interior
+    q = 2 + 5 * (2 + 5 * 0)          # face point: z pinned in both grids
+    rng = np.random.default_rng(6)
+    shift = np.zeros((gp.P, 6))
+    shift[[p, q, p + 1, p + 5]] = rng.integers(-64, 65, (4, 6)) / 64.0  # lattice-exact after 2 * mult * shift
+    ams = np.array([1, 0, 1, 0, 1, 0], np.uint8)
+    free = lambda r: np.array([0 < (r % 5) < 4, 0 < (r // 5) % 5 < 4, 0 < r // 25 < 4] * 2)
+    # single points
+    pts = np.array([p, q], np.int32)
+    mean = np.stack([np.concatenate([I[r], I[r]]) for r in pts]).astype(np.float64)
+    mult = np.array([1.0, 0.5], np.float32)
+    cand = gp.sample_estimated(X, _t(pts), 1, _t(mean), _t(np.zeros((2, 21))), _t(mult), 5, 1,
+                               shift=_t(shift), ams=_t(ams), delta=2.0).cpu().numpy()
+    for s in range(S):
+        for f, r in enumerate(pts):
+            want = mean[f] + (2.0 * mult[f] * shift[r] * free(r) if ams[s] else 0.0)
+            np.testing.assert_array_equal(cand[s, f].reshape(6), want.astype(np.float32))
+    # a 4-point element
+    ps = np.array([p, p + 1, p + 5, q], np.int32)
+    mu = np.concatenate([np.concatenate([I[r], I[r]]) for r in ps]).astype(np.float64)
+    m1 = np.array([0.5], np.float32)
+    cand = gp.sample_elements(X, _t(np.array([0, 4], np.int32)), _t(ps), _t(mu[None]), _t(np.zeros((1, 300))),
+                              _t(m1), 5, 1, shift=_t(shift), ams=_t(ams), delta=2.0).cpu().numpy()
+    for s in range(S):
+        want = mu + (2.0 * 0.5 * np.concatenate([shift[r] * free(r) for r in ps]) if ams[s] else 0.0)
+        np.testing.assert_array_equal(cand[s].reshape(24), want.astype(np.float32))
+    with pytest.raises(ValueError):
+        gp.sample_estimated(X, _t(pts), 1, _t(mean), _t(np.zeros((2, 21))), _t(mult), 5, 1, shift=_t(shift))
+
+
+@pytest.mark.parametrize("fos", ["point", "tetrahedron"])
+def test_optimiser_with_anticipated_mean_shift(fos):
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4 if fos == "tetrahedron" else 1)
+    _say(f"6 generations, {fos} FOS, anticipated mean shift, 3 clusters")
+    log, opt, _ = O.run(gp, _t(X), 6, seed=4, sampler="estimated", fos=fos, clusters=3, ams=True)
+    assert log.hypervolume[-1] > log.hypervolume[0] and sum(log.accepted) > 0
+    assert opt._shift is not None and opt._shift.shape == (gp.P, 6)
+    assert int(opt._ams.sum()) == opt.S // 2
+    assert int((gp.fold_check(opt.X) != 0).sum().item()) == 0
+    obj, flags = gp.eval_full(opt.X)
+    assert int((flags != 0).sum().item()) == 0
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    with pytest.raises(ValueError):
+        O.Optimiser(gp, _t(X), ams=True)  # the shift needs the estimated sampler
