@@ -199,6 +199,10 @@ class Optimiser:
                 raise ValueError("the tetrahedron FOS runs eagerly (its elements are drawn every generation)")
             self.cube_classes = cube_classes(problem.mesh)
             self.tets = np.asarray(problem.topology()["tets"], dtype=np.int32)
+            # per class: its cubes and the element offsets (4 points each), on the device once
+            self.cubes_dev = [torch.from_numpy(c).to(dev) for c in self.cube_classes]
+            self.tet_offs = [torch.from_numpy((4 * np.arange(len(c) + 1)).astype(np.int32)).to(dev)
+                             for c in self.cube_classes]
             self.generation_index = 0
             self.classes = None  # drawn per generation
             n_cubes = int(np.prod([int(n) - 1 for n in problem.mesh]))
@@ -283,13 +287,15 @@ class Optimiser:
         rng = np.random.default_rng([self.seed, self.generation_index])
         self.generation_index += 1
         members = self._cluster() if self.sampler == "estimated" else None
+        # this generation's tetrahedron of every cube, uploaded in one copy
+        drawn = [self.tets[6 * cubes + rng.integers(0, 6, size=len(cubes))].reshape(-1) for cubes in self.cube_classes]
+        start = np.concatenate([[0], np.cumsum([len(d) for d in drawn])])
+        pts_all = torch.from_numpy(np.concatenate(drawn).astype(np.int32)).to(dev)
         outs = []
         for c, cubes in enumerate(self.cube_classes):
-            r = rng.integers(0, 6, size=len(cubes))
-            pts_h = self.tets[6 * cubes + r].reshape(-1).astype(np.int32)
-            pts = torch.from_numpy(pts_h).to(dev)
-            off = torch.from_numpy((4 * np.arange(len(cubes) + 1)).astype(np.int32)).to(dev)
-            cubes_d = torch.from_numpy(cubes).to(dev)
+            pts = pts_all[start[c]:start[c + 1]]
+            off = self.tet_offs[c]
+            cubes_d = self.cubes_dev[c]
             if self.sampler == "isotropic":
                 cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
             else:
