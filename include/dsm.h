@@ -441,6 +441,16 @@ dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_
                                double delta, uint64_t seed, uint64_t counter, const uint64_t* counter_dev, float* cand,
                                void* stream);
 
+/* Forced improvements (RV-GOMEA, on which the optimisation of Sec. 2.2
+ * builds): for every solution s whose donor dev [S] entry donor[s] lies in
+ * [0, S), the candidate of each listed point fos_pts dev [n_pts] becomes the
+ * donor solution's current coordinates in both grids: cand dev
+ * [S][n_pts][2][3] (the layout of dsm_eval_partial; for CSR elements n_pts =
+ * fos_off[F]).  Other solutions' candidates, and points outside [0, P), are
+ * left unchanged.  Errors: DSM_ERR_ARG. */
+dsm_status dsm_copy_from_donor(dsm_problem* p, int32_t S, const float* X, int32_t n_pts, const int32_t* fos_pts,
+                               const int32_t* donor, float* cand, void* stream);
+
 /* Balanced k-leader-means clustering of selected solutions in objective space
  * (MO-RV-GOMEA, on which the optimisation of Sec. 2.2 builds): per generation
  * one distribution per cluster and FOS element is estimated from the cluster's

@@ -381,6 +381,21 @@ __global__ void k_refine(int nx, int ny, int nz, int S, const float* __restrict_
   for (int d = 0; d < 3; ++d) y[d] = (float)(rint(u[d] * 0.125) / kLat - 0.5);
 }
 
+// Forced improvements (RV-GOMEA): a solution s with donor[s] in [0, S) takes,
+// for every listed point, the donor's current coordinates in both grids as its
+// candidate (cand [S][n][2][3], the partial-evaluation layout); other
+// solutions' candidates are left as they are.
+__global__ void k_donor(int S, int P, const float* __restrict__ X, int n, const int* __restrict__ pts,
+                        const int* __restrict__ donor, float* __restrict__ cand) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)S * n * 6) return;
+  const int s = (int)(e / ((int64_t)n * 6));
+  const int k = (int)((e / 6) % n), c = (int)(e % 6);
+  const int d = donor[s], p = pts[k];
+  if (d < 0 || d >= S || p < 0 || p >= P) return;
+  cand[e] = X[(((size_t)d * 2 + c / 3) * P + p) * 3 + c % 3];
+}
+
 // ---------------------------------------------------------------- clustering
 // Balanced k-leader-means of the selected solutions in objective space (the
 // clustering of MO-RV-GOMEA, on which the paper's optimiser builds, Sec. 2.2):
@@ -692,6 +707,16 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
                                                    terms_cand, terms_cache, obj, n_archive, archive, accepted);
   if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
   return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_copy_from_donor(dsm_problem* p, int32_t S, const float* X, int32_t n_pts, const int32_t* fos_pts,
+                               const int32_t* donor, float* cand, void* stream) {
+  if (!p || S < 0 || n_pts < 0) return DSM_ERR_ARG;
+  const int64_t n = (int64_t)S * n_pts * 6;
+  if (n == 0) return DSM_OK;  // empty buffers may be null
+  if (!X || !fos_pts || !donor || !cand) return DSM_ERR_ARG;
+  k_donor<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(S, p->dev.P, X, n_pts, fos_pts, donor, cand);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 
 dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_off,

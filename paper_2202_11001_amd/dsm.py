@@ -89,6 +89,7 @@ def lib():
             "dsm_sample_elements": ([V, I, V, I, V, V, V, V, V, I, V, V, V, C.c_double, C.c_uint64, C.c_uint64, V,
                                      V, V], I),
             "dsm_cluster_objectives": ([I, V, I, V, I, V, V, V, V], I),
+            "dsm_copy_from_donor": ([V, I, V, I, V, V, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
@@ -408,6 +409,18 @@ class Problem:
                                          _dptr(mult), nc, _dptr(cluster), _dptr(shift), _dptr(ams), float(delta),
                                          int(seed), int(counter), _dptr(counter_dev), _dptr(out), _stream(stream)))
         return out
+
+    def copy_from_donor(self, X, pts, donor, cand, stream=None):
+        """Forced improvements: candidates cand [S][len(pts)][2][3] of the
+        solutions with donor[s] >= 0 (int32 [S]) become the donor's current
+        coordinates at pts (in place); returns cand."""
+        torch = _torch()
+        S, n = X.shape[0], pts.shape[0]
+        if donor.dtype != torch.int32 or donor.numel() != S or pts.dtype != torch.int32 or cand.numel() != S * n * 6:
+            raise ValueError("copy_from_donor: donor int32 [S], pts int32 [n], cand [S][n][2][3] expected")
+        _check(lib().dsm_copy_from_donor(self._h, S, _dptr(X), n, _dptr(pts), _dptr(donor), _dptr(cand),
+                                         _stream(stream)))
+        return cand
 
     def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
                         accepted=None, stream=None):

@@ -176,7 +176,8 @@ class Optimiser:
     host work.  Eager and graph generations give bit-identical results."""
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
-                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1, ams=False):
+                 keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1, ams=False,
+                 forced_improvements=False, nis_max=None):
         import torch
         self.torch = torch
         self.p = problem
@@ -244,6 +245,17 @@ class Optimiser:
         self.use_ams = bool(ams)
         if self.use_ams and sampler != "estimated":
             raise ValueError("the anticipated mean shift needs the estimated sampler")
+        # forced improvements (RV-GOMEA): a solution without an accepted change for
+        # more than nis_max generations copies element values from a donor
+        self.use_fi = bool(forced_improvements)
+        if self.use_fi and graph:
+            raise ValueError("forced improvements run eagerly (donors are drawn on the host)")
+        self.nis_max = int(1 + np.floor(np.log10(self.S))) if nis_max is None else int(nis_max)
+        self.nis = torch.zeros(self.S, dtype=torch.int32, device=dev)
+        self._donor = None
+        self._fi = None
+        self.fi_forced = 0    # solutions given a donor, summed over generations
+        self.fi_replaced = 0  # of which replaced by their donor
         self._gen = 0
         self._point_mean = None
         self._shift = None
@@ -298,6 +310,7 @@ class Optimiser:
             cubes_d = self.cubes_dev[c]
             if self.sampler == "isotropic":
                 cand = self.p.sample_candidates(self.X, pts, 1, self.sigma, self.seed, c + 1, counter_dev=self.counter_dev)
+                self._force(pts, cand)
             else:
                 est = [self.p.estimate_elements(self.X, m, off, pts) for m in members]
                 mean = torch.stack([e[0] for e in est]).contiguous()
@@ -306,6 +319,7 @@ class Optimiser:
                 cand = self.p.sample_elements(self.X, off, pts, mean, chol, mult, self.seed, c + 1,
                                               counter_dev=self.counter_dev, cluster=self._assign, shift=self._shift,
                                               ams=self._ams)
+                self._force(pts, cand)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
                                                      tet_terms_new=self.terms_cand)
             acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
@@ -331,8 +345,11 @@ class Optimiser:
             F = pts.shape[0]
             if surrogate is None:
                 cand = self._sample(c, pts, 1)
+                self._force(pts, cand)
                 mask = None
             else:
+                if self.use_fi:
+                    raise ValueError("forced improvements do not combine with surrogate screening")
                 candK = self._sample(c, pts, self.K)
                 _, mask, _, cand = surrogate.screen(self.p, self.X, pts, candK, obj=self.obj, archive=self.arch_dev)
             old, new, flags, _ = self.p.eval_partial(self.X, off, pts, cand, tet_terms_in=self.cache,
@@ -383,15 +400,62 @@ class Optimiser:
         onehot = (self._assign[:, None] == torch.arange(self.k, device=acc.device)[None, :]).to(torch.float32)
         return (onehot.T @ a) > 0
 
+    def _dominated_by(self):
+        """Number of population members dominating each solution (device)."""
+        o = self.obj
+        le = (o[None, :, :] <= o[:, None, :]).all(-1)
+        lt = (o[None, :, :] < o[:, None, :]).any(-1)
+        return (le & lt).sum(1)
+
+    def _force(self, pts, cand):
+        """Forced improvements: the flagged solutions' candidates become their
+        donors' current values at pts."""
+        if self._donor is not None:
+            self.p.copy_from_donor(self.X, pts, self._donor, cand)
+
+    def _draw_donors(self):
+        """Solutions whose no-improvement stretch exceeds nis_max get a donor: a
+        random non-dominated member of the population."""
+        torch = self.torch
+        fl = (self.nis > self.nis_max).cpu().numpy()
+        self._fi = fl
+        if not fl.any():
+            self._donor = None
+            return
+        self.fi_forced += int(fl.sum())
+        nd = torch.nonzero(self._dominated_by() == 0).reshape(-1).cpu().numpy()
+        donor = np.full(self.S, -1, np.int32)
+        donor[fl] = np.random.default_rng([self.seed, self._gen, 11]).choice(nd, size=int(fl.sum()))
+        self._donor = torch.from_numpy(donor).to(self.X.device)
+
+    def _after_forcing(self, outs):
+        """Updates the no-improvement stretches; a forced solution that accepted
+        no change is replaced by its donor (coordinates, objectives, term cache)."""
+        torch = self.torch
+        improved = torch.zeros(self.S, dtype=torch.bool, device=self.X.device)
+        for _, acc, *_ in outs:
+            improved |= (acc != 0).any(dim=1)
+        self.nis = torch.where(improved, torch.zeros_like(self.nis), self.nis + 1)
+        if self._donor is None:
+            return
+        fl = torch.from_numpy(self._fi).to(self.X.device)
+        idx = torch.nonzero(fl & ~improved).reshape(-1)
+        if idx.numel():
+            d = self._donor[idx].long()
+            self.X[idx] = self.X[d]
+            self.obj[idx] = self.obj[d]
+            self.cache[idx] = self.cache[d]
+            self.fi_replaced += int(idx.numel())
+        self.nis[fl] = 0
+        self._donor = None
+
     def select(self):
         """Indices (int32, device) of the tau fraction of the population with the
         fewest dominating solutions; ties by the smallest sum of objectives
         normalised to the population's range."""
         torch = self.torch
         o = self.obj
-        le = (o[None, :, :] <= o[:, None, :]).all(-1)
-        lt = (o[None, :, :] < o[:, None, :]).any(-1)
-        dominated_by = (le & lt).sum(1).to(torch.float64)
+        dominated_by = self._dominated_by().to(torch.float64)
         lo, hi = o.min(0).values, o.max(0).values
         nrm = ((o - lo) / torch.clamp(hi - lo, min=1e-300)).sum(1)
         n = max(1, int(round(self.tau * self.S)))
@@ -400,6 +464,8 @@ class Optimiser:
     def generation(self, surrogate=None, log=None):
         """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
         torch = self.torch
+        if self.use_fi:
+            self._draw_donors()
         if self.sampler == "estimated" and self.fos == "point":
             members = self._cluster()
             self._dist = []
@@ -426,6 +492,8 @@ class Optimiser:
                 hit = self._hits(acc)
                 self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
                                            torch.clamp(self.mult[c] * 0.9, min=0.05))
+        if self.use_fi:
+            self._after_forcing(outs)
         counts = torch.stack([acc.sum(dtype=torch.int64) for _, acc, *_ in outs] +
                              [mask.sum(dtype=torch.int64) for mask, *_ in outs if mask is not None]).cpu().numpy()
         n_acc = int(counts[:len(outs)].sum())
@@ -455,13 +523,13 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
         K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point", clusters=1,
-        ams=False):
+        ams=False, forced_improvements=False, nis_max=None):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
     opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos,
-                    clusters=clusters, ams=ams)
+                    clusters=clusters, ams=ams, forced_improvements=forced_improvements, nis_max=nis_max)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate

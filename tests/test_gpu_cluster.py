@@ -1,6 +1,7 @@
 """GPU clustering in objective space (dsm_cluster_objectives) bit for bit
 against the FP64 reference oracle/gomea_ref.cluster, per-cluster sampling,
-and optimiser runs that sample from clustered distributions."""
+the anticipated mean shift, forced improvements, and optimiser runs that use
+them."""
 import sys
 
 import numpy as np
@@ -185,3 +186,71 @@ def test_optimiser_with_anticipated_mean_shift(fos):
     np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
     with pytest.raises(ValueError):
         O.Optimiser(gp, _t(X), ams=True)  # the shift needs the estimated sampler
+
+
+def test_copy_from_donor():
+    w = W.batched()
+    gp = dsm.Problem.from_workload(w)
+    rng = np.random.default_rng(12)
+    S, P = 6, gp.P
+    X = rng.uniform(0, 60, (S, 2, P, 3)).astype(np.float32)
+    pts = np.array([3, 17, -1, 60, P, 99], np.int32)  # two invalid points stay unchanged
+    donor = np.array([-1, 3, 0, -1, 5, 2], np.int32)
+    cand0 = rng.uniform(0, 60, (S, len(pts), 2, 3)).astype(np.float32)
+    cand = gp.copy_from_donor(_t(X), _t(pts), _t(donor), _t(cand0)).cpu().numpy()
+    for s in range(S):
+        for k, p in enumerate(pts):
+            if donor[s] >= 0 and 0 <= p < P:
+                np.testing.assert_array_equal(cand[s, k], X[donor[s], :, p, :])
+            else:
+                np.testing.assert_array_equal(cand[s, k], cand0[s, k])
+
+
+@pytest.mark.parametrize("fos,sampler,sigma", [("point", "isotropic", 40.0), ("tetrahedron", "estimated", 1.0)])
+def test_optimiser_with_forced_improvements(fos, sampler, sigma):
+    """Forced often (nis_max 0; with sigma 40 nearly every isotropic candidate
+    folds, so solutions stagnate and get donors): replaced solutions carry their
+    donors' objectives and term cache, which equal a fresh full evaluation."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4 if fos == "tetrahedron" else 1)
+    _say(f"6 generations, {fos} FOS, {sampler}, sigma {sigma}, forced improvements")
+    log, opt, _ = O.run(gp, _t(X), 6, sigma=sigma, seed=5, sampler=sampler, fos=fos, forced_improvements=True,
+                        nis_max=0)
+    assert log.hypervolume[-1] >= log.hypervolume[0]
+    if sigma > 10:
+        assert opt.fi_forced > 0  # (copies from non-dominated donors are nearly always accepted)
+    assert int((gp.fold_check(opt.X) != 0).sum().item()) == 0
+    fresh = torch.empty_like(opt.cache)
+    obj, flags = gp.eval_full(opt.X, tet_terms=fresh)
+    assert int((flags != 0).sum().item()) == 0
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(opt.cache.cpu().numpy(), fresh.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    assert opt.nis.min().item() >= 0
+    with pytest.raises(ValueError):
+        O.Optimiser(gp, _t(X), forced_improvements=True, graph=True)
+
+
+def test_forced_solution_without_improvement_takes_its_donor():
+    """The replacement step: forced solutions that accepted nothing become
+    their donors (coordinates, objectives, term cache); improved ones stay."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w)
+    opt = O.Optimiser(gp, _t(X), forced_improvements=True)
+    S = opt.S
+    donor = np.full(S, -1, np.int32)
+    donor[[0, 5, 9]] = [7, 7, 0]  # 9's donor is 0, itself replaced in the same step: the old 0 is copied
+    opt._donor, opt._fi = _t(donor), donor >= 0
+    acc = torch.zeros((S, 4), dtype=torch.uint8, device=DEV)
+    acc[5, 1] = 1   # solution 5 accepted a change: kept
+    acc[11, 0] = 1  # an unforced solution that improved
+    X0, o0, c0, n0 = opt.X.clone(), opt.obj.clone(), opt.cache.clone(), opt.nis.clone()
+    opt._after_forcing([(None, acc)])
+    for s, d in ((0, 7), (9, 0), (5, 5), (3, 3)):
+        assert torch.equal(opt.X[s], X0[d]) and torch.equal(opt.obj[s], o0[d]) and torch.equal(opt.cache[s], c0[d])
+    assert opt.fi_replaced == 2
+    nis = opt.nis.cpu().numpy()
+    assert nis[0] == nis[5] == nis[9] == nis[11] == 0 and nis[3] == n0[3].item() + 1
