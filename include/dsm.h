@@ -494,11 +494,14 @@ dsm_status dsm_refine_population(const int32_t* mesh_coarse, int32_t S, const fl
  * X dev [S][2][P][3] and copy the candidate terms of the point's star from
  * terms_cand dev [S][T][3] (as written by dsm_eval_partial(_masked)) into
  * terms_cache dev [S][T][3]; obj dev [S][3] is then recomputed from the cache.
- * accepted dev [S][F] (uint8) or NULL. */
+ * single_objective dev [S] int32 or NULL: a solution with entry o in {0, 1, 2}
+ * (a member of MO-RV-GOMEA's single-objective cluster for objective o) accepts
+ * a feasible change iff it lowers objective o; other entries use the rule
+ * above.  accepted dev [S][F] (uint8) or NULL. */
 dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_pts, const float* cand,
                       const double* part_old, const double* part_new, const uint32_t* flags, const double* terms_cand,
-                      double* terms_cache, double* obj, int32_t n_archive, const double* archive, uint8_t* accepted,
-                      void* stream);
+                      double* terms_cache, double* obj, int32_t n_archive, const double* archive,
+                      const int32_t* single_objective, uint8_t* accepted, void* stream);
 
 /* dsm_accept for elements of any number of points (e.g. the paper's per-cube
  * tetrahedron elements, Sec. 2.2): element f has the points
@@ -506,12 +509,12 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
  * cand dev [S][fos_off[F]][2][3], the layout of dsm_eval_partial.  The
  * elements of one call must have pairwise disjoint affected tetrahedra.  An
  * accepted change writes all of its points and copies the candidate terms of
- * the union of their stars. */
+ * the union of their stars; single_objective as for dsm_accept. */
 dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_off,
                                const int32_t* fos_pts, const float* cand, const double* part_old,
                                const double* part_new, const uint32_t* flags, const double* terms_cand,
                                double* terms_cache, double* obj, int32_t n_archive, const double* archive,
-                               uint8_t* accepted, void* stream);
+                               const int32_t* single_objective, uint8_t* accepted, void* stream);
 
 #ifdef __cplusplus
 }

@@ -309,7 +309,7 @@ __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, con
                          const double* __restrict__ part_new, const uint32_t* __restrict__ flags,
                          const double* __restrict__ terms_cand, double* __restrict__ cache,
                          const double* __restrict__ obj, int n_arch, const double* __restrict__ arch,
-                         unsigned char* __restrict__ accepted) {
+                         const int* __restrict__ single_objective, unsigned char* __restrict__ accepted) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= S * F) return;
   const int s = e / F, f = e % F;
@@ -324,7 +324,10 @@ __global__ void k_accept(DevProblem pr, int S, float* __restrict__ X, int F, con
       lt = lt || d[o] < 0.0;
     }
     acc = le && lt;
-    if (!acc && n_arch > 0) {
+    const int so = single_objective ? single_objective[s] : -1;
+    if (so >= 0 && so < 3) {
+      acc = d[so] < 0.0;  // a single-objective cluster's member: improve that objective
+    } else if (!acc && n_arch > 0) {
       bool dominated = false, improves = false;
       for (int o = 0; o < 3; ++o) improves = improves || d[o] < 0.0;
       for (int q = 0; q < n_arch && !dominated; ++q) {
@@ -695,8 +698,8 @@ dsm_status dsm_refine_population(const int32_t* mesh_coarse, int32_t S, const fl
 
 dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int32_t* fos_pts, const float* cand,
                       const double* part_old, const double* part_new, const uint32_t* flags, const double* terms_cand,
-                      double* terms_cache, double* obj, int32_t n_archive, const double* archive, uint8_t* accepted,
-                      void* stream) {
+                      double* terms_cache, double* obj, int32_t n_archive, const double* archive,
+                      const int32_t* single_objective, uint8_t* accepted, void* stream) {
   if (!p || S < 0 || F < 0 || n_archive < 0 || (n_archive > 0 && !archive) || S > p->max_S) return DSM_ERR_ARG;
   if (S == 0) return DSM_OK;  // empty buffers may be null
   if (!X || !terms_cache || !obj || (F > 0 && (!fos_pts || !cand || !part_old || !part_new || !flags || !terms_cand)))
@@ -704,7 +707,8 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
   hipStream_t st = (hipStream_t)stream;
   if (F > 0)
     k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, nullptr, fos_pts, cand, part_old, part_new, flags,
-                                                   terms_cand, terms_cache, obj, n_archive, archive, accepted);
+                                                   terms_cand, terms_cache, obj, n_archive, archive, single_objective,
+                                                   accepted);
   if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
   return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
@@ -723,7 +727,7 @@ dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, c
                                const int32_t* fos_pts, const float* cand, const double* part_old,
                                const double* part_new, const uint32_t* flags, const double* terms_cand,
                                double* terms_cache, double* obj, int32_t n_archive, const double* archive,
-                               uint8_t* accepted, void* stream) {
+                               const int32_t* single_objective, uint8_t* accepted, void* stream) {
   if (!p || S < 0 || F < 0 || n_archive < 0 || (n_archive > 0 && !archive) || S > p->max_S) return DSM_ERR_ARG;
   if (S == 0) return DSM_OK;  // empty buffers may be null
   if (!X || !terms_cache || !obj ||
@@ -732,7 +736,8 @@ dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, c
   hipStream_t st = (hipStream_t)stream;
   if (F > 0)
     k_accept<<<(S * F + 255) / 256, 256, 0, st>>>(p->dev, S, X, F, fos_off, fos_pts, cand, part_old, part_new, flags,
-                                                   terms_cand, terms_cache, obj, n_archive, archive, accepted);
+                                                   terms_cand, terms_cache, obj, n_archive, archive, single_objective,
+                                                   accepted);
   if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
   return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }

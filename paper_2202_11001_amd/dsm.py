@@ -90,8 +90,8 @@ def lib():
                                      V, V], I),
             "dsm_cluster_objectives": ([I, V, I, V, I, V, V, V, V], I),
             "dsm_copy_from_donor": ([V, I, V, I, V, V, V, V], I),
-            "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V], I),
-            "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V], I),
+            "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V, V], I),
+            "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
             "dsm_batch_destroy": ([V], I),
             "dsm_eval_partial_batch": ([V, I, V, V], I),
@@ -201,6 +201,12 @@ def _check_dist(mean, chol, mult, cluster, S, n_dist, n_var, n_tri):
             raise ValueError(f"{name}: expected {dt} with {n} elements, got {t.dtype} with {t.numel()}")
     if cluster is not None and (cluster.dtype != torch.int32 or cluster.numel() != S):
         raise ValueError(f"cluster: expected int32 [{S}]")
+
+
+def _check_single_objective(so, S):
+    torch = _torch()
+    if so is not None and (so.dtype != torch.int32 or so.numel() != S):
+        raise ValueError(f"single_objective: expected int32 [{S}]")
 
 
 def _check_shift(shift, ams, S, P):
@@ -373,11 +379,13 @@ class Problem:
         return out
 
     def accept(self, X, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
-               accepted=None, stream=None):
+               accepted=None, stream=None, single_objective=None):
         na = 0 if archive is None else archive.shape[0]
+        _check_single_objective(single_objective, X.shape[0])
         _check(lib().dsm_accept(self._h, X.shape[0], _dptr(X), pts.shape[0], _dptr(pts), _dptr(cand),
                                 _dptr(part_old), _dptr(part_new), _dptr(flags), _dptr(terms_cand), _dptr(terms_cache),
-                                _dptr(obj), na, _dptr(archive), _dptr(accepted), _stream(stream)))
+                                _dptr(obj), na, _dptr(archive), _dptr(single_objective), _dptr(accepted),
+                                _stream(stream)))
 
     def estimate_elements(self, X, sel, off, pts, stream=None):
         """Joint distributions of elements of up to 4 points (CSR off, pts):
@@ -423,14 +431,15 @@ class Problem:
         return cand
 
     def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
-                        accepted=None, stream=None):
+                        accepted=None, stream=None, single_objective=None):
         """accept for elements of several points (CSR off [F+1], pts), candidates
         in the partial-evaluation layout [S][off[F]][2][3]."""
         na = 0 if archive is None else archive.shape[0]
+        _check_single_objective(single_objective, X.shape[0])
         _check(lib().dsm_accept_elements(self._h, X.shape[0], _dptr(X), off.shape[0] - 1, _dptr(off), _dptr(pts),
                                          _dptr(cand), _dptr(part_old), _dptr(part_new), _dptr(flags),
                                          _dptr(terms_cand), _dptr(terms_cache), _dptr(obj), na, _dptr(archive),
-                                         _dptr(accepted), _stream(stream)))
+                                         _dptr(single_objective), _dptr(accepted), _stream(stream)))
 
     @property
     def pitch(self):

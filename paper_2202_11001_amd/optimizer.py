@@ -177,7 +177,7 @@ class Optimiser:
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
                  keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1, ams=False,
-                 forced_improvements=False, nis_max=None):
+                 forced_improvements=False, nis_max=None, single_objective_clusters=False):
         import torch
         self.torch = torch
         self.p = problem
@@ -240,6 +240,12 @@ class Optimiser:
         if not 1 <= self.k <= 16 or (self.k > 1 and sampler != "estimated"):
             raise ValueError("clusters: 1 to 16, more than 1 only with the estimated sampler")
         self._assign = None  # cluster of every solution (device int32) when k > 1
+        # MO-RV-GOMEA's single-objective clusters: a cluster whose mean is best in
+        # objective o optimises o alone (per-solution objective in self._so, else -1)
+        self.use_so = bool(single_objective_clusters)
+        if self.use_so and self.k < 2:
+            raise ValueError("single-objective clusters need at least 2 clusters")
+        self._so = None
         # anticipated mean shift (RV-GOMEA): per generation half of the solutions
         # draw around mean + 2 c (mu_t - mu_{t-1}), mu the selection's point means
         self.use_ams = bool(ams)
@@ -324,7 +330,7 @@ class Optimiser:
                                                      tet_terms_new=self.terms_cand)
             acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
             self.p.accept_elements(self.X, off, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
-                                   archive=self.arch_dev, accepted=acc)
+                                   archive=self.arch_dev, accepted=acc, single_objective=self._so)
             if self.sampler == "estimated":
                 hit = self._hits(acc)
                 m = self.mult_cube[:, cubes_d]
@@ -360,7 +366,7 @@ class Optimiser:
                 self.collect.append((feats[ok], old.reshape(-1, 3)[ok], new.reshape(-1, 3)[ok]))
             acc = torch.empty((self.S, F), dtype=torch.uint8, device=self.X.device)
             self.p.accept(self.X, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
-                          archive=self.arch_dev, accepted=acc)
+                          archive=self.arch_dev, accepted=acc, single_objective=self._so)
             outs.append((mask, acc, cand, old, new, flags))
         self.counter_dev += 8
         return outs
@@ -388,7 +394,16 @@ class Optimiser:
             self._ams = self.torch.from_numpy(half.astype(np.uint8)).to(self.X.device)
         if self.k == 1:
             return [sel]
-        members, self._assign, _ = dsm.cluster_objectives(self.obj, sel, self.k)
+        members, self._assign, means = dsm.cluster_objectives(self.obj, sel, self.k)
+        if self.use_so:
+            torch = self.torch
+            # objective o takes the cluster with the lowest mean in o among those
+            # not yet taken (in objective order), so each gets its own while k >= 3
+            of_cluster = torch.full((self.k,), -1, dtype=torch.int32, device=self.X.device)
+            for o in range(min(3, self.k)):
+                m = torch.where(of_cluster < 0, means[:, o], torch.full_like(means[:, o], float("inf")))
+                of_cluster[m.argmin()] = o
+            self._so = of_cluster[self._assign.long()].contiguous()
         return [members[j] for j in range(self.k)]
 
     def _hits(self, acc):
@@ -523,13 +538,14 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
         K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point", clusters=1,
-        ams=False, forced_improvements=False, nis_max=None):
+        ams=False, forced_improvements=False, nis_max=None, single_objective_clusters=False):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
     opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos,
-                    clusters=clusters, ams=ams, forced_improvements=forced_improvements, nis_max=nis_max)
+                    clusters=clusters, ams=ams, forced_improvements=forced_improvements, nis_max=nis_max,
+                    single_objective_clusters=single_objective_clusters)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate

@@ -254,3 +254,51 @@ def test_forced_solution_without_improvement_takes_its_donor():
     assert opt.fi_replaced == 2
     nis = opt.nis.cpu().numpy()
     assert nis[0] == nis[5] == nis[9] == nis[11] == 0 and nis[3] == n0[3].item() + 1
+
+
+def test_single_objective_acceptance():
+    """A member of a single-objective cluster accepts a feasible change iff it
+    lowers that objective; the others use the Pareto / archive rule."""
+    w = W.batched()
+    gp = dsm.Problem.from_workload(w)
+    I = gp.topology()["identity"]
+    S, T = 5, gp.T
+    X = _t(np.repeat(np.stack([I, I])[None], S, axis=0))
+    pts = _t(np.array([31], np.int32))
+    cand = X[:, :, 31, :].reshape(S, 1, 2, 3).contiguous()
+    old = torch.zeros((S, 1, 3), dtype=torch.float64, device=DEV)
+    new = _t(np.array([[[-1, 1, 0]], [[-1, 1, 0]], [[1, -1, 0]], [[-1, -1, 0]], [[0, 0, -1]]], np.float64))
+    flags = torch.zeros((S, 1), dtype=torch.uint32, device=DEV)
+    flags[4, 0] = 1  # infeasible: never accepted
+    so = _t(np.array([0, -1, 0, 1, 2], np.int32))
+    cache = torch.zeros((S, T, 3), dtype=torch.float64, device=DEV)
+    obj = torch.zeros((S, 3), dtype=torch.float64, device=DEV)
+    acc = torch.empty((S, 1), dtype=torch.uint8, device=DEV)
+    gp.accept(X, pts, cand, old, new, flags, torch.zeros_like(cache), cache, obj, accepted=acc, single_objective=so)
+    assert acc.reshape(-1).cpu().tolist() == [1, 0, 0, 1, 0]
+    gp.accept(X, pts, cand, old, new, flags, torch.zeros_like(cache), cache, obj, accepted=acc)
+    assert acc.reshape(-1).cpu().tolist() == [0, 0, 0, 1, 0]
+    # the multi-point entry point takes the same rule
+    off = _t(np.array([0, 1], np.int32))
+    gp.accept_elements(X, off, pts, cand, old, new, flags, torch.zeros_like(cache), cache, obj, accepted=acc,
+                       single_objective=so)
+    assert acc.reshape(-1).cpu().tolist() == [1, 0, 0, 1, 0]
+
+
+@pytest.mark.parametrize("fos", ["point", "tetrahedron"])
+def test_optimiser_with_single_objective_clusters(fos):
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4 if fos == "tetrahedron" else 1)
+    _say(f"6 generations, {fos} FOS, 5 clusters, single-objective clusters")
+    log, opt, _ = O.run(gp, _t(X), 6, seed=6, sampler="estimated", fos=fos, clusters=5,
+                        single_objective_clusters=True)
+    assert log.hypervolume[-1] > log.hypervolume[0]
+    so = opt._so.cpu().numpy()
+    assert so.shape == (opt.S,) and set(np.unique(so).tolist()) <= {-1, 0, 1, 2} and (so >= 0).any()
+    assert int((gp.fold_check(opt.X) != 0).sum().item()) == 0
+    obj, flags = gp.eval_full(opt.X)
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    with pytest.raises(ValueError):
+        O.Optimiser(gp, _t(X), sampler="estimated", single_objective_clusters=True)  # needs clusters
