@@ -282,7 +282,8 @@ def sampler_run(gp, X, G, name, w):
     print(json.dumps(out), flush=True)
 
 
-def phantom_run(G1=300, G2=600, S1=250, S2=500, clusters=1, ams=False, forced=False, single_objective=False):
+def phantom_run(G1=300, G2=600, S1=250, S2=500, clusters=1, ams=False, forced=False, single_objective=False,
+                schedule="simple"):
     """Sec. 3's synthetic experiment on the seeded replica phantom (a cube with
     parabolic intrusions on every face and a shrinking central sphere, guidance
     on the sphere): the paper's multi-resolution scheme (6^3 grids, population
@@ -304,7 +305,7 @@ def phantom_run(G1=300, G2=600, S1=250, S2=500, clusters=1, ams=False, forced=Fa
     gpf = dsm.Problem.from_workload(wf, max_fos_points=4)
     X = wc.population(reject=lambda X: gpc.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0)
     res = {"workload": wf.name, "clusters": clusters, "ams": ams, "forced_improvements": forced,
-           "single_objective_clusters": single_objective,
+           "single_objective_clusters": single_objective, "multiplier_schedule": schedule,
            "phantom": {"half": 15.0, "depth": 6.0, "r_source": 9.0, "r_target": 5.0,
                        "guidance_pairs": int(len(wf.guid_moving))}}
 
@@ -326,7 +327,7 @@ def phantom_run(G1=300, G2=600, S1=250, S2=500, clusters=1, ams=False, forced=Fa
 
     opts = dict(keep_solutions=True, sampler="estimated", fos="tetrahedron", clusters=clusters,
                 archive_capacity=1 << 16, ams=ams, forced_improvements=forced,
-                single_objective_clusters=single_objective)
+                single_objective_clusters=single_objective, multiplier_schedule=schedule)
     oc = O.Optimiser(gpc, torch.from_numpy(X).to(dev), seed=41, **opts)
     res["coarse"] = level("coarse", oc, G1)
     Xf, rejected = O.seed_finer(oc, gpf, S2, seed=42)
@@ -581,6 +582,7 @@ def main():
     ap.add_argument("--ams", action="store_true", help="anticipated mean shift for --phantom")
     ap.add_argument("--forced", action="store_true", help="forced improvements for --phantom")
     ap.add_argument("--single-objective", action="store_true", help="single-objective clusters for --phantom")
+    ap.add_argument("--sdr", action="store_true", help="standard-deviation-ratio multiplier schedule for --phantom")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -593,7 +595,7 @@ def main():
         return
     if args.phantom:
         phantom_run(*args.phantom, clusters=args.clusters, ams=args.ams, forced=args.forced,
-                    single_objective=args.single_objective)
+                    single_objective=args.single_objective, schedule="sdr" if args.sdr else "simple")
         return
     if args.tet_fos:
         tetrahedron_fos_step()

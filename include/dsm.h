@@ -451,6 +451,23 @@ dsm_status dsm_sample_elements(dsm_problem* p, int32_t S, const float* X, int32_
 dsm_status dsm_copy_from_donor(dsm_problem* p, int32_t S, const float* X, int32_t n_pts, const int32_t* fos_pts,
                                const int32_t* donor, float* cand, void* stream);
 
+/* Adaptive variance scaling (AMaLGaM's standard-deviation ratio, used by
+ * RV-GOMEA, on which the optimisation of Sec. 2.2 builds): for every cluster j
+ * and element f (points fos_pts[fos_off[f] .. fos_off[f+1]), fos_off dev
+ * [F+1]; single points: fos_off = 0, 1, ..., F), the mean of the candidates
+ * cand dev [S][fos_off[F]][2][3] that were accepted (accepted dev [S][F]
+ * uint8) by solutions of cluster j (cluster dev [S] int32, NULL: all in
+ * cluster 0) is compared with the distribution mean dev [n_clusters][F][n_vars]
+ * variable by variable, in units of the variable's standard deviation from
+ * chol dev [n_clusters][F][n_vars (n_vars + 1) / 2] (packed lower rows);
+ * sdr dev [n_clusters][F] f64 receives the largest ratio, or -1 where no
+ * candidate was accepted (and for malformed elements).  Variables with zero
+ * deviation (pinned) are skipped.  n_vars is 6 (single points) or 24
+ * (elements of up to 4 points).  Errors: DSM_ERR_ARG. */
+dsm_status dsm_improvement_ratio(int32_t S, int32_t F, const int32_t* fos_off, const float* cand,
+                                 const uint8_t* accepted, int32_t n_clusters, const int32_t* cluster,
+                                 const double* mean, const double* chol, int32_t n_vars, double* sdr, void* stream);
+
 /* Balanced k-leader-means clustering of selected solutions in objective space
  * (MO-RV-GOMEA, on which the optimisation of Sec. 2.2 builds): per generation
  * one distribution per cluster and FOS element is estimated from the cluster's

@@ -131,7 +131,7 @@ def estimate_elements(X, sel, off, pts, mesh):
 # that keeps this order reproduces every bit.
 
 MAX_CLUSTERS = 16
-MAX_CLUSTER_SELECTION = 2048
+MAX_CLUSTER_SELECTION = 1024
 
 
 def _d2(a, b):
@@ -207,3 +207,22 @@ def cluster(obj, sel, k):
 def cluster_size(n_sel, k):
     """Members per cluster, c = min(n, ceil(2 n / k))."""
     return min(n_sel, -(-2 * n_sel // k))
+
+
+# --------------------------------------------------------------------- variance scaling
+#
+# AMaLGaM's adaptive variance scaling, as used by RV-GOMEA: after a generation,
+# the standard-deviation ratio of a distribution is the largest, over its
+# variables, distance between the mean of the improving (accepted) samples and
+# the distribution mean, in units of that variable's standard deviation.
+
+def standard_deviation_ratio(samples, mean, cov):
+    """Largest |mean(samples)_v - mean_v| / sqrt(cov_vv) over variables with
+    positive variance; -1 for no sample.  samples [n][V], mean [V], cov [V][V]."""
+    samples = np.asarray(samples, dtype=np.float64).reshape(-1, len(mean))
+    if len(samples) == 0:
+        return -1.0
+    d = np.abs(samples.mean(axis=0) - np.asarray(mean, dtype=np.float64))
+    var = np.diag(np.asarray(cov, dtype=np.float64))
+    ok = var > 0
+    return float((d[ok] / np.sqrt(var[ok])).max()) if ok.any() else 0.0

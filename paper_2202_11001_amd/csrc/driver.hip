@@ -399,6 +399,48 @@ __global__ void k_donor(int S, int P, const float* __restrict__ X, int n, const 
   cand[e] = X[(((size_t)d * 2 + c / 3) * P + p) * 3 + c % 3];
 }
 
+// Standard-deviation ratio of the improvements (AMaLGaM's adaptive variance
+// scaling, used by RV-GOMEA): per (cluster j, element f) the mean of the
+// accepted candidates of the cluster's solutions, compared with the
+// distribution's mean variable by variable in units of the variable's standard
+// deviation (sqrt of the row norm of L); the largest ratio, or -1 without an
+// accepted candidate.  One thread per (cluster, element).
+__global__ void k_sdr(int S, int F, const int* __restrict__ off, const float* __restrict__ cand,
+                      const unsigned char* __restrict__ accepted, int n_clusters, const int* __restrict__ cluster,
+                      const double* __restrict__ mean, const double* __restrict__ chol, int nvar,
+                      double* __restrict__ sdr) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_clusters * F) return;
+  const int j = e / F, f = e % F;
+  const int b = off[f], np = off[f + 1] - b, total = off[F];
+  const int nv = 6 * np;
+  if (b < 0 || np < 1 || nv > nvar || b + np > total) {
+    sdr[e] = -1.0;
+    return;
+  }
+  double sum[kEstVars];
+  for (int v = 0; v < nv; ++v) sum[v] = 0.0;
+  int n = 0;
+  for (int s = 0; s < S; ++s) {
+    if ((cluster ? cluster[s] : 0) != j || !accepted[(size_t)s * F + f]) continue;
+    for (int v = 0; v < nv; ++v) sum[v] += (double)cand[((size_t)s * total + b) * 6 + v];
+    ++n;
+  }
+  if (n == 0) {
+    sdr[e] = -1.0;
+    return;
+  }
+  const double* mu = mean + (size_t)e * nvar;
+  const double* L = chol + (size_t)e * (nvar * (nvar + 1) / 2);
+  double r = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    double s2 = 0.0;
+    for (int k = 0; k <= v; ++k) s2 += L[v * (v + 1) / 2 + k] * L[v * (v + 1) / 2 + k];
+    if (s2 > 0.0) r = fmax(r, fabs(sum[v] / n - mu[v]) / sqrt(s2));
+  }
+  sdr[e] = r;
+}
+
 // ---------------------------------------------------------------- clustering
 // Balanced k-leader-means of the selected solutions in objective space (the
 // clustering of MO-RV-GOMEA, on which the paper's optimiser builds, Sec. 2.2):
@@ -711,6 +753,18 @@ dsm_status dsm_accept(dsm_problem* p, int32_t S, float* X, int32_t F, const int3
                                                    accepted);
   if (hipGetLastError() != hipSuccess) return DSM_ERR_DEVICE;
   return launch_full_reduce(p->dev, S, terms_cache, obj, st) == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_improvement_ratio(int32_t S, int32_t F, const int32_t* fos_off, const float* cand,
+                                 const uint8_t* accepted, int32_t n_clusters, const int32_t* cluster,
+                                 const double* mean, const double* chol, int32_t n_vars, double* sdr, void* stream) {
+  if (S < 0 || F < 0 || n_clusters < 1 || (n_vars != 6 && n_vars != kEstVars)) return DSM_ERR_ARG;
+  const int64_t n = (int64_t)n_clusters * F;
+  if (n == 0) return DSM_OK;
+  if (!fos_off || !mean || !chol || !sdr || (S > 0 && (!cand || !accepted))) return DSM_ERR_ARG;
+  k_sdr<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(S, F, fos_off, cand, accepted, n_clusters,
+                                                                    cluster, mean, chol, n_vars, sdr);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 
 dsm_status dsm_copy_from_donor(dsm_problem* p, int32_t S, const float* X, int32_t n_pts, const int32_t* fos_pts,

@@ -90,6 +90,7 @@ def lib():
                                      V, V], I),
             "dsm_cluster_objectives": ([I, V, I, V, I, V, V, V, V], I),
             "dsm_copy_from_donor": ([V, I, V, I, V, V, V, V], I),
+            "dsm_improvement_ratio": ([I, I, V, V, V, I, V, V, V, I, V, V], I),
             "dsm_accept": ([V, I, V, I, V, V, V, V, V, V, V, V, I, V, V, V, V], I),
             "dsm_accept_elements": ([V, I, V, I, V, V, V, V, V, V, V, V, V, I, V, V, V, V], I),
             "dsm_batch_create": ([I, V], I),
@@ -166,6 +167,27 @@ def cluster_objectives(obj, sel, k, stream=None):
     _check(lib().dsm_cluster_objectives(S, _dptr(obj), n, _dptr(sel), int(k), _dptr(members) if cmax else None,
                                         _dptr(assign) if S else None, _dptr(means), _stream(stream)))
     return members, assign, means
+
+
+def improvement_ratio(off, cand, accepted, mean, chol, cluster=None, stream=None):
+    """Standard-deviation ratio of the accepted candidates per (cluster,
+    element) (``dsm_improvement_ratio``): off int32 [F+1], cand [S][off[F]][2][3],
+    accepted uint8 [S][F], mean float64 [C][F][n] and chol [C][F][n(n+1)/2]
+    with n = 6 or 24; returns float64 [C][F] (-1: nothing accepted)."""
+    torch = _torch()
+    S, F = accepted.shape[0], off.shape[0] - 1
+    n_vars = 6 if chol.shape[-1] == 21 else 24
+    C = max(1, mean.numel() // max(1, F * n_vars))
+    if (mean.dtype != torch.float64 or chol.dtype != torch.float64 or mean.numel() != C * F * n_vars
+            or chol.numel() != C * F * n_vars * (n_vars + 1) // 2 or accepted.dtype != torch.uint8
+            or accepted.numel() != S * F or off.dtype != torch.int32):
+        raise ValueError("improvement_ratio: argument shapes or dtypes")
+    if cluster is not None and (cluster.dtype != torch.int32 or cluster.numel() != S):
+        raise ValueError("improvement_ratio: cluster int32 [S] expected")
+    out = torch.empty((C, F), dtype=torch.float64, device=accepted.device)
+    _check(lib().dsm_improvement_ratio(S, F, _dptr(off), _dptr(cand), _dptr(accepted), C, _dptr(cluster),
+                                       _dptr(mean), _dptr(chol), n_vars, _dptr(out), _stream(stream)))
+    return out
 
 
 def mesh_topology(mesh, dims=None):

@@ -134,6 +134,24 @@ def merge_archive_with(archive, archive_X, new, new_X):
     return pts[keep][order], pay[keep][order]
 
 
+def avs_update(c, nis, sdr, nis_max, eta=0.9, lo=0.05, hi=10.0):
+    """AMaLGaM's adaptive variance scaling step for multipliers c (with their
+    no-improvement stretches nis) given standard-deviation ratios sdr (-1: no
+    improvement): after an improvement the multiplier is at least 1 and grows
+    by 1/eta if sdr > 1; otherwise the stretch grows while c <= 1, c shrinks by
+    eta if c > 1 or the stretch reached nis_max, and returns to 1 while the
+    stretch is short.  Returns (c, nis), c within [lo, hi]."""
+    import torch
+    imp = sdr >= 0
+    one = torch.ones_like(c)
+    c1 = torch.where(imp & (c < 1), one, c)
+    c1 = torch.where(imp & (sdr > 1), c1 / eta, c1)
+    nis1 = torch.where(imp, torch.zeros_like(nis), torch.where(c <= 1, nis + 1, nis))
+    c1 = torch.where(~imp & ((c > 1) | (nis1 >= nis_max)), c * eta, c1)
+    c1 = torch.where(~imp & (c1 < 1) & (nis1 < nis_max), one, c1)
+    return torch.clamp(c1, lo, hi), nis1
+
+
 def hypervolume(points, ref):
     """Exact 3-D hypervolume dominated by `points` and bounded by `ref`
     (minimisation): slices along the third objective, each a 2-D union area."""
@@ -177,7 +195,8 @@ class Optimiser:
 
     def __init__(self, problem, X, sigma=1.0, seed=1, K=4, graph=False, archive_capacity=1 << 14,
                  keep_solutions=False, sampler="isotropic", tau=0.35, fos="point", clusters=1, ams=False,
-                 forced_improvements=False, nis_max=None, single_objective_clusters=False):
+                 forced_improvements=False, nis_max=None, single_objective_clusters=False,
+                 multiplier_schedule="simple"):
         import torch
         self.torch = torch
         self.p = problem
@@ -270,11 +289,17 @@ class Optimiser:
             if self.use_graph:
                 raise ValueError("the estimated sampler runs eagerly (its selection needs the current objectives)")
             self.tau = float(tau)
-            # distribution multipliers per cluster and element (per cube for the tetrahedron FOS)
+            # distribution multipliers per cluster and element (per cube for the tetrahedron FOS),
+            # with the no-improvement stretches of the standard-deviation-ratio schedule
+            if multiplier_schedule not in ("simple", "sdr"):
+                raise ValueError(f"unknown multiplier schedule {multiplier_schedule!r}")
+            self.schedule = multiplier_schedule
             if fos == "point":
                 self.mult = [torch.ones((self.k, len(c)), dtype=torch.float32, device=dev) for c in self.classes]
+                self.avs_nis = [torch.zeros((self.k, len(c)), dtype=torch.int32, device=dev) for c in self.classes]
             else:
                 self.mult_cube = torch.ones((self.k, self.n_cubes), dtype=torch.float32, device=dev)
+                self.avs_nis_cube = torch.zeros((self.k, self.n_cubes), dtype=torch.int32, device=dev)
             self._dist = None
 
     @property
@@ -331,7 +356,12 @@ class Optimiser:
             acc = torch.empty((self.S, len(cubes)), dtype=torch.uint8, device=dev)
             self.p.accept_elements(self.X, off, pts, cand, old, new, flags, self.terms_cand, self.cache, self.obj,
                                    archive=self.arch_dev, accepted=acc, single_objective=self._so)
-            if self.sampler == "estimated":
+            if self.sampler == "estimated" and self.schedule == "sdr":
+                sdr = dsm.improvement_ratio(off, cand, acc, mean, chol, cluster=self._assign)
+                m, nis = avs_update(self.mult_cube[:, cubes_d], self.avs_nis_cube[:, cubes_d], sdr, 25 + 24)
+                self.mult_cube[:, cubes_d] = m
+                self.avs_nis_cube[:, cubes_d] = nis
+            elif self.sampler == "estimated":
                 hit = self._hits(acc)
                 m = self.mult_cube[:, cubes_d]
                 self.mult_cube[:, cubes_d] = torch.where(hit, torch.clamp(m / 0.9, max=10.0),
@@ -503,7 +533,12 @@ class Optimiser:
         else:
             outs = self._steps(surrogate)
         if self.sampler == "estimated" and self.fos == "point":
-            for c, (_, acc, *_) in enumerate(outs):
+            for c, (_, acc, cand, *_) in enumerate(outs):
+                if self.schedule == "sdr":
+                    mean, chol = self._dist[c]
+                    sdr = dsm.improvement_ratio(self.offs[c], cand, acc, mean, chol, cluster=self._assign)
+                    self.mult[c], self.avs_nis[c] = avs_update(self.mult[c], self.avs_nis[c], sdr, 25 + 6)
+                    continue
                 hit = self._hits(acc)
                 self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
                                            torch.clamp(self.mult[c] * 0.9, min=0.05))
@@ -538,14 +573,15 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
 
 def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_generations=0, train_steps=2000,
         K=4, target_hv=None, log_every=0, graph=False, sampler="isotropic", tau=0.35, fos="point", clusters=1,
-        ams=False, forced_improvements=False, nis_max=None, single_objective_clusters=False):
+        ams=False, forced_improvements=False, nis_max=None, single_objective_clusters=False,
+        multiplier_schedule="simple"):
     """Runs `generations` generations; with `train_generations` > 0 the first
     ones are plain and collect training rows, a surrogate is then trained and
     the remaining generations are screened.  Returns (RunLog, optimiser, surrogate)."""
     import torch
     opt = Optimiser(problem, X, sigma=sigma, seed=seed, K=K, graph=graph, sampler=sampler, tau=tau, fos=fos,
                     clusters=clusters, ams=ams, forced_improvements=forced_improvements, nis_max=nis_max,
-                    single_objective_clusters=single_objective_clusters)
+                    single_objective_clusters=single_objective_clusters, multiplier_schedule=multiplier_schedule)
     log = RunLog()
     t_opt = 0.0  # optimisation time; the hypervolume monitoring is not counted
     sur = surrogate

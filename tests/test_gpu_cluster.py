@@ -302,3 +302,50 @@ def test_optimiser_with_single_objective_clusters(fos):
     np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
     with pytest.raises(ValueError):
         O.Optimiser(gp, _t(X), sampler="estimated", single_objective_clusters=True)  # needs clusters
+
+
+@pytest.mark.parametrize("npts", [1, 4])
+def test_improvement_ratio_matches_reference(npts):
+    """Standard-deviation ratio per (cluster, element) against
+    oracle/gomea_ref.standard_deviation_ratio on random accepted sets."""
+    rng = np.random.default_rng(20 + npts)
+    S, F, C = 40, 7, 3
+    nv = 6 if npts == 1 else 24
+    off = np.arange(F + 1, dtype=np.int32) * npts
+    cand = rng.normal(30, 3, (S, F * npts, 2, 3)).astype(np.float32)
+    acc = (rng.uniform(0, 1, (S, F)) < 0.3).astype(np.uint8)
+    acc[:, 2] = 0  # an element with no accepted candidate
+    cl = rng.integers(0, C, S).astype(np.int32)
+    mean = rng.normal(30, 1, (C, F, nv))
+    Ls = np.zeros((C, F, nv, nv))
+    for j in range(C):
+        for f in range(F):
+            A = rng.normal(0, 1, (nv, nv))
+            Cv = A @ A.T + 0.5 * np.eye(nv)
+            Cv[:, 3] = Cv[3, :] = 0  # a pinned variable
+            Ls[j, f] = G.cholesky_semidefinite(Cv)
+    packed = np.array([[G.packed_lower(Ls[j, f]) for f in range(F)] for j in range(C)])
+    got = dsm.improvement_ratio(_t(off), _t(cand), _t(acc), _t(mean), _t(packed), cluster=_t(cl)).cpu().numpy()
+    for j in range(C):
+        for f in range(F):
+            rows = [cand[s, off[f]:off[f + 1]].reshape(-1) for s in range(S) if cl[s] == j and acc[s, f]]
+            want = G.standard_deviation_ratio(np.array(rows).reshape(-1, nv), mean[j, f], Ls[j, f] @ Ls[j, f].T)
+            np.testing.assert_allclose(got[j, f], want, rtol=1e-9, atol=1e-12)
+    assert np.all(got[:, 2] == -1.0)
+
+
+@pytest.mark.parametrize("fos", ["point", "tetrahedron"])
+def test_optimiser_with_sdr_schedule(fos):
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4 if fos == "tetrahedron" else 1)
+    _say(f"6 generations, {fos} FOS, 3 clusters, standard-deviation-ratio multipliers")
+    log, opt, _ = O.run(gp, _t(X), 6, seed=7, sampler="estimated", fos=fos, clusters=3, multiplier_schedule="sdr")
+    assert log.hypervolume[-1] > log.hypervolume[0]
+    m = torch.cat([x.reshape(-1) for x in opt.mult]) if fos == "point" else opt.mult_cube.reshape(-1)
+    assert float(m.min()) >= 0.05 and float(m.max()) <= 10.0 and float(m.max()) > 1.0
+    obj, flags = gp.eval_full(opt.X)
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    with pytest.raises(ValueError):
+        O.Optimiser(gp, _t(X), sampler="estimated", multiplier_schedule="other")

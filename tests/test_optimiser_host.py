@@ -92,3 +92,21 @@ def test_device_merge_payload_matches_host_merge():
         np.testing.assert_array_equal(arch[:n].numpy(), h_arch)
         np.testing.assert_array_equal(arch_X[:n].numpy(), h_pay)
         assert torch.all(torch.isinf(arch[n:]))
+
+
+def test_avs_update_rule():
+    """AMaLGaM's variance-scaling step, case by case (run on CPU tensors)."""
+    import torch
+    c = torch.tensor([0.5, 1.0, 2.0, 2.0, 1.0, 1.0, 0.8], dtype=torch.float32)
+    nis = torch.tensor([3, 3, 0, 5, 2, 9, 9], dtype=torch.int32)
+    sdr = torch.tensor([2.0, 0.5, 1.5, -1.0, -1.0, -1.0, -1.0], dtype=torch.float64)
+    c1, n1 = O.avs_update(c, nis, sdr, nis_max=10)
+    want = [1.0 / 0.9,   # improved, c < 1 -> 1, sdr > 1 -> grows
+            1.0,         # improved, sdr <= 1: at least 1
+            2.0 / 0.9,   # improved far from the mean: grows
+            1.8,         # no improvement, c > 1: shrinks, stretch unchanged
+            1.0,         # no improvement, c <= 1, short stretch: stays 1, stretch + 1
+            0.9,         # no improvement, stretch reaches the maximum: shrinks below 1
+            0.72]        # c < 1 and the stretch past the maximum: keeps shrinking
+    assert np.allclose(c1.numpy(), want, rtol=1e-6)
+    assert n1.tolist() == [0, 0, 0, 5, 3, 10, 10]

@@ -178,3 +178,12 @@ def test_cluster_edge_cases():
     # identical objectives: zero ranges divide by 1, every solution ties to the first cluster
     m, asg, mu = G.cluster(np.ones((6, 3)), np.arange(6), 2)
     assert np.all(asg == 0) and m[0].tolist() == [0, 1, 2, 3, 4, 5]
+
+
+def test_standard_deviation_ratio():
+    # mean of the samples (2, 0, 5) against (0, 0, 5): 2 / sqrt(4) = 1 on the first
+    # variable, 0 on the second, the third has zero variance (pinned) and is skipped
+    cov = np.diag([4.0, 1.0, 0.0])
+    assert G.standard_deviation_ratio([[1, 0, 5], [3, 0, 5]], [0, 0, 5], cov) == 1.0
+    assert G.standard_deviation_ratio([[0, 3, 9]], [0, 0, 5], cov) == 3.0
+    assert G.standard_deviation_ratio(np.zeros((0, 3)), [0, 0, 5], cov) == -1.0
