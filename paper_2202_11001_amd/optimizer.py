@@ -610,12 +610,15 @@ def run(problem, X, generations, sigma=1.0, seed=1, surrogate=None, train_genera
     return log, opt, sur
 
 
-def seed_finer(opt, problem_fine, S_fine, seed=0):
+def seed_finer(opt, problem_fine, S_fine, seed=0, rounds=64):
     """Sec. 2.4: a random sample (with replacement when the approximation set is
     smaller) of S_fine solutions of the coarse run's approximation set, refined
     to the finer mesh on the GPU.  Refined solutions that fail the finer
-    problem's constraints are replaced by further draws; returns the device
-    population and the number of draws rejected."""
+    problem's constraints are replaced by further draws; if `rounds` rounds of
+    draws leave places open, the whole approximation set is refined once and
+    the rest is drawn from its feasible members (with replacement when they
+    are fewer).  Returns the device population and the number of draws
+    rejected."""
     import torch
     pool = opt.archive_X
     if pool is None:
@@ -624,7 +627,7 @@ def seed_finer(opt, problem_fine, S_fine, seed=0):
     dev = opt.X.device
     out, rejected = [], 0
     need = S_fine
-    for _ in range(64):
+    for _ in range(rounds):
         idx = rng.choice(len(pool), size=need, replace=len(pool) < need)
         Xf = dsm.refine_population(opt.p.mesh, torch.from_numpy(np.ascontiguousarray(pool[idx])).to(dev))
         ok = (problem_fine.fold_check(Xf) == 0).cpu().numpy()
@@ -634,5 +637,13 @@ def seed_finer(opt, problem_fine, S_fine, seed=0):
         if need == 0:
             break
     if need:
-        raise RuntimeError("could not draw enough feasible refined solutions")
+        feasible = []
+        for b in range(0, len(pool), 4096):
+            Xb = dsm.refine_population(opt.p.mesh, torch.from_numpy(np.ascontiguousarray(pool[b:b + 4096])).to(dev))
+            feasible.append(b + np.nonzero((problem_fine.fold_check(Xb) == 0).cpu().numpy())[0])
+        feasible = np.concatenate(feasible)
+        if len(feasible) == 0:
+            raise RuntimeError("no solution of the approximation set stays feasible when refined")
+        idx = rng.choice(feasible, size=need, replace=len(feasible) < need)
+        out.append(dsm.refine_population(opt.p.mesh, torch.from_numpy(np.ascontiguousarray(pool[idx])).to(dev)))
     return torch.cat(out)[:S_fine].contiguous(), rejected

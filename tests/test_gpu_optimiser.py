@@ -197,6 +197,13 @@ def test_multiresolution_seeding():
     for _ in range(2):
         of.generation()
     assert of.hypervolume() > hv0
+    # no rounds of rejection draws: every place is drawn from the feasible refined archive members
+    Xg, rej = O.seed_finer(oc, gpf, 64, seed=6, rounds=0)
+    assert Xg.shape == (64, 2, wf.P, 3) and rej == 0
+    assert int((gpf.fold_check(Xg) != 0).sum().item()) == 0
+    refined = dsm.refine_population(w.mesh, _t(oc.archive_X)).cpu().numpy()
+    got = Xg.cpu().numpy()
+    assert all(np.any(np.all(refined == g, axis=(1, 2, 3))) for g in got)  # each a refined archive member
 
 
 def test_device_archive_merge_equals_host():
