@@ -256,8 +256,10 @@ def sampler_run(gp, X, G, name, w):
     changes; tau = 0.35, adaptive multipliers), for single-point elements and
     for the paper's FOS (one random tetrahedron per cube, its 4 points drawn
     jointly), each estimated sampler also with 5 clusters of the selection in
-    objective space, all eager from the same population; hypervolume of the
-    elitist archive against a reference point fixed by the initial population."""
+    objective space, and with 5 clusters plus the anticipated mean shift,
+    forced improvements and the standard-deviation-ratio multiplier schedule;
+    all eager from the same population; hypervolume of the elitist archive
+    against a reference point fixed by the initial population."""
     import torch
     from paper_2202_11001_amd import dsm
     from paper_2202_11001_amd import optimizer as O
@@ -265,10 +267,12 @@ def sampler_run(gp, X, G, name, w):
     gp4 = dsm.Problem.from_workload(w, max_fos_points=4)
     out = {"workload": name, "generations": G}
     for fos, prob in (("point", gp), ("tetrahedron", gp4)):
-        for sampler, k in (("isotropic", 1), ("estimated", 1), ("estimated", 5)):
-            key = f"{fos}/{sampler}" + (f"/{k} clusters" if k > 1 else "")
+        for sampler, k, full in (("isotropic", 1, False), ("estimated", 1, False), ("estimated", 5, False),
+                                 ("estimated", 5, True)):
+            key = f"{fos}/{sampler}" + (f"/{k} clusters" if k > 1 else "") + ("/AMS+FI+SDR" if full else "")
             log(f"{key}: {G} generations")
-            lg, opt, _ = O.run(prob, Xd, G, sigma=1.0, seed=5, log_every=10, sampler=sampler, fos=fos, clusters=k)
+            lg, opt, _ = O.run(prob, Xd, G, sigma=1.0, seed=5, log_every=10, sampler=sampler, fos=fos, clusters=k,
+                               ams=full, forced_improvements=full, multiplier_schedule="sdr" if full else "simple")
             arch = np.asarray(opt.archive)
             pop = opt.obj.cpu().numpy()
             out[key] = {"final_hv": lg.hypervolume[-1], "seconds": lg.seconds[-1], "hv": lg.hypervolume,
