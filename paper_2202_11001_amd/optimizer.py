@@ -134,6 +134,13 @@ def merge_archive_with(archive, archive_X, new, new_X):
     return pts[keep][order], pay[keep][order]
 
 
+# The full RV-GOMEA configuration (estimated distributions per cluster of the
+# selection, anticipated mean shift, forced improvements, standard-deviation-
+# ratio multipliers), the best measured one on both FOS; pass as
+# Optimiser(problem, X, fos=..., **RV_GOMEA) or run(..., **RV_GOMEA).
+RV_GOMEA = dict(sampler="estimated", clusters=5, ams=True, forced_improvements=True, multiplier_schedule="sdr")
+
+
 def avs_update(c, nis, sdr, nis_max, eta=0.9, lo=0.05, hi=10.0):
     """AMaLGaM's adaptive variance scaling step for multipliers c (with their
     no-improvement stretches nis) given standard-deviation ratios sdr (-1: no

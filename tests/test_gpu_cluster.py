@@ -349,3 +349,16 @@ def test_optimiser_with_sdr_schedule(fos):
     np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
     with pytest.raises(ValueError):
         O.Optimiser(gp, _t(X), sampler="estimated", multiplier_schedule="other")
+
+
+def test_rv_gomea_preset_run():
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)
+    gp = dsm.Problem.from_workload(w, max_fos_points=4)
+    _say("5 generations with the full RV-GOMEA preset, tetrahedron FOS")
+    log, opt, _ = O.run(gp, _t(X), 5, seed=8, fos="tetrahedron", **O.RV_GOMEA)
+    assert log.hypervolume[-1] > log.hypervolume[0]
+    obj, flags = gp.eval_full(opt.X)
+    assert int((flags != 0).sum().item()) == 0
+    np.testing.assert_allclose(opt.obj.cpu().numpy(), obj.cpu().numpy(), rtol=1e-5, atol=1e-9)
