@@ -1,6 +1,6 @@
 """GPU parity of dsm_transform (the registration's DVF and transformed image,
 Sec. 2.1 / Fig. 2) against the FP64 oracle: every voxel on small and ragged
-workloads, sampled voxels at 512x512x100."""
+workloads, sampled voxels at 512x512x100 and at 512^3, the largest size."""
 import sys
 
 import numpy as np
@@ -107,3 +107,39 @@ def test_transform_clinical_sampled():
             x = lam @ X[1 - own][tets[t]].astype(np.float64)
             np.testing.assert_allclose(v + d[v[2], v[1], v[0]], x, rtol=0, atol=1e-4)
             np.testing.assert_allclose(m[v[2], v[1], v[0]], rp.trilinear(1 - own, x), rtol=0, atol=1e-5)
+
+
+def test_transform_maximum_size_sampled():
+    """512^3 images (the largest the exact lattice predicates support), 4^3
+    meshes: every voxel covered, and sampled voxels against the oracle's exact
+    location, a linear solve and its trilinear sample."""
+    shape = (512, 512, 512)
+    rng = np.random.default_rng(8)
+    coarse = rng.uniform(0, 1, (17, 17, 17)).astype(np.float32)
+    from scipy import ndimage
+    fixed = ndimage.zoom(coarse, 512 / 17, order=1)[:512, :512, :512].astype(np.float32)
+    moving = np.roll(fixed, 3, axis=2)
+    w = W.Workload("max-512^3", moving, fixed, (4, 4, 4), (1.0, 1.0, 1.0), 0.2, 1, 6.0, 4.0, 51, 52)
+    _say(w.name)
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp, S=1)[0]
+    gp = dsm.Problem.from_workload(w, max_solutions=1, max_fos=1)
+    tets = rp.tets()
+    vox = rng.integers(0, 512, (40, 3))
+    for own in (1, 0):
+        d, m = gp.transform(_t(X), own=own)
+        assert not bool(torch.isnan(d).any()) and not bool(torch.isnan(m).any())
+        iz, iy, ix = (torch.from_numpy(vox[:, a]).to(DEV) for a in (2, 1, 0))
+        ds, ms = d[iz, iy, ix].cpu().numpy(), m[iz, iy, ix].cpu().numpy()
+        del d, m
+        L = np.rint((X[own].astype(np.float64) + 0.5) * 128)
+        for n, v in enumerate(vox):
+            U = 128.0 * v + 64.0
+            owners = [t for t in range(rp.T) if ref.lib().ref_inside(ref._p(np.ascontiguousarray(L[tets[t]])),
+                                                                      ref._p(np.ascontiguousarray(U)))]
+            assert len(owners) == 1
+            t = owners[0]
+            lam = np.linalg.solve(np.vstack([X[own][tets[t]].astype(np.float64).T, np.ones(4)]), np.append(v, 1.0))
+            x = lam @ X[1 - own][tets[t]].astype(np.float64)
+            np.testing.assert_allclose(v + ds[n], x, rtol=0, atol=2e-4)
+            np.testing.assert_allclose(ms[n], rp.trilinear(1 - own, x), rtol=0, atol=1e-5)
