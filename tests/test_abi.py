@@ -113,3 +113,27 @@ def test_distribution_arguments_checked_on_host():
         dsm._check_dist(*ok, torch.zeros(4, dtype=torch.int32), 5, 6, 6, 21)
     with pytest.raises(ValueError):
         dsm.cluster_objectives(torch.zeros((4, 3), dtype=torch.float32), torch.zeros(2, dtype=torch.int32), 2)
+
+
+def test_new_entry_points_validate_on_the_host():
+    """Argument errors of the transformation, clustering, donor, variance-scaling
+    and sampling entry points are reported before any device work."""
+    L = dsm.lib()
+    assert L.dsm_transform(None, 1, None, None, None, None) == dsm.ERR_ARG
+    # clustering: k outside [1, 16], negative sizes, selection above capacity
+    assert L.dsm_cluster_objectives(4, None, 2, None, 0, None, None, None, None) == dsm.ERR_ARG
+    assert L.dsm_cluster_objectives(4, None, 2, None, 17, None, None, None, None) == dsm.ERR_ARG
+    assert L.dsm_cluster_objectives(-1, None, 2, None, 2, None, None, None, None) == dsm.ERR_ARG
+    assert L.dsm_cluster_objectives(4, None, 1025, None, 2, None, None, None, None) == dsm.ERR_CAPACITY
+    assert L.dsm_cluster_objectives(4, None, 2, None, 2, None, None, None, None) == dsm.ERR_ARG  # null buffers
+    assert L.dsm_cluster_objectives(0, None, 0, None, 2, None, None, None, None) == dsm.OK  # nothing to write
+    # variance scaling: 6 or 24 variables only, at least one cluster
+    assert L.dsm_improvement_ratio(4, 2, None, None, None, 1, None, None, None, 7, None, None) == dsm.ERR_ARG
+    assert L.dsm_improvement_ratio(4, 2, None, None, None, 0, None, None, None, 6, None, None) == dsm.ERR_ARG
+    assert L.dsm_improvement_ratio(4, 2, None, None, None, 1, None, None, None, 6, None, None) == dsm.ERR_ARG
+    assert L.dsm_improvement_ratio(4, 0, None, None, None, 1, None, None, None, 24, None, None) == dsm.OK
+    assert L.dsm_copy_from_donor(None, 4, None, 3, None, None, None, None) == dsm.ERR_ARG
+    assert L.dsm_sample_elements(None, 4, None, 1, None, None, None, None, None, 1, None, None, None, 2.0, 0, 0,
+                                 None, None, None) == dsm.ERR_ARG
+    assert L.dsm_sample_estimated(None, 4, None, 1, None, 1, None, None, None, 1, None, None, None, 2.0, 0, 0,
+                                  None, None, None) == dsm.ERR_ARG
