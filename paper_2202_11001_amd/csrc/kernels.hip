@@ -1072,40 +1072,99 @@ __global__ void k_first_bad_fix(int S, int* first_bad) {
   if (s < S && first_bad[s] == 0x7fffffff) first_bad[s] = -1;
 }
 
-// Affected tetrahedra of each FOS element: ascending union of its points' stars.
-__global__ void k_affected(DevProblem pr, int F, const int* __restrict__ fos_off, const int* __restrict__ fos_pts,
-                           int max_pts, int maxA, int* aff, int* aff_cnt) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= F) return;
-  const int b = fos_off[f], e = fos_off[f + 1];
-  int* out = aff + (size_t)f * maxA;
-  if (b < 0 || e < b || e - b > max_pts) {
-    aff_cnt[f] = -1;
-    return;
-  }
+// Affected tetrahedra of element f with points fos_pts[b .. e): the sorted
+// union of the points' stars, written to out (at most maxA); the count, or -1
+// if it would exceed maxA.  One thread, insertion into the sorted prefix: the
+// path for elements whose stars hold more than kAffCap entries.
+__device__ int affected_serial(const DevProblem& pr, int b, int e, const int* __restrict__ fos_pts, int maxA,
+                               int* out) {
   int n = 0;
   for (int k = b; k < e; ++k) {
     const int p = fos_pts[k];
-    if (p < 0 || p >= pr.P) {
-      aff_cnt[f] = -1;
-      return;
-    }
     for (int j = pr.star_off[p]; j < pr.star_off[p + 1]; ++j) {
       const int t = pr.star[j];
-      // insertion into the sorted list, skipping duplicates
       int pos = n;
       while (pos > 0 && out[pos - 1] > t) --pos;
       if (pos > 0 && out[pos - 1] == t) continue;
-      if (n >= maxA) {
-        aff_cnt[f] = -1;
-        return;
-      }
+      if (n >= maxA) return -1;
       for (int m = n; m > pos; --m) out[m] = out[m - 1];
       out[pos] = t;
       ++n;
     }
   }
-  aff_cnt[f] = n;
+  return n;
+}
+
+constexpr int kAffCap = 1024;  // star entries of one element sorted in LDS
+
+// Affected sets of the FOS elements (Sec. 2.2: the tetrahedra to re-evaluate
+// when the element's points move): one wave per element gathers the stars of
+// its points into LDS, sorts them (bitonic) and keeps the first of every run
+// of equal ids, written in ascending order; aff_cnt[f] = their number, or -1
+// for a malformed element or one whose set would exceed maxA.
+__global__ __launch_bounds__(64) void k_affected(DevProblem pr, int F, const int* __restrict__ fos_off,
+                                                 const int* __restrict__ fos_pts, int max_pts, int maxA, int* aff,
+                                                 int* aff_cnt) {
+  __shared__ int s_c[kAffCap];
+  const int f = blockIdx.x, lane = threadIdx.x;
+  const int b = fos_off[f], e = fos_off[f + 1];
+  int* out = aff + (size_t)f * maxA;
+  bool bad = b < 0 || e < b || e - b > max_pts;
+  int total = 0;
+  for (int k = b; !bad && k < e; ++k) {
+    const int p = fos_pts[k];
+    if (p < 0 || p >= pr.P)
+      bad = true;
+    else
+      total += pr.star_off[p + 1] - pr.star_off[p];
+  }
+  if (bad) {
+    if (lane == 0) aff_cnt[f] = -1;
+    return;
+  }
+  if (total > kAffCap) {
+    if (lane == 0) aff_cnt[f] = affected_serial(pr, b, e, fos_pts, maxA, out);
+    return;
+  }
+  int base = 0;
+  for (int k = b; k < e; ++k) {
+    const int p = fos_pts[k], so = pr.star_off[p], n = pr.star_off[p + 1] - so;
+    for (int i = lane; i < n; i += 64) s_c[base + i] = pr.star[so + i];
+    base += n;
+  }
+  int n2 = 1;
+  while (n2 < total) n2 <<= 1;
+  for (int i = total + lane; i < n2; i += 64) s_c[i] = 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < n2; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int a = s_c[i], c = s_c[ixj];
+          if ((i & k) == 0 ? a > c : a < c) {
+            s_c[i] = c;
+            s_c[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // lane l keeps the run starts among entries [l * chunk, (l + 1) * chunk)
+  const int chunk = (total + 63) / 64;
+  const int lo = min(lane * chunk, total), hi = min(lo + chunk, total);
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) cnt += i == 0 || s_c[i] != s_c[i - 1];
+  const int incl = wave_incl_scan(cnt, lane);
+  const int n_unique = __shfl(incl, 63, 64);
+  if (n_unique > maxA) {
+    if (lane == 0) aff_cnt[f] = -1;
+    return;
+  }
+  int pos = incl - cnt;
+  for (int i = lo; i < hi; ++i)
+    if (i == 0 || s_c[i] != s_c[i - 1]) out[pos++] = s_c[i];
+  if (lane == 0) aff_cnt[f] = n_unique;
 }
 
 // Full evaluation: fixed-order sum of the per-tetrahedron terms of each solution.
@@ -1378,7 +1437,8 @@ hipError_t launch_order(int G, const int* aff_cnt, int* order, hipStream_t strea
 
 hipError_t launch_affected(const DevProblem& pr, int F, const int* fos_off, const int* fos_pts, int max_pts,
                            int maxA, int* aff, int* aff_cnt, hipStream_t stream) {
-  k_affected<<<(F + 63) / 64, 64, 0, stream>>>(pr, F, fos_off, fos_pts, max_pts, maxA, aff, aff_cnt);
+  if (F <= 0) return hipSuccess;
+  k_affected<<<F, 64, 0, stream>>>(pr, F, fos_off, fos_pts, max_pts, maxA, aff, aff_cnt);
   return hipGetLastError();
 }
 
