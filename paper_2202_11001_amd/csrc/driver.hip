@@ -179,6 +179,7 @@ __global__ void k_sample_est(DevProblem pr, int S, const float* __restrict__ X, 
 // target x y z), at most kEstPoints points.  The distribution is estimated
 // over all of them jointly (full covariance).
 constexpr int kEstPoints = 4, kEstVars = 6 * kEstPoints, kEstTri = kEstVars * (kEstVars + 1) / 2;
+constexpr int kEstTile = 128;  // selected solutions staged in LDS at a time
 
 // One 64-thread workgroup per element: mean [F][kEstVars] and the lower
 // Cholesky factor chol [F][kEstTri] (row r holding columns 0..r) of the
@@ -193,7 +194,9 @@ __global__ __launch_bounds__(64) void k_estimate_el(DevProblem pr, int S, const 
                                                     double* __restrict__ chol) {
   __shared__ double s_mu[kEstVars];
   __shared__ double s_C[kEstTri];
-  __shared__ int s_ok;
+  __shared__ int s_valid;
+  __shared__ float s_x[kEstTile][kEstVars];
+  __shared__ int s_ok[kEstTile];
   const int f = blockIdx.x, t = threadIdx.x;
   double* mu = mean + (size_t)f * kEstVars;
   double* L = chol + (size_t)f * kEstTri;
@@ -203,41 +206,78 @@ __global__ __launch_bounds__(64) void k_estimate_el(DevProblem pr, int S, const 
   if (t == 0) {
     int ok = b >= 0 && np >= 1 && np <= kEstPoints && b + np <= off[F];
     for (int k = 0; ok && k < np; ++k) ok = pts[b + k] >= 0 && pts[b + k] < pr.P;
-    s_ok = ok;
+    s_valid = ok;
   }
   __syncthreads();
-  if (!s_ok) return;
+  if (!s_valid) return;
   const int nv = 6 * np;
   int n = 0;  // solutions used
   for (int i = 0; i < n_sel; ++i) n += sel[i] >= 0 && sel[i] < S;
   if (n == 0) return;
   // variable v: point v / 6, coordinate v % 6; free unless pinned to the box
-  auto coord = [&](int si, int v) {
-    const int p = pts[b + v / 6], c = v % 6;
-    return (double)X[(((size_t)si * 2 + c / 3) * pr.P + p) * 3 + c % 3];
-  };
   auto is_free = [&](int v) {
     const int p = pts[b + v / 6], a = v % 3;
     const int idx = a == 0 ? p % pr.n[0] : (a == 1 ? (p / pr.n[0]) % pr.n[1] : p / (pr.n[0] * pr.n[1]));
     return idx > 0 && idx < pr.n[a] - 1;
   };
-  if (t < nv) {
-    double m = 0.0;
-    for (int i = 0; i < n_sel; ++i)
-      if (sel[i] >= 0 && sel[i] < S) m += coord(sel[i], t);
-    s_mu[t] = m / n;
+  // the selected solutions' coordinates, staged in LDS tiles of kEstTile rows;
+  // every sum still runs over the selection in order
+  auto stage = [&](int i0) {
+    const int rows = min(kEstTile, n_sel - i0);
+    for (int q = t; q < rows * nv; q += 64) {
+      const int i = q / nv, v = q % nv;
+      const int si = sel[i0 + i];
+      float x = 0.f;
+      if (si >= 0 && si < S) {
+        const int p = pts[b + v / 6], c = v % 6;
+        x = X[(((size_t)si * 2 + c / 3) * pr.P + p) * 3 + c % 3];
+      }
+      s_x[i][v] = x;
+    }
+    for (int i = t; i < rows; i += 64) s_ok[i] = sel[i0 + i] >= 0 && sel[i0 + i] < S;
+    __syncthreads();
+    return rows;
+  };
+  double m = 0.0;
+  for (int i0 = 0; i0 < n_sel; i0 += kEstTile) {
+    const int rows = stage(i0);
+    if (t < nv)
+      for (int i = 0; i < rows; ++i)
+        if (s_ok[i]) m += (double)s_x[i][t];
+    __syncthreads();
   }
+  if (t < nv) s_mu[t] = m / n;
   __syncthreads();
-  for (int e = t; e < nv * (nv + 1) / 2; e += 64) {
+  constexpr int kPer = (kEstTri + 63) / 64;  // covariance entries per thread
+  const int ne = nv * (nv + 1) / 2;
+  double acc[kPer];
+  int er[kPer], ec[kPer];
+  bool ef[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int e = t + 64 * k;
     int r = 0;
-    while ((r + 1) * (r + 2) / 2 <= e) ++r;
-    const int c = e - r * (r + 1) / 2;
-    double acc = 0.0;
-    if (is_free(r) && is_free(c))
-      for (int i = 0; i < n_sel; ++i)
-        if (sel[i] >= 0 && sel[i] < S) acc += (coord(sel[i], r) - s_mu[r]) * (coord(sel[i], c) - s_mu[c]);
-    s_C[e] = acc / n;
+    if (e < ne)
+      while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    er[k] = r;
+    ec[k] = e - r * (r + 1) / 2;
+    ef[k] = e < ne && is_free(r) && is_free(ec[k]);
+    acc[k] = 0.0;
   }
+  for (int i0 = 0; i0 < n_sel; i0 += kEstTile) {
+    const int rows = stage(i0);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (ef[k]) {
+        const double mr = s_mu[er[k]], mc = s_mu[ec[k]];
+        for (int i = 0; i < rows; ++i)
+          if (s_ok[i]) acc[k] += ((double)s_x[i][er[k]] - mr) * ((double)s_x[i][ec[k]] - mc);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (t + 64 * k < ne) s_C[t + 64 * k] = acc[k] / n;
   __syncthreads();
   if (t == 0) {  // in place: s_C becomes the factor
     for (int r = 0; r < nv; ++r)
