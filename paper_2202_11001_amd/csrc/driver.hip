@@ -71,6 +71,8 @@ __global__ void k_sample(DevProblem pr, int S, const float* __restrict__ X, int 
 // coordinates (source grid x y z, target grid x y z); coordinates pinned to
 // the box (border points) are not variables.
 
+constexpr int kPtTile = 128;  // selected solutions staged in LDS at a time
+
 // Per element f: mean [F][6] of the point's coordinates over the solutions
 // sel[0..n_sel) (indices outside [0, S) are skipped), and chol [F][21], the
 // lower Cholesky factor (rows 0..5, row r holding columns 0..r) of their
@@ -78,55 +80,81 @@ __global__ void k_sample(DevProblem pr, int S, const float* __restrict__ X, int 
 // restricted to the free coordinates; pinned rows and columns are 0, and a
 // pivot that is not positive (a rank-deficient selection) gives a zero
 // column.  Sums run over sel in order, in FP64.
-__global__ void k_estimate(DevProblem pr, int S, const float* __restrict__ X, int n_sel, const int* __restrict__ sel,
-                           int F, const int* __restrict__ pts, double* __restrict__ mean, double* __restrict__ chol) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= F) return;
+__global__ __launch_bounds__(64) void k_estimate(DevProblem pr, int S, const float* __restrict__ X, int n_sel,
+                                                 const int* __restrict__ sel, int F, const int* __restrict__ pts,
+                                                 double* __restrict__ mean, double* __restrict__ chol) {
+  // one wave per point: the selected solutions' 6 coordinates are staged in LDS
+  // tiles; lane c < 6 sums mean component c and lane e < 21 covariance entry e,
+  // each over the selection in order
+  __shared__ float s_x[kPtTile][6];
+  __shared__ int s_ok[kPtTile];
+  __shared__ double s_m[6];
+  __shared__ double s_C[21];
+  const int f = blockIdx.x, t = threadIdx.x;
   double* mu = mean + (size_t)f * 6;
   double* L = chol + (size_t)f * 21;
-  for (int c = 0; c < 6; ++c) mu[c] = 0.0;
-  for (int c = 0; c < 21; ++c) L[c] = 0.0;
+  if (t < 6) mu[t] = 0.0;
+  if (t < 21) L[t] = 0.0;
   const int p = pts[f];
   if (p < 0 || p >= pr.P || n_sel < 1) return;
   const int idx[3] = {p % pr.n[0], (p / pr.n[0]) % pr.n[1], p / (pr.n[0] * pr.n[1])};
   bool fr[6];
   for (int c = 0; c < 6; ++c) fr[c] = idx[c % 3] > 0 && idx[c % 3] < pr.n[c % 3] - 1;
-  double m[6] = {0, 0, 0, 0, 0, 0};
   int n = 0;
-  for (int i = 0; i < n_sel; ++i) {
-    const int si = sel[i];
-    if (si < 0 || si >= S) continue;
-    const float* x = X + (size_t)si * 6 * pr.P;
-    for (int c = 0; c < 6; ++c) m[c] += (double)x[((size_t)(c / 3) * pr.P + p) * 3 + c % 3];
-    ++n;
-  }
+  for (int i = 0; i < n_sel; ++i) n += sel[i] >= 0 && sel[i] < S;
   if (n == 0) return;
-  for (int c = 0; c < 6; ++c) m[c] /= n;
-  double C[21] = {0};
-  for (int i = 0; i < n_sel; ++i) {
-    const int si = sel[i];
-    if (si < 0 || si >= S) continue;
-    const float* x = X + (size_t)si * 6 * pr.P;
-    double d[6];
-    for (int c = 0; c < 6; ++c) d[c] = fr[c] ? (double)x[((size_t)(c / 3) * pr.P + p) * 3 + c % 3] - m[c] : 0.0;
-    for (int r = 0; r < 6; ++r)
-      for (int c = 0; c <= r; ++c) C[r * (r + 1) / 2 + c] += d[r] * d[c];
+  auto stage = [&](int i0) {
+    const int rows = min(kPtTile, n_sel - i0);
+    for (int q = t; q < rows * 6; q += 64) {
+      const int i = q / 6, c = q % 6, si = sel[i0 + i];
+      s_x[i][c] = si >= 0 && si < S ? X[(((size_t)si * 2 + c / 3) * pr.P + p) * 3 + c % 3] : 0.f;
+    }
+    for (int i = t; i < rows; i += 64) s_ok[i] = sel[i0 + i] >= 0 && sel[i0 + i] < S;
+    __syncthreads();
+    return rows;
+  };
+  double m = 0.0;
+  for (int i0 = 0; i0 < n_sel; i0 += kPtTile) {
+    const int rows = stage(i0);
+    if (t < 6)
+      for (int i = 0; i < rows; ++i)
+        if (s_ok[i]) m += (double)s_x[i][t];
+    __syncthreads();
   }
-  for (int c = 0; c < 21; ++c) C[c] /= n;
+  if (t < 6) s_m[t] = m / n;
+  __syncthreads();
+  int r = 0;
+  while (t < 21 && (r + 1) * (r + 2) / 2 <= t) ++r;
+  const int c = t - r * (r + 1) / 2;
+  double acc = 0.0;
+  for (int i0 = 0; i0 < n_sel; i0 += kPtTile) {
+    const int rows = stage(i0);
+    if (t < 21)
+      for (int i = 0; i < rows; ++i)
+        if (s_ok[i]) {
+          const double dr = fr[r] ? (double)s_x[i][r] - s_m[r] : 0.0;
+          const double dc = fr[c] ? (double)s_x[i][c] - s_m[c] : 0.0;
+          acc += dr * dc;
+        }
+    __syncthreads();
+  }
+  if (t < 21) s_C[t] = acc / n;
+  __syncthreads();
+  if (t != 0) return;
   double l[21] = {0};
-  for (int r = 0; r < 6; ++r)
-    for (int c = 0; c <= r; ++c) {
-      double v = C[r * (r + 1) / 2 + c];
-      for (int t = 0; t < c; ++t) v -= l[r * (r + 1) / 2 + t] * l[c * (c + 1) / 2 + t];
-      if (c == r)
-        l[r * (r + 1) / 2 + r] = v > 0.0 ? sqrt(v) : 0.0;
+  for (int r2 = 0; r2 < 6; ++r2)
+    for (int c2 = 0; c2 <= r2; ++c2) {
+      double v = s_C[r2 * (r2 + 1) / 2 + c2];
+      for (int k = 0; k < c2; ++k) v -= l[r2 * (r2 + 1) / 2 + k] * l[c2 * (c2 + 1) / 2 + k];
+      if (c2 == r2)
+        l[r2 * (r2 + 1) / 2 + r2] = v > 0.0 ? sqrt(v) : 0.0;
       else {
-        const double dc = l[c * (c + 1) / 2 + c];
-        l[r * (r + 1) / 2 + c] = dc > 0.0 ? v / dc : 0.0;
+        const double d = l[c2 * (c2 + 1) / 2 + c2];
+        l[r2 * (r2 + 1) / 2 + c2] = d > 0.0 ? v / d : 0.0;
       }
     }
-  for (int c = 0; c < 6; ++c) mu[c] = m[c];
-  for (int c = 0; c < 21; ++c) L[c] = l[c];
+  for (int k = 0; k < 6; ++k) mu[k] = s_m[k];
+  for (int k = 0; k < 21; ++k) L[k] = l[k];
 }
 
 // cand [S][F][K][2][3]: mean + sqrt(mult[f]) L z on the free coordinates of
@@ -711,7 +739,7 @@ dsm_status dsm_estimate_distributions(dsm_problem* p, int32_t S, const float* X,
   if (!p || S < 0 || F < 0 || n_sel < 0) return DSM_ERR_ARG;
   if (F == 0) return DSM_OK;  // empty buffers may be null
   if (!fos_pts || !mean || !chol || (n_sel > 0 && (!X || !sel))) return DSM_ERR_ARG;
-  k_estimate<<<(unsigned)((F + 63) / 64), 64, 0, (hipStream_t)stream>>>(p->dev, S, X, n_sel, sel, F, fos_pts, mean,
+  k_estimate<<<(unsigned)F, 64, 0, (hipStream_t)stream>>>(p->dev, S, X, n_sel, sel, F, fos_pts, mean,
                                                                         chol);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
