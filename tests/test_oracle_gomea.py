@@ -186,4 +186,5 @@ def test_standard_deviation_ratio():
     cov = np.diag([4.0, 1.0, 0.0])
     assert G.standard_deviation_ratio([[1, 0, 5], [3, 0, 5]], [0, 0, 5], cov) == 1.0
     assert G.standard_deviation_ratio([[0, 3, 9]], [0, 0, 5], cov) == 3.0
+    assert G.standard_deviation_ratio([[-4, 0.5, 5]], [0, 0, 5], cov) == 2.0  # a shift below the mean counts too
     assert G.standard_deviation_ratio(np.zeros((0, 3)), [0, 0, 5], cov) == -1.0
