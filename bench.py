@@ -389,6 +389,47 @@ def phantom_run(G1=300, G2=600, S1=250, S2=500, clusters=1, ams=False, forced=Fa
     print(json.dumps(res), flush=True)
 
 
+def transform_bench(reps=5):
+    """The registration output (dsm_transform: DVF and transformed image, Sec.
+    2.1 / Fig. 2) of one solution of the 512x512x100 clinical-shaped pair, both
+    directions, timed with HIP events.  Algorithmic bytes per voxel: 16 written
+    (3 DVF components and the transformed value, FP32) + 4 for the sampled
+    voxel of the other image, as for the sweep."""
+    import torch
+    from paper_2202_11001_amd import dsm
+    from paper_2202_11001_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.clinical()
+    gp = dsm.Problem.from_workload(w, max_solutions=1, max_fos=1)
+    X = w.population(reject=lambda X: gp.fold_check(torch.from_numpy(X).to(dev)).cpu().numpy() != 0, S=1)
+    X2 = torch.from_numpy(X[0]).to(dev)
+    V = int(np.prod(w.fixed.shape))
+    Dz, Dy, Dx = w.fixed.shape
+    dvf = torch.empty((Dz, Dy, Dx, 3), dtype=torch.float32, device=dev)
+    warped = torch.empty((Dz, Dy, Dx), dtype=torch.float32, device=dev)
+    L = dsm.lib()
+    out = {"workload": w.name, "voxels": V, "bytes_per_voxel": 20}
+    for own in (1, 0):
+        def call():
+            dsm._check(L.dsm_transform(gp._h, own, dsm._dptr(X2), dsm._dptr(dvf), dsm._dptr(warped), None))
+        call()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        for r in range(reps):
+            ev[2 * r].record()
+            call()
+            ev[2 * r + 1].record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps)]))
+        gbs = 20.0 * V / (ms / 1e3) / 1e9
+        nan = int(torch.isnan(dvf).sum().item())
+        log(f"transform own={own}: {ms:.3f} ms per call, {V / (ms / 1e3) / 1e9:.2f} G voxels/s, "
+            f"{gbs:.0f} GB/s algorithmic, uncovered voxels {nan}")
+        out["target" if own == 1 else "source"] = {"ms": ms, "voxels_per_s": V / (ms / 1e3), "algorithmic_GBps": gbs,
+                                                   "roofline_frac": gbs / 8000.0, "uncovered": nan}
+    print(json.dumps(out), flush=True)
+
+
 def uneven_batch(steps=3, warmup=1):
     """Several registration problems of uneven size in one fused launch per
     pyramid level: the 12 problems of workloads.UNEVEN_PROBLEMS at the 2x
@@ -573,6 +614,8 @@ def main():
                     help="multi-resolution run: G1 coarse then G2 fine generations (reported separately)")
     ap.add_argument("--tet-fos", action="store_true",
                     help="partial evaluation with the paper's one-tetrahedron-per-cube FOS (reported separately)")
+    ap.add_argument("--transform", action="store_true",
+                    help="DVF and transformed image of one 512x512x100 solution (reported separately)")
     ap.add_argument("--uneven", action="store_true",
                     help="12 problems of uneven size in one fused launch per pyramid level (reported separately)")
     ap.add_argument("--surrogate-run", type=int, default=0, metavar="G",
@@ -593,6 +636,9 @@ def main():
         return
     if args.uneven:
         uneven_batch()
+        return
+    if args.transform:
+        transform_bench()
         return
     if args.multires:
         multires(*args.multires)
