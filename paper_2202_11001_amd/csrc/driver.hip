@@ -472,41 +472,59 @@ __global__ void k_donor(int S, int P, const float* __restrict__ X, int n, const 
 // accepted candidates of the cluster's solutions, compared with the
 // distribution's mean variable by variable in units of the variable's standard
 // deviation (sqrt of the row norm of L); the largest ratio, or -1 without an
-// accepted candidate.  One thread per (cluster, element).
-__global__ void k_sdr(int S, int F, const int* __restrict__ off, const float* __restrict__ cand,
-                      const unsigned char* __restrict__ accepted, int n_clusters, const int* __restrict__ cluster,
-                      const double* __restrict__ mean, const double* __restrict__ chol, int nvar,
-                      double* __restrict__ sdr) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_clusters * F) return;
+// accepted candidate.  One wave per (cluster, element): the candidates are
+// staged in LDS tiles and lane v sums variable v over the solutions in order.
+constexpr int kSdrTile = 128;
+
+__global__ __launch_bounds__(64) void k_sdr(int S, int F, const int* __restrict__ off, const float* __restrict__ cand,
+                                            const unsigned char* __restrict__ accepted, int n_clusters,
+                                            const int* __restrict__ cluster, const double* __restrict__ mean,
+                                            const double* __restrict__ chol, int nvar, double* __restrict__ sdr) {
+  __shared__ float s_x[kSdrTile][kEstVars];
+  __shared__ int s_use[kSdrTile];
+  const int e = blockIdx.x, lane = threadIdx.x;
   const int j = e / F, f = e % F;
   const int b = off[f], np = off[f + 1] - b, total = off[F];
   const int nv = 6 * np;
   if (b < 0 || np < 1 || nv > nvar || b + np > total) {
-    sdr[e] = -1.0;
+    if (lane == 0) sdr[e] = -1.0;
     return;
   }
-  double sum[kEstVars];
-  for (int v = 0; v < nv; ++v) sum[v] = 0.0;
+  double sum = 0.0;
   int n = 0;
-  for (int s = 0; s < S; ++s) {
-    if ((cluster ? cluster[s] : 0) != j || !accepted[(size_t)s * F + f]) continue;
-    for (int v = 0; v < nv; ++v) sum[v] += (double)cand[((size_t)s * total + b) * 6 + v];
-    ++n;
+  for (int s0 = 0; s0 < S; s0 += kSdrTile) {
+    const int rows = min(kSdrTile, S - s0);
+    for (int i = lane; i < rows; i += 64) {
+      const int s = s0 + i;
+      s_use[i] = (cluster ? cluster[s] : 0) == j && accepted[(size_t)s * F + f];
+    }
+    __syncthreads();
+    for (int q = lane; q < rows * nv; q += 64) {
+      const int i = q / nv, v = q % nv;
+      s_x[i][v] = s_use[i] ? cand[((size_t)(s0 + i) * total + b) * 6 + v] : 0.f;
+    }
+    __syncthreads();
+    for (int i = 0; i < rows; ++i)
+      if (s_use[i]) {
+        if (lane < nv) sum += (double)s_x[i][lane];
+        ++n;
+      }
+    __syncthreads();
   }
   if (n == 0) {
-    sdr[e] = -1.0;
+    if (lane == 0) sdr[e] = -1.0;
     return;
   }
-  const double* mu = mean + (size_t)e * nvar;
-  const double* L = chol + (size_t)e * (nvar * (nvar + 1) / 2);
   double r = 0.0;
-  for (int v = 0; v < nv; ++v) {
+  if (lane < nv) {
+    const double* mu = mean + (size_t)e * nvar;
+    const double* L = chol + (size_t)e * (nvar * (nvar + 1) / 2);
     double s2 = 0.0;
-    for (int k = 0; k <= v; ++k) s2 += L[v * (v + 1) / 2 + k] * L[v * (v + 1) / 2 + k];
-    if (s2 > 0.0) r = fmax(r, fabs(sum[v] / n - mu[v]) / sqrt(s2));
+    for (int k = 0; k <= lane; ++k) s2 += L[lane * (lane + 1) / 2 + k] * L[lane * (lane + 1) / 2 + k];
+    if (s2 > 0.0) r = fabs(sum / n - mu[lane]) / sqrt(s2);
   }
-  sdr[e] = r;
+  for (int m = 32; m >= 1; m >>= 1) r = fmax(r, __shfl_xor(r, m, 64));  // the maximum does not depend on order
+  if (lane == 0) sdr[e] = r;
 }
 
 // ---------------------------------------------------------------- clustering
@@ -830,8 +848,8 @@ dsm_status dsm_improvement_ratio(int32_t S, int32_t F, const int32_t* fos_off, c
   const int64_t n = (int64_t)n_clusters * F;
   if (n == 0) return DSM_OK;
   if (!fos_off || !mean || !chol || !sdr || (S > 0 && (!cand || !accepted))) return DSM_ERR_ARG;
-  k_sdr<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(S, F, fos_off, cand, accepted, n_clusters,
-                                                                    cluster, mean, chol, n_vars, sdr);
+  k_sdr<<<(unsigned)n, 64, 0, (hipStream_t)stream>>>(S, F, fos_off, cand, accepted, n_clusters, cluster, mean, chol,
+                                                    n_vars, sdr);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 
