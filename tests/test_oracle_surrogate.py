@@ -79,3 +79,46 @@ def test_feature_invariants():
         for j, (dx, dy, dz) in enumerate(offs):
             inside = 0 <= pi + dx < n[0] and 0 <= pj + dy < n[1] and 0 <= pk + dz < n[2]
             np.testing.assert_allclose(f2[p_, 6 + 6 * j:6 + 6 * j + 3], -d if inside else 0.0)
+
+
+def test_intensity_features_on_ramp_images_closed_form():
+    """Features [162, 188): for each of the 26 offsets o (dz, dy, dx order,
+    dx fastest) the source image sampled at the source candidate + h o minus
+    the target image sampled at the target candidate + h o, with h half the
+    undeformed cube extent per axis and positions clamped to [0, D - 1].  On
+    linear ramp images trilinear sampling is exact, so each feature is
+    g_src . clamp(c_src + h o) + k_src - g_tgt . clamp(c_tgt + h o) - k_tgt."""
+    dims, mesh = (20, 16, 12), (4, 3, 3)
+    g_src, k_src = np.array([0.02, -0.01, 0.03]), 0.2
+    g_tgt, k_tgt = np.array([-0.015, 0.025, 0.01]), 0.6
+    src = W.ramp(dims[::-1], tuple(g_src), k_src)
+    tgt = W.ramp(dims[::-1], tuple(g_tgt), k_tgt)
+    rp = ref.Problem(src, tgt, mesh)
+    I = rp.identity()
+    X = np.stack([I, I])[None].astype(np.float32)
+    rng = np.random.default_rng(5)
+    pts = np.arange(rp.P, dtype=np.int32)
+    cand = np.stack([X[0, 0, pts], X[0, 1, pts]], axis=1)[None, :, None].astype(np.float64)
+    cand = cand + rng.normal(0, 1.0, cand.shape)
+    cand = np.asarray(W.snap(np.clip(cand, -0.5, np.array(dims) - 0.5)), np.float64)
+    f = R.features(rp, X, pts, cand)
+    h = np.array([dims[a] / (2.0 * (mesh[a] - 1)) for a in range(3)])
+    hi = np.array(dims, np.float64) - 1.0
+    ramp_s = lambda x: g_src @ np.clip(x, 0.0, hi) + k_src
+    ramp_t = lambda x: g_tgt @ np.clip(x, 0.0, hi) + k_tgt
+    # the offsets spelled out in their slot order
+    slots = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dx, dy, dz) != (0, 0, 0)]
+    assert len(slots) == 26
+    clamped = 0
+    for q in range(rp.P):
+        cs, ct = cand[0, q, 0, 0], cand[0, q, 0, 1]
+        for j, o in enumerate(slots):
+            ps, pt = cs + h * np.array(o), ct + h * np.array(o)
+            clamped += np.any((ps < 0) | (ps > hi))
+            want = ramp_s(ps) - ramp_t(pt)
+            # the ramp images are float32: allow their rounding only
+            assert abs(f[q, 162 + j] - want) <= 2e-6, (q, j, f[q, 162 + j], want)
+    assert clamped > 0          # the border points exercise the clamp
+    # sign and offset pinned: swapping the images or the direction of o changes values
+    swapped = [ramp_t(ct + h * np.array(o)) - ramp_s(cs + h * np.array(o)) for o in slots]
+    assert np.max(np.abs(np.array(swapped) - f[rp.P - 1, 162:188])) > 1e-2
