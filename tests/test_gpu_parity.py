@@ -256,9 +256,10 @@ def test_determinism():
         np.testing.assert_array_equal(a, b)
 
 
-def test_batched_sampled():
+def test_batched_all_pairs():
     """64^3 blurred-ellipsoid pair, 5^3 meshes, 96 solutions x 125 single-point
-    elements in one launch; the oracle checks a sample of solutions."""
+    elements in one launch; the oracle recomputes every full evaluation and
+    every one of the 12,000 (solution, element) pairs."""
     w = W.batched()
     rp = oracle_problem(w)
     X = feasible_population(w, rp)
@@ -271,26 +272,29 @@ def test_batched_sampled():
     obj, flags = gp.eval_full(Xd, tet_terms=cache)
     old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
     torch.cuda.synchronize()
-    sample = [0, 17, 58, 95]
-    robj, rflags = rp.eval_full(X[sample])
-    assert_objectives_close(obj.cpu().numpy()[sample], robj, what="full objectives")
-    rold, rnew, rfl, rnv = rp.eval_partial(X[sample], off, pts, cand[sample])
-    flg = fl.cpu().numpy().astype(np.uint32)[sample]
+    _say("batched: oracle on all pairs")
+    robj, rflags, rterms, _ = rp.eval_full(X, want_terms=True)
+    np.testing.assert_array_equal(flags.cpu().numpy().astype(np.uint32), rflags)
+    assert_objectives_close(obj.cpu().numpy(), robj, what="full objectives")
+    rold, rnew, rfl, rnv = rp.eval_partial(X, off, pts, cand, tet_terms=rterms)
+    flg = fl.cpu().numpy().astype(np.uint32)
     np.testing.assert_array_equal(flg, rfl)
-    np.testing.assert_array_equal(vc.cpu().numpy()[sample][flg == 0], rnv[flg == 0])
-    assert_objectives_close(new.cpu().numpy()[sample], rnew, flags=flg, what="part_new")
-    assert_objectives_close(old.cpu().numpy()[sample], rold, what="part_old")
+    assert (flg == 0).sum() > 0.5 * flg.size
+    np.testing.assert_array_equal(vc.cpu().numpy()[flg == 0], rnv[flg == 0])
+    assert_objectives_close(new.cpu().numpy(), rnew, flags=flg, what="part_new")
+    assert_objectives_close(old.cpu().numpy(), rold, what="part_old")
+    assert_delta_close(old.cpu().numpy(), new.cpu().numpy(), rold, rnew, flg)
     # exactly-once coverage: every single-point element's samples add up to 8 V per solution
     vcs = vc.cpu().numpy().astype(np.int64)
-    allok = (fl.cpu().numpy() == 0).all(axis=1)
+    allok = (flg == 0).all(axis=1)
     assert np.all(vcs[allok].sum(axis=1) == 8 * gp.V)
 
 
-def test_clinical_full_size_sampled():
+def test_clinical_full_size_all_elements():
     """512x512x100 clinical-shaped workload in the benchmark's launch
     configuration (512 solutions x 600 single-point elements in one launch,
-    cached old terms); the oracle recomputes a sample of (solution, element)
-    pairs and two full evaluations."""
+    cached old terms); the oracle recomputes the full evaluation and all 600
+    elements (every star size, 2 to 48 tetrahedra) of 4 solutions."""
     w = W.clinical()
     _say(f"clinical full size {w.name}")
     gp = _gpu_problem(w, w.S)
@@ -305,24 +309,53 @@ def test_clinical_full_size_sampled():
     torch.cuda.synchronize()
     assert int((flags != 0).sum()) == 0
     vcs = vc.cpu().numpy().astype(np.int64)
-    fln = fl.cpu().numpy()
+    fln = fl.cpu().numpy().astype(np.uint32)
     allok = (fln == 0).all(axis=1)
     assert np.all(vcs[allok].sum(axis=1) == 8 * gp.V)  # exactly-once coverage, both grids, every star
+    star_off, _ = rp.star()
+    assert sorted(set(np.diff(star_off).tolist())) == [2, 4, 6, 8, 12, 16, 24, 48]
     rng = np.random.default_rng(0)
-    sols = rng.choice(w.S, 4, replace=False)
-    elems = np.sort(rng.choice(w.P, 6, replace=False)).astype(np.int32)
-    off_s = np.arange(len(elems) + 1, dtype=np.int32)
-    for s in sols:
-        c_s = cand[s:s + 1, elems]
-        rold, rnew, rfl, rnv = rp.eval_partial(X[s:s + 1], off_s, elems, c_s)
-        g_fl = fln[s, elems][None].astype(np.uint32)
-        np.testing.assert_array_equal(g_fl, rfl)
-        np.testing.assert_array_equal(vcs[s, elems][None][g_fl == 0], rnv[g_fl == 0])
-        assert_objectives_close(new.cpu().numpy()[s, elems][None], rnew, flags=g_fl, what="part_new")
-        assert_objectives_close(old.cpu().numpy()[s, elems][None], rold, what="part_old")
-        assert_delta_close(old.cpu().numpy()[s, elems][None], new.cpu().numpy()[s, elems][None], rold, rnew, g_fl)
-    robj, rflags = rp.eval_full(X[sols[:2]])
-    assert_objectives_close(obj.cpu().numpy()[sols[:2]], robj, what="full objectives")
+    sols = np.sort(rng.choice(w.S, 4, replace=False))
+    _say(f"clinical: oracle on all {w.P} elements of solutions {sols.tolist()}")
+    robj, rflags, rterms, _ = rp.eval_full(X[sols], want_terms=True)
+    assert_objectives_close(obj.cpu().numpy()[sols], robj, what="full objectives")
+    rold, rnew, rfl, rnv = rp.eval_partial(X[sols], off, pts, cand[sols], tet_terms=rterms)
+    g_fl = fln[sols]
+    np.testing.assert_array_equal(g_fl, rfl)
+    assert (g_fl == 0).sum() > 0.5 * g_fl.size
+    np.testing.assert_array_equal(vcs[sols][g_fl == 0], rnv[g_fl == 0])
+    assert_objectives_close(new.cpu().numpy()[sols], rnew, flags=g_fl, what="part_new")
+    assert_objectives_close(old.cpu().numpy()[sols], rold, what="part_old")
+    assert_delta_close(old.cpu().numpy()[sols], new.cpu().numpy()[sols], rold, rnew, g_fl)
+
+
+def test_clinical_tetrahedron_voxel_sets_bitexact():
+    """512x512x100, deformed feasible grids of two solutions: the GPU's
+    rasterised owner map covers every voxel exactly once, and the voxel set
+    of each of 150 tetrahedra per grid (border, corner and interior cubes)
+    equals the oracle's scan of its bounding box, voxel for voxel."""
+    w = W.clinical()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp, S=2)
+    gp = _gpu_problem(w, 2)
+    rng = np.random.default_rng(5)
+    T = rp.T
+    corner = [0, 1, 2, 3, 4, 5, T - 6, T - 5, T - 4, T - 3, T - 2, T - 1]
+    for s in range(2):
+        for g in range(2):
+            owner, overlap = gp.rasterize_owner(_t(X[s, g]))
+            torch.cuda.synchronize()
+            assert int(overlap.item()) == 0
+            own = owner.cpu().numpy().ravel()
+            assert own.min() >= 0
+            order = np.argsort(own, kind="stable")
+            bounds = np.searchsorted(own[order], np.arange(T + 1))
+            tets = np.unique(np.concatenate([corner, rng.choice(T, 138, replace=False)]))
+            _say(f"tetrahedron voxel sets: solution {s} grid {g}, {len(tets)} tetrahedra")
+            for t in tets:
+                mine = np.sort(order[bounds[t]:bounds[t + 1]])
+                theirs = np.sort(rp.tet_voxels(X[s, g], int(t)))
+                assert len(mine) == len(theirs) and np.array_equal(mine, theirs), (s, g, int(t))
 
 
 @pytest.mark.parametrize("level", [0, 1])
@@ -462,9 +495,10 @@ def test_empty_calls_are_no_ops():
     torch.cuda.synchronize()
 
 
-def test_maximum_image_size_sampled():
-    """512^3 images (the largest the exact lattice predicates support): one
-    full evaluation and sampled partial evaluations against the oracle."""
+def test_maximum_image_size():
+    """512^3 images (the largest the exact lattice predicates support): two
+    full evaluations and every single-point element of one solution against
+    the oracle."""
     shape = (512, 512, 512)
     rng = np.random.default_rng(8)
     coarse = rng.uniform(0, 1, (17, 17, 17)).astype(np.float32)
@@ -481,13 +515,14 @@ def test_maximum_image_size_sampled():
     obj, fl = gp.eval_full(_t(X))
     old, new, flg, vc = gp.eval_partial(_t(X), _t(off), _t(pts), _t(cand), voxel_count=True)
     torch.cuda.synchronize()
-    robj, rfl = rp.eval_full(X[:1])
-    np.testing.assert_array_equal(fl.cpu().numpy()[:1], rfl)
-    assert_objectives_close(obj.cpu().numpy()[:1], robj, what="full objectives at 512^3")
-    elems = np.array([0, 21, 42], dtype=np.int32)  # a corner, an interior and another interior point
-    rold, rnew, rfl2, rnv = rp.eval_partial(X[1:2], np.arange(4, dtype=np.int32), elems, cand[1:2, elems])
-    g_fl = flg.cpu().numpy()[1, elems][None].astype(np.uint32)
+    _say(f"{w.name}: oracle on every element of solution 1")
+    robj, rfl, rterms, _ = rp.eval_full(X[:2], want_terms=True)
+    np.testing.assert_array_equal(fl.cpu().numpy()[:2], rfl)
+    assert_objectives_close(obj.cpu().numpy()[:2], robj, what="full objectives at 512^3")
+    rold, rnew, rfl2, rnv = rp.eval_partial(X[1:2], off, pts, cand[1:2], tet_terms=rterms[1:2])
+    g_fl = flg.cpu().numpy()[1:2].astype(np.uint32)
     np.testing.assert_array_equal(g_fl, rfl2)
-    np.testing.assert_array_equal(vc.cpu().numpy()[1, elems][None][g_fl == 0], rnv[g_fl == 0])
-    assert_objectives_close(new.cpu().numpy()[1, elems][None], rnew, flags=g_fl, what="part_new at 512^3")
-    assert_objectives_close(old.cpu().numpy()[1, elems][None], rold, what="part_old at 512^3")
+    assert (g_fl == 0).sum() > w.P // 2
+    np.testing.assert_array_equal(vc.cpu().numpy()[1:2][g_fl == 0], rnv[g_fl == 0])
+    assert_objectives_close(new.cpu().numpy()[1:2], rnew, flags=g_fl, what="part_new at 512^3")
+    assert_objectives_close(old.cpu().numpy()[1:2], rold, what="part_old at 512^3")
