@@ -725,6 +725,7 @@ def main():
     evals_per_s = S * F / (ms / 1e3)
     samples_per_s = samples / (ms / 1e3)
     achieved = samples * BYTES_PER_SAMPLE / (kms / 1e3) / 1e9
+    achieved_step = samples * BYTES_PER_SAMPLE / (ms / 1e3) / 1e9
     traffic = measured_traffic()
     res = {
         "metric": "partial solution evals/s @512^2x100 (plain, batched)",
@@ -742,8 +743,19 @@ def main():
         "config": {"workload": w.name + f", meshes {w.mesh}, population {S}, {F} single-point FOS elements per step",
                    "partial_evals_per_step": S * F, "voxel_samples_per_step": samples},
         "voxel_samples_per_s": samples_per_s,
+        # "bound" names the roofline the fraction is taken against (HBM, on
+        # algorithmic bytes); "limiter" is what the kernel's counters show
+        # limits it: the vector-memory (texture) address and data path, with
+        # HBM-side traffic a few percent of the algorithmic bytes because both
+        # images stay in the caches.
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "limiter": "vector-memory gather path (texture address and data units busy 97-100 %)",
+                     "frac_step": achieved_step / HBM_PEAK_GBS,
+                     "hbm_measured_GBps": traffic / (kms / 1e3) / 1e9 if traffic else None,
+                     "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source, scaled by a copy "
+                                       "kernel (profiles/k_sweep_partial_clinical_traffic.txt); not re-measured "
+                                       "in this run" if traffic else None,
                      "kernel": "k_sweep<1> (partial-evaluation voxel sweep)", "kernel_ms": kms,
                      "algorithmic_bytes_per_launch": samples * BYTES_PER_SAMPLE,
                      "kernel_source_sha256_16": kernel_source_hash()},

@@ -41,6 +41,7 @@
 #ifndef DSM_H
 #define DSM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -202,6 +203,24 @@ dsm_status dsm_batch_destroy(dsm_batch* b);
  * problem), DSM_ERR_CAPACITY (n_jobs > max_jobs or a job above its problem's
  * capacities).  Waits on the host only for the previous call's job-table copy. */
 dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs, void* stream);
+
+/* The same fused evaluation split into a set-up call and an enqueue-only call,
+ * so that a generation over several problems (e.g. both pyramid levels of
+ * uneven problems) can be captured in a HIP graph and replayed.
+ * dsm_batch_set_jobs validates the jobs as dsm_eval_partial_batch does and
+ * stores their job table on the device (synchronously: it waits for the device
+ * to be idle, so call it before any capture); every pointer in the jobs is
+ * kept and must stay valid while the configuration is used.  The caller
+ * changes inputs between runs by writing into the same buffers.
+ * dsm_batch_run enqueues the affected-set, ordering, sweep and finishing
+ * kernels of the stored configuration on `stream`: no allocation, no copy, no
+ * host wait.  Results are identical to dsm_eval_partial_batch on the same
+ * jobs.  dsm_eval_partial_batch and dsm_batch_set_jobs use separate device
+ * tables; a new dsm_batch_set_jobs replaces the stored configuration.  Errors:
+ * as dsm_eval_partial_batch; dsm_batch_run without a configuration is a
+ * no-op. */
+dsm_status dsm_batch_set_jobs(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs);
+dsm_status dsm_batch_run(dsm_batch* b, void* stream);
 
 /* Device image layout.  The sampled images are stored on the device with a
  * replicated one-voxel border, z-pairs interleaved, in rows of `pitch`
@@ -532,6 +551,91 @@ dsm_status dsm_accept_elements(dsm_problem* p, int32_t S, float* X, int32_t F, c
                                const double* part_new, const uint32_t* flags, const double* terms_cand,
                                double* terms_cache, double* obj, int32_t n_archive, const double* archive,
                                const int32_t* single_objective, uint8_t* accepted, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Generation bookkeeping on the device.  All enqueue on `stream` only; sizes
+ * that live on the device (the archive's row count) are read by the kernels,
+ * so the calls can be captured in a HIP graph.  Workspaces are caller-owned
+ * device memory of the size the matching *_work_bytes function returns.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of workspace for dsm_archive_merge (host function, no device). */
+size_t dsm_archive_work_bytes(int32_t capacity, int32_t m, int32_t row_floats);
+
+/* Sec. 2.4 (the approximation set the finer run is seeded from): merges m
+ * objective vectors points dev [m][3] float64 into the elitist archive.  The
+ * archive is archive dev [capacity][3] float64 holding *n_archive (dev int32)
+ * rows that are mutually non-dominated, distinct and in lexicographic order,
+ * +inf in every later row, as this call leaves them (start from *n_archive = 0
+ * or any such set).  Of the archive rows then the points, in that order, a
+ * vector is kept iff no vector of either dominates it (minimisation) and no
+ * earlier one equals it; the kept vectors are written back in lexicographic
+ * order, later rows set to +inf, and *n_archive updated.  With row_floats > 0
+ * every vector carries a payload row (e.g. its solution): archive_rows dev
+ * [capacity][row_floats] moves with the archive, point_rows dev
+ * [m][row_floats] are the points' rows.  If more than `capacity` vectors would
+ * be kept, nothing changes and *overflow (dev int32, may be NULL) is set to 1,
+ * else to 0.  work: dev, dsm_archive_work_bytes(capacity, m, row_floats)
+ * bytes.  Errors: DSM_ERR_ARG (sizes, null pointers), DSM_ERR_DEVICE. */
+dsm_status dsm_archive_merge(int32_t capacity, double* archive, int32_t* n_archive, int32_t m, const double* points,
+                             int32_t row_floats, float* archive_rows, const float* point_rows, void* work,
+                             int32_t* overflow, void* stream);
+
+/* Sec. 2.2 selection for the distributions of the partial changes: the n_sel
+ * of the S solutions (obj dev [S][3] float64) with the fewest population
+ * members dominating them, ties by the smallest sum, in objective order, of
+ * the objectives normalised to the population's range (divisor at least
+ * 1e-300), then by index; sel dev [n_sel] int32 in that order.
+ * dominated_by dev [S] int32 or NULL receives every solution's count.  One
+ * workgroup.  Errors: DSM_ERR_ARG (n_sel outside [0, S], null pointers),
+ * DSM_ERR_CAPACITY (S > 8192), DSM_ERR_DEVICE. */
+dsm_status dsm_select(int32_t S, const double* obj, int32_t n_sel, int32_t* sel, int32_t* dominated_by, void* stream);
+
+/* Adaptive variance scaling of the distribution multipliers (AMaLGaM's rule,
+ * used by RV-GOMEA, Sec. 2.2), n independent distributions, float32: with
+ * sdr dev [n] float64 (the standard-deviation ratio of the accepted changes,
+ * < 0 where none was accepted, as dsm_improvement_ratio writes it), after an
+ * improvement the multiplier is at least 1 and is divided by eta if sdr > 1,
+ * and the no-improvement stretch nis restarts at 0; otherwise the stretch
+ * grows by 1 while the multiplier is at most 1, the multiplier is multiplied
+ * by eta if it is above 1 or the stretch reached nis_max, and reset to 1 if
+ * it fell below 1 while the stretch is shorter than nis_max.  The result is
+ * clamped to [lo, hi].  mult dev [n] float32 and nis dev [n] int32 are updated
+ * in place.  Errors: DSM_ERR_ARG (eta outside (0, 1), lo not in (0, hi], null
+ * pointers), DSM_ERR_DEVICE. */
+dsm_status dsm_avs_update(int32_t n, float* mult, int32_t* nis, const double* sdr, int32_t nis_max, float eta, float lo,
+                          float hi, void* stream);
+
+/* The simple multiplier schedule of the distributions (a simplification of
+ * the adaptive variance scaling above): for every cluster j < k and element
+ * f, the multiplier mult dev [k][F] float32 is divided by eta (at most hi) if
+ * some solution s of cluster j (cluster dev [S] int32; with k = 1 every
+ * solution, and cluster may be NULL) had element f accepted (accepted dev
+ * [S][F] uint8, as dsm_accept writes it), else multiplied by eta (at least
+ * lo).  Errors: DSM_ERR_ARG, DSM_ERR_DEVICE. */
+dsm_status dsm_multiplier_step(int32_t k, int32_t F, int32_t S, const uint8_t* accepted, const int32_t* cluster,
+                               float* mult, float eta, float lo, float hi, void* stream);
+
+/* improved dev [S] uint8 is set to 1 where some entry of accepted dev [S][F]
+ * (as dsm_accept writes it) is non-zero; other entries are left as they are
+ * (clear it once per generation, then call once per class step). */
+dsm_status dsm_mark_improved(int32_t S, int32_t F, const uint8_t* accepted, uint8_t* improved, void* stream);
+
+/* Bytes of workspace for dsm_forced_replace (host function). */
+size_t dsm_forced_work_bytes(const dsm_problem* p, int32_t S);
+
+/* Forced improvements (RV-GOMEA, Sec. 2.2) at the end of a generation: a
+ * solution's no-improvement stretch nis dev [S] int32 restarts at 0 if
+ * improved dev [S] uint8 is set and grows by 1 otherwise; a solution with a
+ * donor (donor dev [S] int32 >= 0, -1 = none) that accepted nothing takes the
+ * donor's coordinates X dev [S][2][P][3], objectives obj dev [S][3] and term
+ * cache dev [S][T][3] as they were before this call (chains of donors read
+ * the old rows); every solution with a donor restarts its stretch.
+ * n_replaced dev [1] int32 or NULL is increased by the number replaced.
+ * work: dev, dsm_forced_work_bytes(p, S) bytes.  Errors: DSM_ERR_ARG,
+ * DSM_ERR_DEVICE. */
+dsm_status dsm_forced_replace(dsm_problem* p, int32_t S, float* X, double* obj, double* cache, const int32_t* donor,
+                              const uint8_t* improved, int32_t* nis, void* work, int32_t* n_replaced, void* stream);
 
 #ifdef __cplusplus
 }

@@ -226,3 +226,122 @@ def standard_deviation_ratio(samples, mean, cov):
     var = np.diag(np.asarray(cov, dtype=np.float64))
     ok = var > 0
     return float((d[ok] / np.sqrt(var[ok])).max()) if ok.any() else 0.0
+
+
+# ---------------------------------------------------------------------------
+# Generation bookkeeping of the multi-objective optimiser (Sec. 2.2, Sec. 2.4)
+# written from the definitions, one solution at a time.
+
+def dominates(a, b):
+    """a Pareto-dominates b (minimisation): no worse in every objective, better in one."""
+    return all(x <= y for x, y in zip(a, b)) and any(x < y for x, y in zip(a, b))
+
+
+def archive_merge(archive, points, archive_rows=None, point_rows=None):
+    """The elitist archive (the approximation set of Sec. 2.4) after adding
+    `points`: of archive rows then points, in that order, a vector is kept iff
+    no vector of either dominates it and no earlier vector equals it; the kept
+    vectors are returned in lexicographic order, with their payload rows (e.g.
+    solutions) if given.  Returns (vectors [k][3], rows [k][...] or None)."""
+    vecs = [tuple(float(v) for v in r) for r in np.asarray(archive, np.float64).reshape(-1, 3)]
+    vecs += [tuple(float(v) for v in r) for r in np.asarray(points, np.float64).reshape(-1, 3)]
+    rows = None
+    if archive_rows is not None:
+        rows = list(np.asarray(archive_rows)) + list(np.asarray(point_rows))
+    kept = []
+    for i, v in enumerate(vecs):
+        if any(dominates(u, v) for u in vecs):
+            continue
+        if any(vecs[j] == v for j in range(i)):
+            continue
+        kept.append(i)
+    kept.sort(key=lambda i: vecs[i])  # tuples compare lexicographically
+    out = np.array([vecs[i] for i in kept], np.float64).reshape(-1, 3)
+    return out, (None if rows is None else np.array([rows[i] for i in kept]))
+
+
+def select(obj, n_sel):
+    """Selection: the n_sel solutions with the fewest population members
+    dominating them; ties by the smallest sum, in objective order, of the
+    objectives normalised to the population's range (divisor at least 1e-300),
+    then by index.  Returns (indices [n_sel], dominated-by counts [S])."""
+    obj = np.asarray(obj, np.float64)
+    S = len(obj)
+    count = np.array([sum(1 for j in range(S) if dominates(obj[j], obj[i])) for i in range(S)])
+    lo = [min(obj[:, c]) for c in range(3)]
+    hi = [max(obj[:, c]) for c in range(3)]
+    key = []
+    for i in range(S):
+        nrm = 0.0
+        for c in range(3):
+            nrm = nrm + (obj[i, c] - lo[c]) / max(hi[c] - lo[c], 1e-300)
+        key.append((count[i] * 4.0 + nrm, i))
+    order = [i for _, i in sorted(key)]
+    return np.array(order[:n_sel], np.int64), count
+
+
+def avs_update(mult, nis, sdr, nis_max, eta=0.9, lo=0.05, hi=10.0):
+    """AMaLGaM's adaptive variance scaling step per distribution, in float32:
+    after an improvement (sdr >= 0) the multiplier is at least 1 and is divided
+    by eta if sdr > 1, and the no-improvement stretch restarts; without one the
+    stretch grows while the multiplier is at most 1, the multiplier is
+    multiplied by eta if it is above 1 or the stretch reached nis_max, and is
+    reset to 1 if it fell below 1 while the stretch is short; the result is
+    clamped to [lo, hi].  Returns (mult float32, nis int32)."""
+    f32 = np.float32
+    out_c = np.zeros(len(mult), np.float32)
+    out_n = np.zeros(len(mult), np.int32)
+    for i, (c, n, r) in enumerate(zip(np.asarray(mult, np.float32), np.asarray(nis), np.asarray(sdr, np.float64))):
+        c = f32(c)
+        if r >= 0:
+            c1 = f32(1.0) if c < 1 else c
+            if r > 1:
+                c1 = f32(c1 / f32(eta))
+            n1 = 0
+        else:
+            n1 = int(n) + 1 if c <= 1 else int(n)
+            c1 = c
+            if c > 1 or n1 >= nis_max:
+                c1 = f32(c * f32(eta))
+            if c1 < 1 and n1 < nis_max:
+                c1 = f32(1.0)
+        out_c[i] = min(max(c1, f32(lo)), f32(hi))
+        out_n[i] = n1
+    return out_c, out_n
+
+
+def forced_replace(X, obj, cache, donor, improved, nis):
+    """Forced improvements at the end of a generation: the no-improvement
+    stretch of a solution restarts if it accepted a change and grows otherwise;
+    a solution that had a donor (donor >= 0) and accepted nothing takes the
+    donor's coordinates, objectives and per-tetrahedron terms as they were
+    before this step; every solution that had a donor restarts its stretch.
+    Returns new (X, obj, cache, nis, number replaced)."""
+    X2, obj2, cache2, nis2 = X.copy(), obj.copy(), cache.copy(), np.asarray(nis).copy()
+    replaced = 0
+    for s in range(len(X)):
+        nis2[s] = 0 if improved[s] else nis2[s] + 1
+        d = int(donor[s])
+        if d >= 0:
+            if not improved[s]:
+                X2[s], obj2[s], cache2[s] = X[d], obj[d], cache[d]
+                replaced += 1
+            nis2[s] = 0
+    return X2, obj2, cache2, nis2, replaced
+
+
+def multiplier_step(accepted, mult, cluster=None, eta=0.9, lo=0.05, hi=10.0):
+    """The simple multiplier schedule, float32: for each cluster j and element
+    f the multiplier is divided by eta (at most hi) if a solution of cluster j
+    (every solution without clusters) had element f accepted, else multiplied
+    by eta (at least lo)."""
+    acc = np.asarray(accepted)
+    out = np.asarray(mult, np.float32).copy()
+    k, F = out.shape
+    for j in range(k):
+        for f in range(F):
+            hit = any(acc[s, f] and (cluster is None or cluster[s] == j) for s in range(acc.shape[0]))
+            c = np.float32(out[j, f])
+            out[j, f] = min(np.float32(c / np.float32(eta)), np.float32(hi)) if hit else \
+                max(np.float32(c * np.float32(eta)), np.float32(lo))
+    return out

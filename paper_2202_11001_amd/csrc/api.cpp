@@ -495,6 +495,17 @@ dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t
 
 }  // extern "C"
 
+// What the affected-set and ordering launches of one stored job need.
+struct BatchSetJob {
+  DevProblem pr;
+  int F, max_pts, maxA;
+  const int* fos_off;
+  const int* fos_pts;
+  int* aff;
+  int* aff_cnt;
+  int* order;  // null: no ordering launch
+};
+
 struct dsm_batch {
   int max_jobs = 0;
   EvalArgs* d_jobs = nullptr;
@@ -503,7 +514,69 @@ struct dsm_batch {
   int* h_off = nullptr;
   hipEvent_t copied = nullptr;
   bool pending = false;
+  // configuration stored by dsm_batch_set_jobs
+  EvalArgs* d_set_jobs = nullptr;
+  int* d_set_off = nullptr;
+  std::vector<BatchSetJob> set;
+  int set_n = 0, set_per_xcd = 0, set_total_finish = 0;
+  size_t set_lds = 0;
 };
+
+namespace {
+
+// Validates the jobs and fills their evaluation arguments, the per-XCD slot
+// offsets of the sweep (a job of n workgroups takes ceil(n / 8) slots on each
+// of the 8 XCDs) and the workgroup offsets of the finishing kernel.
+dsm_status batch_tables(const dsm_batch* b, int n_jobs, const dsm_partial_job* jobs, std::vector<EvalArgs>& args,
+                        std::vector<int>& off, std::vector<int>& foff, size_t& lds) {
+  if (!b || (n_jobs > 0 && !jobs) || n_jobs < 0) return fail(DSM_ERR_ARG, "null argument");
+  if (n_jobs > b->max_jobs) return fail(DSM_ERR_CAPACITY, "n_jobs = %d exceeds max_jobs = %d", n_jobs, b->max_jobs);
+  args.assign(n_jobs, EvalArgs{});
+  off.assign(n_jobs + 1, 0);
+  foff.assign(n_jobs + 1, 0);
+  lds = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const dsm_partial_job& q = jobs[j];
+    dsm_problem* p = q.problem;
+    if (!p || !q.X || !q.fos_off || !q.fos_pts || !q.cand || !q.part_old || !q.part_new || !q.flags)
+      return fail(DSM_ERR_ARG, "job %d: null argument", j);
+    for (int k = 0; k < j; ++k)
+      if (jobs[k].problem == p) return fail(DSM_ERR_ARG, "job %d repeats the problem of job %d", j, k);
+    if (q.S < 0 || q.F < 0) return fail(DSM_ERR_ARG, "job %d: negative S or F", j);
+    if (q.S > p->max_S || q.F > p->max_F) return fail(DSM_ERR_CAPACITY, "job %d: S or F above the problem's capacity", j);
+    EvalArgs& a = args[j];
+    a.pr = p->dev;
+    a.S = q.S;
+    a.G = q.F;
+    a.partial = 1;
+    a.X = q.X;
+    a.fos_off = q.fos_off;
+    a.fos_pts = q.fos_pts;
+    a.cand = q.cand;
+    a.aff = p->d_aff;
+    a.aff_cnt = p->d_aff_cnt;
+    a.order = q.F <= kOrderMax ? p->d_order : nullptr;
+    a.maxA = p->maxA;
+    a.nver = q.tet_terms_in ? 1 : 2;
+    a.terms_in = q.tet_terms_in;
+    a.part_old = q.part_old;
+    a.part_new = q.part_new;
+    a.flags = q.flags;
+    a.terms_out = q.tet_terms_new;
+    a.vcount = q.voxel_count;
+    a.mask = q.mask;
+    a.simws = p->d_simws;
+    a.nchunk = p->nchunk;
+    a.cflags = p->d_cflags;
+    a.ccount = p->d_ccount;
+    off[j + 1] = off[j] + (q.S * q.F * a.nchunk + 7) / 8;
+    foff[j + 1] = foff[j] + q.S * q.F;
+    lds = std::max(lds, eval_lds_bytes(kMaxChunk, a.nver));
+  }
+  return DSM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -535,58 +608,19 @@ dsm_status dsm_batch_destroy(dsm_batch* b) {
   if (b->h_jobs) (void)hipHostFree(b->h_jobs);
   if (b->h_off) (void)hipHostFree(b->h_off);
   if (b->copied) (void)hipEventDestroy(b->copied);
+  if (b->d_set_jobs) (void)hipFree(b->d_set_jobs);
+  if (b->d_set_off) (void)hipFree(b->d_set_off);
   delete b;
   return DSM_OK;
 }
 
 dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs, void* stream) {
   g_err.clear();
-  if (!b || (n_jobs > 0 && !jobs) || n_jobs < 0) return fail(DSM_ERR_ARG, "null argument");
-  if (n_jobs > b->max_jobs) return fail(DSM_ERR_CAPACITY, "n_jobs = %d exceeds max_jobs = %d", n_jobs, b->max_jobs);
-  std::vector<EvalArgs> args(n_jobs);
-  // sweep: per-XCD slot offsets (a job of n workgroups takes ceil(n / 8) slots
-  // on each of the 8 XCDs); finish: workgroup offsets
-  std::vector<int> off(n_jobs + 1, 0), foff(n_jobs + 1, 0);
+  std::vector<EvalArgs> args;
+  std::vector<int> off, foff;
   size_t lds = 0;
-  for (int j = 0; j < n_jobs; ++j) {
-    const dsm_partial_job& q = jobs[j];
-    dsm_problem* p = q.problem;
-    if (!p || !q.X || !q.fos_off || !q.fos_pts || !q.cand || !q.part_old || !q.part_new || !q.flags)
-      return fail(DSM_ERR_ARG, "job %d: null argument", j);
-    for (int k = 0; k < j; ++k)
-      if (jobs[k].problem == p) return fail(DSM_ERR_ARG, "job %d repeats the problem of job %d", j, k);
-    if (q.S < 0 || q.F < 0) return fail(DSM_ERR_ARG, "job %d: negative S or F", j);
-    if (q.S > p->max_S || q.F > p->max_F) return fail(DSM_ERR_CAPACITY, "job %d: S or F above the problem's capacity", j);
-    EvalArgs& a = args[j];
-    a = EvalArgs{};
-    a.pr = p->dev;
-    a.S = q.S;
-    a.G = q.F;
-    a.partial = 1;
-    a.X = q.X;
-    a.fos_off = q.fos_off;
-    a.fos_pts = q.fos_pts;
-    a.cand = q.cand;
-    a.aff = p->d_aff;
-    a.aff_cnt = p->d_aff_cnt;
-    a.order = q.F <= kOrderMax ? p->d_order : nullptr;
-    a.maxA = p->maxA;
-    a.nver = q.tet_terms_in ? 1 : 2;
-    a.terms_in = q.tet_terms_in;
-    a.part_old = q.part_old;
-    a.part_new = q.part_new;
-    a.flags = q.flags;
-    a.terms_out = q.tet_terms_new;
-    a.vcount = q.voxel_count;
-    a.mask = q.mask;
-    a.simws = p->d_simws;
-    a.nchunk = p->nchunk;
-    a.cflags = p->d_cflags;
-    a.ccount = p->d_ccount;
-    off[j + 1] = off[j] + (q.S * q.F * a.nchunk + 7) / 8;
-    foff[j + 1] = foff[j] + q.S * q.F;
-    lds = std::max(lds, eval_lds_bytes(kMaxChunk, a.nver));
-  }
+  const dsm_status vs = batch_tables(b, n_jobs, jobs, args, off, foff, lds);
+  if (vs != DSM_OK) return vs;
   if (n_jobs == 0 || off[n_jobs] == 0) return DSM_OK;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSuccess;
@@ -610,6 +644,58 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
   if ((e = launch_eval_batch(b->d_jobs, b->d_off, n_jobs, off[n_jobs], foff[n_jobs], lds, st)) != hipSuccess)
     return hip_fail(e, "batched evaluation launch");
   return DSM_OK;
+}
+
+dsm_status dsm_batch_set_jobs(dsm_batch* b, int32_t n_jobs, const dsm_partial_job* jobs) {
+  g_err.clear();
+  std::vector<EvalArgs> args;
+  std::vector<int> off, foff;
+  size_t lds = 0;
+  const dsm_status vs = batch_tables(b, n_jobs, jobs, args, off, foff, lds);
+  if (vs != DSM_OK) return vs;
+  hipError_t e = hipSuccess;
+  if (!b->d_set_jobs) {
+    e = hipMalloc((void**)&b->d_set_jobs, sizeof(EvalArgs) * b->max_jobs);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_set_off, sizeof(int) * 2 * (b->max_jobs + 1));
+    if (e != hipSuccess) return hip_fail(e, "batch configuration allocation");
+  }
+  // the previous configuration may still be in use by enqueued runs
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "device synchronisation");
+  std::vector<int> both(off);
+  both.insert(both.end(), foff.begin(), foff.end());
+  if (n_jobs > 0) {
+    e = hipMemcpy(b->d_set_jobs, args.data(), sizeof(EvalArgs) * n_jobs, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_set_off, both.data(), sizeof(int) * both.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "job table copy");
+  }
+  b->set.clear();
+  for (int j = 0; j < n_jobs; ++j) {
+    const EvalArgs& a = args[j];
+    if (a.S <= 0 || a.G <= 0) continue;
+    dsm_problem* p = jobs[j].problem;
+    b->set.push_back(BatchSetJob{a.pr, a.G, p->max_pts, a.maxA, a.fos_off, a.fos_pts, p->d_aff, p->d_aff_cnt,
+                                 a.order ? p->d_order : nullptr});
+  }
+  b->set_per_xcd = n_jobs > 0 ? off[n_jobs] : 0;
+  b->set_total_finish = n_jobs > 0 ? foff[n_jobs] : 0;
+  b->set_lds = lds;
+  b->set_n = n_jobs;
+  return DSM_OK;
+}
+
+dsm_status dsm_batch_run(dsm_batch* b, void* stream) {
+  g_err.clear();
+  if (!b) return fail(DSM_ERR_ARG, "null batch");
+  if (b->set_per_xcd == 0) return DSM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (const BatchSetJob& q : b->set) {
+    e = launch_affected(q.pr, q.F, q.fos_off, q.fos_pts, q.max_pts, q.maxA, q.aff, q.aff_cnt, st);
+    if (e == hipSuccess && q.order) e = launch_order(q.F, q.aff_cnt, q.order, st);
+    if (e != hipSuccess) return hip_fail(e, "affected-set launch");
+  }
+  e = launch_eval_batch(b->d_set_jobs, b->d_set_off, b->set_n, b->set_per_xcd, b->set_total_finish, b->set_lds, st);
+  return e == hipSuccess ? DSM_OK : hip_fail(e, "batched evaluation launch");
 }
 
 dsm_status dsm_problem_timing(dsm_problem* p, int32_t capacity) {

@@ -96,6 +96,16 @@ def lib():
             "dsm_batch_create": ([I, V], I),
             "dsm_batch_destroy": ([V], I),
             "dsm_eval_partial_batch": ([V, I, V, V], I),
+            "dsm_batch_set_jobs": ([V, I, V], I),
+            "dsm_archive_work_bytes": ([I, I, I], C.c_size_t),
+            "dsm_archive_merge": ([I, V, V, I, V, I, V, V, V, V, V], I),
+            "dsm_select": ([I, V, I, V, V, V], I),
+            "dsm_avs_update": ([I, V, V, V, I, C.c_float, C.c_float, C.c_float, V], I),
+            "dsm_mark_improved": ([I, I, V, V, V], I),
+            "dsm_multiplier_step": ([I, I, I, V, V, V, C.c_float, C.c_float, C.c_float, V], I),
+            "dsm_forced_work_bytes": ([V, I], C.c_size_t),
+            "dsm_forced_replace": ([V, I, V, V, V, V, V, V, V, V, V], I),
+            "dsm_batch_run": ([V, V], I),
             "dsm_problem_set_pitch": ([V, I], I),
             "dsm_refine_population": ([V, I, V, V, V], I),
             "dsm_autotune_pitch": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
@@ -188,6 +198,94 @@ def improvement_ratio(off, cand, accepted, mean, chol, cluster=None, stream=None
     _check(lib().dsm_improvement_ratio(S, F, _dptr(off), _dptr(cand), _dptr(accepted), C, _dptr(cluster),
                                        _dptr(mean), _dptr(chol), n_vars, _dptr(out), _stream(stream)))
     return out
+
+
+class Archive:
+    """The elitist archive on the device (``dsm_archive_merge``): vectors
+    float64 [capacity][3] in lexicographic order, +inf after the count; with
+    row_floats > 0 a payload row per vector.  The count lives on the device
+    (``n_dev``); ``n`` reads it."""
+
+    def __init__(self, capacity, m_max, row_floats=0, device="cuda:0"):
+        torch = _torch()
+        self.capacity, self.m_max, self.row_floats = int(capacity), int(m_max), int(row_floats)
+        self.vec = torch.full((self.capacity, 3), float("inf"), dtype=torch.float64, device=device)
+        self.rows = torch.empty((self.capacity, self.row_floats), dtype=torch.float32, device=device) \
+            if self.row_floats else None
+        self.n_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        nbytes = lib().dsm_archive_work_bytes(self.capacity, self.m_max, self.row_floats)
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    @property
+    def n(self):
+        return int(self.n_dev.item())
+
+    def merge(self, points, rows=None, stream=None):
+        """Merges points float64 [m][3] (m <= m_max), with payload rows [m][row_floats] if the archive has them."""
+        torch = _torch()
+        m = points.shape[0]
+        if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3 or m > self.m_max:
+            raise ValueError(f"archive merge: points float64 [m][3] with m <= {self.m_max} expected")
+        if self.row_floats and (rows is None or rows.dtype != torch.float32 or rows.numel() != m * self.row_floats):
+            raise ValueError(f"archive merge: rows float32 [m][{self.row_floats}] expected")
+        _check(lib().dsm_archive_merge(self.capacity, _dptr(self.vec), _dptr(self.n_dev), m, _dptr(points),
+                                       self.row_floats, _dptr(self.rows), _dptr(rows) if self.row_floats else None,
+                                       _dptr(self.work), _dptr(self.overflow), _stream(stream)))
+
+
+def select(obj, n_sel, dominated_by=None, stream=None):
+    """Selection (``dsm_select``): int32 [n_sel] indices of obj float64 [S][3]
+    with the fewest dominating members, ties by the normalised objective sum;
+    dominated_by int32 [S] receives the counts if given."""
+    torch = _torch()
+    S = obj.shape[0]
+    if obj.dtype != torch.float64 or obj.dim() != 2 or obj.shape[1] != 3 or not 0 <= n_sel <= S:
+        raise ValueError("select: obj float64 [S][3] and 0 <= n_sel <= S expected")
+    if dominated_by is not None and (dominated_by.dtype != torch.int32 or dominated_by.numel() != S):
+        raise ValueError("select: dominated_by int32 [S] expected")
+    sel = torch.empty(n_sel, dtype=torch.int32, device=obj.device)
+    _check(lib().dsm_select(S, _dptr(obj), int(n_sel), _dptr(sel), _dptr(dominated_by), _stream(stream)))
+    return sel
+
+
+def avs_update(mult, nis, sdr, nis_max, eta=0.9, lo=0.05, hi=10.0, stream=None):
+    """Adaptive variance scaling in place (``dsm_avs_update``): mult float32,
+    nis int32 and sdr float64 of equal size; returns (mult, nis)."""
+    torch = _torch()
+    n = mult.numel()
+    if (mult.dtype != torch.float32 or nis.dtype != torch.int32 or sdr.dtype != torch.float64 or nis.numel() != n
+            or sdr.numel() != n or not (mult.is_contiguous() and nis.is_contiguous() and sdr.is_contiguous())):
+        raise ValueError("avs_update: contiguous mult float32, nis int32, sdr float64 of equal size expected")
+    _check(lib().dsm_avs_update(n, _dptr(mult), _dptr(nis), _dptr(sdr), int(nis_max), float(eta), float(lo), float(hi),
+                                _stream(stream)))
+    return mult, nis
+
+
+def multiplier_step(accepted, mult, cluster=None, eta=0.9, lo=0.05, hi=10.0, stream=None):
+    """The simple multiplier schedule in place (``dsm_multiplier_step``):
+    accepted uint8 [S][F], mult float32 [k][F] (contiguous), cluster int32 [S]
+    (needed when k > 1)."""
+    torch = _torch()
+    S, F = accepted.shape
+    k = mult.shape[0]
+    if (accepted.dtype != torch.uint8 or mult.dtype != torch.float32 or mult.dim() != 2 or mult.shape[1] != F
+            or not mult.is_contiguous() or (k > 1 and (cluster is None or cluster.dtype != torch.int32
+                                                       or cluster.numel() != S))):
+        raise ValueError("multiplier_step: accepted uint8 [S][F], mult float32 [k][F], cluster int32 [S] expected")
+    _check(lib().dsm_multiplier_step(k, F, S, _dptr(accepted), _dptr(cluster) if k > 1 else None, _dptr(mult),
+                                     float(eta), float(lo), float(hi), _stream(stream)))
+    return mult
+
+
+def mark_improved(accepted, improved, stream=None):
+    """improved uint8 [S] |= any(accepted uint8 [S][F], axis 1) (``dsm_mark_improved``)."""
+    torch = _torch()
+    S = improved.numel()
+    if accepted.dtype != torch.uint8 or improved.dtype != torch.uint8 or accepted.shape[0] != S:
+        raise ValueError("mark_improved: accepted uint8 [S][F], improved uint8 [S] expected")
+    F = accepted.numel() // max(1, S)
+    _check(lib().dsm_mark_improved(S, F, _dptr(accepted), _dptr(improved), _stream(stream)))
 
 
 def mesh_topology(mesh, dims=None):
@@ -452,6 +550,20 @@ class Problem:
                                          _stream(stream)))
         return cand
 
+    def forced_replace(self, X, obj, cache, donor, improved, nis, n_replaced=None, work=None, stream=None):
+        """Forced-improvement replacement in place (``dsm_forced_replace``);
+        work is allocated here if not given (pass it to allocate nothing)."""
+        torch = _torch()
+        S = X.shape[0]
+        if (donor.dtype != torch.int32 or donor.numel() != S or improved.dtype != torch.uint8 or improved.numel() != S
+                or nis.dtype != torch.int32 or nis.numel() != S or obj.dtype != torch.float64
+                or cache.dtype != torch.float64 or cache.numel() != S * self.T * 3 or X.numel() != S * 6 * self.P):
+            raise ValueError("forced_replace: argument shapes or dtypes")
+        if work is None:
+            work = torch.empty(lib().dsm_forced_work_bytes(self._h, S), dtype=torch.uint8, device=X.device)
+        _check(lib().dsm_forced_replace(self._h, S, _dptr(X), _dptr(obj), _dptr(cache), _dptr(donor), _dptr(improved),
+                                        _dptr(nis), _dptr(work), _dptr(n_replaced), _stream(stream)))
+
     def accept_elements(self, X, off, pts, cand, part_old, part_new, flags, terms_cand, terms_cache, obj, archive=None,
                         accepted=None, stream=None, single_objective=None):
         """accept for elements of several points (CSR off [F+1], pts), candidates
@@ -666,9 +778,21 @@ class Batch:
         except Exception:
             pass
 
-    def eval_partial(self, jobs, stream=None):
-        """jobs: list of dicts (problem, X, fos_off, fos_pts, cand, [tet_terms_in, mask]); returns a list of
-        (part_old, part_new, flags, voxel_count) per job."""
+    def set_jobs(self, jobs):
+        """Stores a configuration for run() (dsm_batch_set_jobs; synchronises the
+        device): jobs as for eval_partial; returns the output tensors
+        (part_old, part_new, flags, voxel_count) per job, which every run()
+        overwrites.  The job tensors must stay alive and keep their storage."""
+        arr, outs = self._table(jobs)
+        self._set_keep = (arr, jobs, outs)
+        _check(lib().dsm_batch_set_jobs(self._h, len(jobs), arr))
+        return outs
+
+    def run(self, stream=None):
+        """Enqueues the stored configuration (dsm_batch_run): capture-safe."""
+        _check(lib().dsm_batch_run(self._h, _stream(stream)))
+
+    def _table(self, jobs):
         torch = _torch()
         arr = (PartialJob * len(jobs))()
         outs = []
@@ -685,6 +809,12 @@ class Batch:
                                 d["mask"].data_ptr() if d.get("mask") is not None else None,
                                 d["tet_terms_in"].data_ptr() if d.get("tet_terms_in") is not None else None,
                                 o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), None, o[3].data_ptr())
+        return arr, outs
+
+    def eval_partial(self, jobs, stream=None):
+        """jobs: list of dicts (problem, X, fos_off, fos_pts, cand, [tet_terms_in, mask]); returns a list of
+        (part_old, part_new, flags, voxel_count) per job."""
+        arr, outs = self._table(jobs)
         self._keep = (arr, jobs, outs)
         _check(lib().dsm_eval_partial_batch(self._h, len(jobs), arr, _stream(stream)))
         return outs

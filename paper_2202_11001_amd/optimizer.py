@@ -84,79 +84,11 @@ def merge_archive(archive, new):
     return out[np.lexsort(out.T[::-1])]
 
 
-def merge_archive_device(arch, n, new, arch_X=None, new_X=None):
-    """merge_archive on the device: arch float64 [capacity][3] holds the
-    archive in rows 0..n-1 (+inf after), new [m][3]; the non-dominated rows of
-    both (duplicates kept once) are written back to arch in lexicographic order,
-    the remaining rows set to +inf.  With a payload (arch_X [capacity][...]
-    holding the archived rows' solutions, new_X [m][...]) the solutions move
-    with their rows.  Returns their number."""
-    import torch
-    pts = torch.cat([arch[:n], new.to(torch.float64)])
-    M = pts.shape[0]
-    idx = torch.arange(M, device=pts.device)
-    keep = torch.empty(M, dtype=torch.bool, device=pts.device)
-    for b in range(0, M, 2048):
-        blk = pts[b:b + 2048]
-        le = (pts[None, :, :] <= blk[:, None, :]).all(-1)
-        lt = (pts[None, :, :] < blk[:, None, :]).any(-1)
-        eq = (pts[None, :, :] == blk[:, None, :]).all(-1)
-        earlier = idx[None, :] < idx[b:b + 2048, None]
-        keep[b:b + 2048] = ~(le & lt).any(1) & ~(eq & earlier).any(1)
-    rows = idx[keep]
-    for c in (2, 1, 0):  # lexicographic: stable sorts from the last key
-        rows = rows[torch.argsort(pts[rows, c], stable=True)]
-    k = rows.shape[0]
-    if k > arch.shape[0]:
-        raise ValueError(f"archive of {k} points exceeds the capacity {arch.shape[0]}")
-    if arch_X is not None:
-        arch_X[:k] = torch.cat([arch_X[:n], new_X])[rows]
-    arch[:k] = pts[rows]
-    arch[k:] = float("inf")
-    return k
-
-
-def merge_archive_with(archive, archive_X, new, new_X):
-    """merge_archive that carries a payload row (e.g. the solution) with every
-    objective vector; among equal vectors the archived one is kept."""
-    pts = np.concatenate([np.asarray(archive, np.float64).reshape(-1, 3), np.asarray(new, np.float64)])
-    pay = new_X if len(archive) == 0 else np.concatenate([archive_X, new_X])
-    n = len(pts)
-    keep = np.ones(n, dtype=bool)
-    for b in range(0, n, 1024):
-        blk = pts[b:b + 1024]
-        le = np.all(pts[None, :, :] <= blk[:, None, :], axis=2)
-        lt = np.any(pts[None, :, :] < blk[:, None, :], axis=2)
-        eq = np.all(pts[None, :, :] == blk[:, None, :], axis=2)
-        earlier = np.arange(n)[None, :] < np.arange(b, b + len(blk))[:, None]
-        keep[b:b + 1024] = ~np.any(le & lt, axis=1) & ~np.any(eq & earlier, axis=1)
-    order = np.lexsort(pts[keep].T[::-1])
-    return pts[keep][order], pay[keep][order]
-
-
 # The full RV-GOMEA configuration (estimated distributions per cluster of the
 # selection, anticipated mean shift, forced improvements, standard-deviation-
 # ratio multipliers), the best measured one on both FOS; pass as
 # Optimiser(problem, X, fos=..., **RV_GOMEA) or run(..., **RV_GOMEA).
 RV_GOMEA = dict(sampler="estimated", clusters=5, ams=True, forced_improvements=True, multiplier_schedule="sdr")
-
-
-def avs_update(c, nis, sdr, nis_max, eta=0.9, lo=0.05, hi=10.0):
-    """AMaLGaM's adaptive variance scaling step for multipliers c (with their
-    no-improvement stretches nis) given standard-deviation ratios sdr (-1: no
-    improvement): after an improvement the multiplier is at least 1 and grows
-    by 1/eta if sdr > 1; otherwise the stretch grows while c <= 1, c shrinks by
-    eta if c > 1 or the stretch reached nis_max, and returns to 1 while the
-    stretch is short.  Returns (c, nis), c within [lo, hi]."""
-    import torch
-    imp = sdr >= 0
-    one = torch.ones_like(c)
-    c1 = torch.where(imp & (c < 1), one, c)
-    c1 = torch.where(imp & (sdr > 1), c1 / eta, c1)
-    nis1 = torch.where(imp, torch.zeros_like(nis), torch.where(c <= 1, nis + 1, nis))
-    c1 = torch.where(~imp & ((c > 1) | (nis1 >= nis_max)), c * eta, c1)
-    c1 = torch.where(~imp & (c1 < 1) & (nis1 < nis_max), one, c1)
-    return torch.clamp(c1, lo, hi), nis1
 
 
 def hypervolume(points, ref):
@@ -242,14 +174,15 @@ class Optimiser:
         self.obj = obj
         self.keep_solutions = bool(keep_solutions)
         self.capacity = int(archive_capacity)
-        # elitist archive on the device: arch_dev rows 0..n_arch-1 (+inf after),
-        # with keep_solutions the solution of every row in arch_X_dev; host
-        # copies are made on demand
-        self.arch_dev = torch.full((self.capacity, 3), float("inf"), dtype=torch.float64, device=dev)
-        self.arch_X_dev = torch.empty((self.capacity,) + tuple(X.shape[1:]), dtype=X.dtype, device=dev) \
-            if self.keep_solutions else None
+        # elitist archive on the device (dsm_archive_merge): vectors in
+        # lexicographic order padded with +inf rows (arch_dev, read by the
+        # acceptance kernels), the count on the device, with keep_solutions
+        # each row's solution as its payload; host copies are made on demand
+        row_floats = int(np.prod(X.shape[1:])) if self.keep_solutions else 0
+        self.A = dsm.Archive(self.capacity, m_max=self.S, row_floats=row_floats, device=dev)
+        self.arch_dev = self.A.vec
         self._archive = None
-        self.n_arch = merge_archive_device(self.arch_dev, 0, obj, self.arch_X_dev, self.X)
+        self._merge()
         self.ref = 1.1 * obj.cpu().numpy().max(axis=0)
         self.collect = None  # optional list receiving (features, part_old, part_new) of exact evaluations
         # sampler counter: generation g uses counters 8 g + 1 ... 8 g + 8
@@ -287,7 +220,8 @@ class Optimiser:
         self._donor = None
         self._fi = None
         self.fi_forced = 0    # solutions given a donor, summed over generations
-        self.fi_replaced = 0  # of which replaced by their donor
+        self._n_replaced = torch.zeros(1, dtype=torch.int32, device=dev)  # of which replaced by their donor
+        self._fi_work = None
         self._gen = 0
         self._point_mean = None
         self._shift = None
@@ -312,6 +246,22 @@ class Optimiser:
     @property
     def counter(self):
         return int(self.counter_dev.item())
+
+    def _merge(self):
+        """Merges the population's objective vectors (and solutions) into the archive."""
+        self.A.merge(self.obj, rows=self.X.reshape(self.S, -1) if self.keep_solutions else None)
+
+    @property
+    def n_arch(self):
+        """Rows of the elitist archive (reads the device count)."""
+        if int(self.A.overflow.item()):
+            raise ValueError(f"the archive would exceed its capacity of {self.capacity} rows")
+        return self.A.n
+
+    @property
+    def arch_X_dev(self):
+        """With keep_solutions: the solutions of the archive rows (device, [capacity][2][P][3]), else None."""
+        return None if self.A.rows is None else self.A.rows.view((self.capacity,) + tuple(self.X.shape[1:]))
 
     @property
     def archive(self):
@@ -365,14 +315,14 @@ class Optimiser:
                                    archive=self.arch_dev, accepted=acc, single_objective=self._so)
             if self.sampler == "estimated" and self.schedule == "sdr":
                 sdr = dsm.improvement_ratio(off, cand, acc, mean, chol, cluster=self._assign)
-                m, nis = avs_update(self.mult_cube[:, cubes_d], self.avs_nis_cube[:, cubes_d], sdr, 25 + 24)
+                m, nis = self.mult_cube[:, cubes_d].contiguous(), self.avs_nis_cube[:, cubes_d].contiguous()
+                dsm.avs_update(m, nis, sdr.contiguous(), 25 + 24)
                 self.mult_cube[:, cubes_d] = m
                 self.avs_nis_cube[:, cubes_d] = nis
             elif self.sampler == "estimated":
-                hit = self._hits(acc)
-                m = self.mult_cube[:, cubes_d]
-                self.mult_cube[:, cubes_d] = torch.where(hit, torch.clamp(m / 0.9, max=10.0),
-                                                         torch.clamp(m * 0.9, min=0.05))
+                m = self.mult_cube[:, cubes_d].contiguous()
+                dsm.multiplier_step(acc, m, cluster=self._assign)
+                self.mult_cube[:, cubes_d] = m
             outs.append((None, acc, cand, old, new, flags))
         self.counter_dev += self.n_classes
         return outs
@@ -443,21 +393,11 @@ class Optimiser:
             self._so = of_cluster[self._assign.long()].contiguous()
         return [members[j] for j in range(self.k)]
 
-    def _hits(self, acc):
-        """[k][F] bool: some solution of the cluster had element f accepted."""
-        torch = self.torch
-        a = (acc != 0).to(torch.float32)
-        if self.k == 1:
-            return (a.sum(dim=0) > 0)[None]
-        onehot = (self._assign[:, None] == torch.arange(self.k, device=acc.device)[None, :]).to(torch.float32)
-        return (onehot.T @ a) > 0
-
     def _dominated_by(self):
-        """Number of population members dominating each solution (device)."""
-        o = self.obj
-        le = (o[None, :, :] <= o[:, None, :]).all(-1)
-        lt = (o[None, :, :] < o[:, None, :]).any(-1)
-        return (le & lt).sum(1)
+        """Number of population members dominating each solution (device int32, dsm_select)."""
+        cnt = self.torch.empty(self.S, dtype=self.torch.int32, device=self.X.device)
+        dsm.select(self.obj, 0, dominated_by=cnt)
+        return cnt
 
     def _force(self, pts, cand):
         """Forced improvements: the flagged solutions' candidates become their
@@ -482,36 +422,33 @@ class Optimiser:
 
     def _after_forcing(self, outs):
         """Updates the no-improvement stretches; a forced solution that accepted
-        no change is replaced by its donor (coordinates, objectives, term cache)."""
+        no change is replaced by its donor (coordinates, objectives, term cache)
+        (dsm_mark_improved, dsm_forced_replace)."""
         torch = self.torch
-        improved = torch.zeros(self.S, dtype=torch.bool, device=self.X.device)
+        dev = self.X.device
+        improved = torch.zeros(self.S, dtype=torch.uint8, device=dev)
         for _, acc, *_ in outs:
-            improved |= (acc != 0).any(dim=1)
-        self.nis = torch.where(improved, torch.zeros_like(self.nis), self.nis + 1)
-        if self._donor is None:
-            return
-        fl = torch.from_numpy(self._fi).to(self.X.device)
-        idx = torch.nonzero(fl & ~improved).reshape(-1)
-        if idx.numel():
-            d = self._donor[idx].long()
-            self.X[idx] = self.X[d]
-            self.obj[idx] = self.obj[d]
-            self.cache[idx] = self.cache[d]
-            self.fi_replaced += int(idx.numel())
-        self.nis[fl] = 0
+            dsm.mark_improved(acc, improved)
+        if self._fi_work is None:
+            self._fi_work = torch.empty(dsm.lib().dsm_forced_work_bytes(self.p._h, self.S), dtype=torch.uint8,
+                                        device=dev)
+            self._no_donor = torch.full((self.S,), -1, dtype=torch.int32, device=dev)
+        donor = self._donor if self._donor is not None else self._no_donor
+        self.p.forced_replace(self.X, self.obj, self.cache, donor, improved, self.nis, n_replaced=self._n_replaced,
+                              work=self._fi_work)
         self._donor = None
+
+    @property
+    def fi_replaced(self):
+        """Forced solutions replaced by their donors, summed over generations."""
+        return int(self._n_replaced.item())
 
     def select(self):
         """Indices (int32, device) of the tau fraction of the population with the
         fewest dominating solutions; ties by the smallest sum of objectives
-        normalised to the population's range."""
-        torch = self.torch
-        o = self.obj
-        dominated_by = self._dominated_by().to(torch.float64)
-        lo, hi = o.min(0).values, o.max(0).values
-        nrm = ((o - lo) / torch.clamp(hi - lo, min=1e-300)).sum(1)
+        normalised to the population's range (dsm_select)."""
         n = max(1, int(round(self.tau * self.S)))
-        return torch.argsort(dominated_by * 4.0 + nrm, stable=True)[:n].to(torch.int32).contiguous()
+        return dsm.select(self.obj, n)
 
     def generation(self, surrogate=None, log=None):
         """One generation over all 8 parity classes; returns (exact evaluations, accepted)."""
@@ -544,11 +481,9 @@ class Optimiser:
                 if self.schedule == "sdr":
                     mean, chol = self._dist[c]
                     sdr = dsm.improvement_ratio(self.offs[c], cand, acc, mean, chol, cluster=self._assign)
-                    self.mult[c], self.avs_nis[c] = avs_update(self.mult[c], self.avs_nis[c], sdr, 25 + 6)
+                    dsm.avs_update(self.mult[c], self.avs_nis[c], sdr, 25 + 6)
                     continue
-                hit = self._hits(acc)
-                self.mult[c] = torch.where(hit, torch.clamp(self.mult[c] / 0.9, max=10.0),
-                                           torch.clamp(self.mult[c] * 0.9, min=0.05))
+                dsm.multiplier_step(acc, self.mult[c], cluster=self._assign)
         if self.use_fi:
             self._after_forcing(outs)
         counts = torch.stack([acc.sum(dtype=torch.int64) for _, acc, *_ in outs] +
@@ -557,7 +492,7 @@ class Optimiser:
         masked = iter(counts[len(outs):])
         n_exact = sum(self.S * acc.shape[1] if mask is None else int(next(masked)) for mask, acc, *_ in outs)
         self._gen += 1
-        self.n_arch = merge_archive_device(self.arch_dev, self.n_arch, self.obj, self.arch_X_dev, self.X)
+        self._merge()
         self._archive = None
         return n_exact, n_acc
 

@@ -207,21 +207,22 @@ def test_multiresolution_seeding():
 
 
 def test_device_archive_merge_equals_host():
+    """The device archive (dsm_archive_merge) against the harness's host merge,
+    with duplicates inside a batch and of archived points."""
     rng = np.random.default_rng(12)
-    cap = 4096
-    arch_dev = torch.full((cap, 3), float("inf"), dtype=torch.float64, device=DEV)
+    A = dsm.Archive(capacity=4096, m_max=300)
     host = np.zeros((0, 3))
-    n = 0
     for step in range(6):
         new = rng.integers(0, 40, size=(300, 3)).astype(np.float64)  # many ties and duplicates
         new[:20] = new[20:40]  # exact duplicates within the batch
         if len(host):
             new[40:50] = host[rng.integers(0, len(host), 10)]  # duplicates of archived points
         host = O.merge_archive(host, new)
-        n = O.merge_archive_device(arch_dev, n, _t(new))
-        got = arch_dev[:n].cpu().numpy()
+        A.merge(_t(new))
+        n = A.n
+        got = A.vec[:n].cpu().numpy()
         np.testing.assert_array_equal(got, host)
-        assert torch.all(torch.isinf(arch_dev[n:]))
+        assert torch.all(torch.isinf(A.vec[n:]))
 
 
 def test_accept_tetrahedron_elements():

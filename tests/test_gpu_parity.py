@@ -526,3 +526,92 @@ def test_maximum_image_size():
     np.testing.assert_array_equal(vc.cpu().numpy()[1:2][g_fl == 0], rnv[g_fl == 0])
     assert_objectives_close(new.cpu().numpy()[1:2], rnew, flags=g_fl, what="part_new at 512^3")
     assert_objectives_close(old.cpu().numpy()[1:2], rold, what="part_old at 512^3")
+
+
+def _uneven_level(level, idx):
+    """Oracle and GPU problems, feasible populations, candidates and cached
+    current terms of the uneven problems idx at one pyramid level (level 1
+    starts from a level-0 population handed off to full resolution)."""
+    out = []
+    for i, w in zip(idx, W.uneven(idx, level=level)):
+        rp = oracle_problem(w)
+        if level == 0:
+            X = feasible_population(w, rp)
+        else:
+            wh = W.uneven([i], level=0)[0]
+            X = W.upsample_population(feasible_population(wh, oracle_problem(wh)))
+        off, pts = w.fos()
+        cand = w.candidates(X, off, pts)
+        gp = _gpu_problem(w, len(X))
+        Xd = _t(X)
+        cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+        gp.eval_full(Xd, tet_terms=cache)
+        job = dict(problem=gp, X=Xd, fos_off=_t(off), fos_pts=_t(pts), cand=_t(cand), tet_terms_in=cache)
+        out.append((w, rp, X, off, pts, cand, job))
+    return out
+
+
+def test_uneven_batch_graph_both_levels():
+    """All 12 uneven problems at both pyramid levels as two stored batch
+    configurations, enqueued by dsm_batch_run and captured together in one HIP
+    graph: every replay (with eager work in between) equals the eager run bit
+    for bit, the eager run equals one launch per problem, and every problem is
+    checked against the oracle on sampled pairs."""
+    idx = list(range(12))
+    levels = []
+    for level in (0, 1):
+        probs = _uneven_level(level, idx)
+        batch = dsm.Batch(max_jobs=len(probs))
+        outs = batch.set_jobs([p[-1] for p in probs])
+        levels.append((probs, batch, outs))
+        _say(f"uneven level {level}: {[p[0].name for p in probs]}")
+    single = [[p[-1]["problem"].eval_partial(p[-1]["X"], p[-1]["fos_off"], p[-1]["fos_pts"], p[-1]["cand"],
+                                             tet_terms_in=p[-1]["tet_terms_in"], voxel_count=True) for p in probs]
+              for probs, _, _ in levels]
+    for _, batch, _ in levels:
+        batch.run()
+    torch.cuda.synchronize()
+    eager = [[[t.cpu().numpy().copy() for t in o] for o in outs] for _, _, outs in levels]
+    for lv in range(2):
+        for e, sg in zip(eager[lv], single[lv]):
+            for a, b in zip(e, sg):
+                np.testing.assert_array_equal(a, b.cpu().numpy())
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    _say("capturing both levels")
+    with torch.cuda.graph(graph, stream=stream):
+        for _, batch, _ in levels:
+            batch.run()
+    torch.cuda.synchronize()
+    w0, _, X0, off0, pts0, cand0, job0 = levels[1][0][0]
+    for rep in range(3):
+        for _, _, outs in levels:
+            for o in outs:
+                o[0].fill_(float("nan"))
+                o[1].fill_(float("nan"))
+                o[2].fill_(-1)
+                o[3].fill_(-1)
+        graph.replay()
+        # eager work of the program between replays
+        job0["problem"].eval_partial(job0["X"], job0["fos_off"], job0["fos_pts"], job0["cand"],
+                                     tet_terms_in=job0["tet_terms_in"])
+        torch.cuda.synchronize()
+        for lv, (_, _, outs) in enumerate(levels):
+            for e, o in zip(eager[lv], outs):
+                for a, b in zip(e, o):
+                    np.testing.assert_array_equal(a, b.cpu().numpy(), err_msg=f"replay {rep} level {lv}")
+        _say(f"replay {rep} equal to eager")
+    rng = np.random.default_rng(17)
+    for lv, (probs, _, _) in enumerate(levels):
+        for k, (w, rp, X, off, pts, cand, _) in enumerate(probs):
+            s = int(rng.integers(len(X)))
+            elems = np.sort(rng.choice(w.P, 4, replace=False)).astype(np.int32)
+            rold, rnew, rfl, rnv = rp.eval_partial(X[s:s + 1], np.arange(5, dtype=np.int32), elems,
+                                                    cand[s:s + 1, elems])
+            o = eager[lv][k]
+            g_fl = o[2][s, elems][None].astype(np.uint32)
+            np.testing.assert_array_equal(g_fl, rfl)
+            np.testing.assert_array_equal(o[3][s, elems][None][g_fl == 0], rnv[g_fl == 0])
+            assert_objectives_close(o[1][s, elems][None], rnew, flags=g_fl, what=f"level {lv} {w.name} part_new")
+            assert_objectives_close(o[0][s, elems][None], rold, what=f"level {lv} {w.name} part_old")
