@@ -166,6 +166,30 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
                             double* part_new, uint32_t* flags, double* tet_terms_new, uint32_t* voxel_count,
                             void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * partial evaluation as dsm_eval_partial, with identical results, whose
+ * workspace (affected sets, element order, per-tetrahedron swept sums,
+ * per-chunk flags and voxel counts) lives in a fixed array of
+ * DSM_SCRATCH_BYTES per device, held from the first call on a device until
+ * the process ends, instead of the problem's create-time workspace; S and F
+ * are therefore not bounded by max_solutions / max_fos.  The call allocates
+ * nothing and only enqueues on `stream`.  Every call on one device shares that
+ * device's array and leaves its contents behind (nothing in it needs to start
+ * at zero): calls that overlap on one device race, across problems, streams
+ * and threads alike, so serialise them (one stream, or events).  The problem
+ * must live on the current device.  Workspace bytes: 256-byte aligned regions
+ * of 4 F maxA + 8 F + 8 S F nver maxA + 8 S F ceil(maxA / 8), with nver = 1
+ * if tet_terms_in is given, else 2, and maxA = dsm_problem_info.max_affected.
+ * Errors: DSM_ERR_CAPACITY if that exceeds DSM_SCRATCH_BYTES (split the
+ * population into calls of fewer solutions); DSM_ERR_ARG for null pointers or
+ * a problem of another device; DSM_ERR_DEVICE. */
+#define DSM_SCRATCH_BYTES (64u << 20)
+dsm_status dsm_eval_partial_noalloc(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                                    const int32_t* fos_pts, const float* cand, const double* tet_terms_in,
+                                    double* part_old, double* part_new, uint32_t* flags, double* tet_terms_new,
+                                    uint32_t* voxel_count, void* stream);
+
 /* dsm_eval_partial restricted to the (solution, element) pairs whose entry in
  * mask dev [S][F] (uint8) is non-zero; the other pairs cost a workgroup launch
  * only, get flags = DSM_FLAG_SKIPPED, zero partial sums and no term writes.

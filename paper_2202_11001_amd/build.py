@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsm.so")
-SOURCES = ["api.cpp", "topology.cpp", "kernels.hip", "surrogate.hip", "driver.hip", "archive.hip"]
+SOURCES = ["api.cpp", "topology.cpp", "kernels.hip", "surrogate.hip", "driver.hip", "scratch.hip", "archive.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.

@@ -96,6 +96,14 @@ bool on_lattice(float x, int D, double& u) {
 
 }  // namespace
 
+namespace dsm {
+dsm_status set_error(dsm_status st, const char* msg) {
+  g_err = msg ? msg : "";
+  return st;
+}
+void clear_error() { g_err.clear(); }
+}  // namespace dsm
+
 extern "C" {
 
 const char* dsm_status_string(dsm_status s) {

@@ -134,6 +134,10 @@ hipError_t launch_pack_bordered(const float* raw, float* out, int Dx, int Dy, in
                                 hipStream_t stream);
 size_t eval_lds_bytes(int maxA, int nver);
 
+// Error string of the calling thread, read by dsm_last_error (api.cpp).
+dsm_status set_error(dsm_status st, const char* msg);
+void clear_error();
+
 }  // namespace dsm
 
 // The problem object behind the opaque ABI handle.

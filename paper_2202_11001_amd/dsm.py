@@ -76,6 +76,7 @@ def lib():
             "dsm_fold_check": ([V, I, V, V, V, V], I),
             "dsm_eval_full": ([V, I, V, V, V, V, V], I),
             "dsm_eval_partial": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V], I),
+            "dsm_eval_partial_noalloc": ([V, I, V, I, V, V, V, V, V, V, V, V, V, V], I),
             "dsm_rasterize_owner": ([V, V, V, V, V], I),
             "dsm_transform": ([V, I, V, V, V, V], I),
             "dsm_problem_timing": ([V, I], I),
@@ -450,6 +451,24 @@ class Problem:
             _check(lib().dsm_eval_partial_masked(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
                                                  _dptr(mask), _dptr(tet_terms_in), _dptr(old), _dptr(new),
                                                  _dptr(flags), _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
+        return out
+
+    def eval_partial_noalloc(self, X, fos_off, fos_pts, cand, tet_terms_in=None, tet_terms_new=None,
+                             voxel_count=False, out=None, stream=None):
+        """eval_partial through dsm_eval_partial_noalloc (workspace in the
+        library's fixed per-device array; pass ``out`` to allocate nothing here
+        either)."""
+        torch = _torch()
+        S, F = X.shape[0], fos_off.shape[0] - 1
+        if out is None:
+            out = (torch.empty((S, F, 3), dtype=torch.float64, device=X.device),
+                   torch.empty((S, F, 3), dtype=torch.float64, device=X.device),
+                   torch.empty((S, F), dtype=torch.int32, device=X.device),
+                   torch.empty((S, F), dtype=torch.int32, device=X.device) if voxel_count else None)
+        old, new, flags, vc = out
+        _check(lib().dsm_eval_partial_noalloc(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                              _dptr(tet_terms_in), _dptr(old), _dptr(new), _dptr(flags),
+                                              _dptr(tet_terms_new), _dptr(vc), _stream(stream)))
         return out
 
     def sample_candidates(self, X, pts, K, sigma, seed, counter, out=None, stream=None, counter_dev=None):
