@@ -33,16 +33,30 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, X, off, pts, cand, budget_s=20.0):
+def cpu_model():
+    """The host CPU's model name."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, X, off, pts, cand, budget_s=20.0, budget_1core_s=8.0):
     """The FP64 oracle on a bounded sample: all FOS elements of the first
-    solutions, until about budget_s of CPU time; partial evaluations/s."""
+    solutions, until about budget_s of CPU time, on every host thread it
+    uses; then a smaller sample of solution 0 on one thread.  Partial
+    evaluations/s (the oracle has no term cache here: zero cached terms make
+    it time the candidate side only)."""
     from oracle import ref
     rp = ref.Problem(w.moving, w.fixed, w.mesh, w.spacing, w.tau, guid_moving=w.guid_moving,
                      corr_moving=w.corr_moving, guid_fixed=w.guid_fixed, corr_fixed=w.corr_fixed)
     F = len(off) - 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # probe: 64 elements of solution 0 (current terms recomputed by the oracle too: it has no cache,
-    # so time the candidate side only by passing zero cached terms)
+    threads = ref.lib().ref_max_threads()
     zeros = np.zeros((1, rp.T, 3))
     nprobe = min(F, 64)
     t0 = time.perf_counter()
@@ -54,9 +68,20 @@ def cpu_baseline(w, X, off, pts, cand, budget_s=20.0):
     t0 = time.perf_counter()
     rp.eval_partial(X[:ns], off, pts, cand[:ns], tet_terms=np.zeros((ns, rp.T, 3)))
     dt = time.perf_counter() - t0
-    return {"value": ns * F / dt, "unit": "partial_evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{ns} solution(s) x {F} single-point FOS elements of the same workload, FP64, "
-                      f"{dt:.1f} s wall"}
+    res = {"value": ns * F / dt, "unit": "partial_evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{ns} solution(s) x {F} single-point FOS elements of the same workload, FP64, "
+                     f"{dt:.1f} s wall", "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    prev = ref.set_threads(1)
+    try:
+        n1 = int(max(1, min(F, budget_1core_s / max(per * threads, 1e-9))))
+        t0 = time.perf_counter()
+        rp.eval_partial(X[:1], off[:n1 + 1], pts[:off[n1]], cand[:1, :off[n1]], tet_terms=zeros)
+        dt1 = time.perf_counter() - t0
+    finally:
+        ref.set_threads(prev)
+    res["one_core"] = {"value": n1 / dt1, "unit": "partial_evals/s", "cores": 1,
+                       "sample": f"{n1} single-point FOS elements of solution 0, FP64, {dt1:.1f} s wall"}
+    return res
 
 
 def kernel_source_hash():
@@ -219,33 +244,115 @@ def surrogate_report(gp, opt, sur, K=4, seed=4242):
     return res
 
 
-def surrogate_run(gp, X, G, train_generations, name):
-    """Plain run of G generations vs a run whose first train_generations
-    generations are plain (collecting exact deltas), followed by surrogate
-    training and screened generations; hypervolume of the elitist archive
-    against a reference point fixed by the initial population.  Generations
-    replay a captured HIP graph (the collecting ones run eagerly); the clock
-    counts optimisation and training, not the hypervolume monitoring."""
+def surrogate_oracle_report(w, gp, opt, sur, n_sol=16, n_pts=64, K=4, seed=4343):
+    """Held-out quality judged against the FP64 oracle: K fresh candidates for
+    n_pts points of one parity class in n_sol solutions of the final screened
+    population (n_sol * n_pts * K candidates); their exact deltas come from the
+    oracle (which recomputes the current terms itself), the predictions from
+    the surrogate.  Also reports how far the GPU's exact deltas are from the
+    oracle's on the same candidates."""
+    import torch
+    from oracle import ref
+    rp = ref.Problem(w.moving, w.fixed, w.mesh, w.spacing, w.tau, guid_moving=w.guid_moving,
+                     corr_moving=w.corr_moving, guid_fixed=w.guid_fixed, corr_fixed=w.corr_fixed)
+    rng = np.random.default_rng(seed)
+    dev = opt.X.device
+    pts_all = opt.classes[0].cpu().numpy()
+    pts = np.sort(rng.choice(pts_all, size=min(n_pts, len(pts_all)), replace=False)).astype(np.int32)
+    sols = np.sort(rng.choice(opt.S, size=n_sol, replace=False))
+    Xd = opt.X[torch.from_numpy(sols).to(dev)].contiguous()
+    ptsd = torch.from_numpy(pts).to(dev)
+    F = len(pts)
+    off = np.arange(F + 1, dtype=np.int32)
+    offd = torch.from_numpy(off).to(dev)
+    candK = gp.sample_candidates(Xd, ptsd, K, opt.sigma, seed, 1)          # [n_sol][F][K][2][3]
+    _, _, pred, _ = sur.screen(gp, Xd, ptsd, candK)
+    gpu = np.zeros((n_sol, F, K, 3))
+    for k in range(K):
+        o, n, fl, _ = gp.eval_partial(Xd, offd, ptsd, candK[:, :, k].contiguous())
+        gpu[:, :, k] = (n - o).cpu().numpy()
+    Xh, ch, predh = Xd.cpu().numpy(), candK.cpu().numpy(), pred.cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    true = np.zeros((n_sol, F, K, 3))
+    ok = np.ones((n_sol, F), dtype=bool)
+    for k in range(K):
+        rold, rnew, rfl, _ = rp.eval_partial(Xh, off, pts, np.ascontiguousarray(ch[:, :, k]))
+        true[:, :, k] = rnew - rold
+        ok &= rfl == 0
+    t_oracle = time.perf_counter() - t0
+    t = true[ok].reshape(-1, 3)
+    p = predh[ok].reshape(-1, 3)
+    g = gpu[ok].reshape(-1, 3)
+    res = {"candidates": int(t.shape[0]), "oracle_seconds": t_oracle, "rmse": [], "r2": [],
+           "sign_agreement_nonzero": [], "nonzero_fraction": [],
+           "gpu_vs_oracle_max_abs": [float(np.abs(g[:, c] - t[:, c]).max()) for c in range(3)]}
+    for c in range(3):
+        err = p[:, c] - t[:, c]
+        var = float(np.var(t[:, c]))
+        nz = t[:, c] != 0
+        res["rmse"].append(float(np.sqrt(np.mean(err ** 2))))
+        res["r2"].append(float(1 - np.mean(err ** 2) / var) if var > 0 else None)
+        res["sign_agreement_nonzero"].append(float(np.mean(np.sign(p[nz, c]) == np.sign(t[nz, c]))) if nz.any() else None)
+        res["nonzero_fraction"].append(float(nz.mean()))
+    return res
+
+
+def surrogate_run(gp, X, G, train_generations, name, w, seeds=(5, 6, 7)):
+    """For each seed: a plain run of G generations vs a run whose first
+    train_generations generations are plain (collecting exact deltas),
+    followed by surrogate training and screened generations until 99 % of the
+    plain run's final hypervolume; hypervolume of the elitist archive against a
+    reference point fixed by the initial population.  Generations replay a
+    captured HIP graph (the collecting ones run eagerly); the clock counts
+    optimisation and training, not the hypervolume monitoring.  Reports every
+    seed and the medians; the first seed's surrogate is scored on held-out
+    candidates against the GPU's exact deltas and against the FP64 oracle."""
     import torch
     from paper_2202_11001_amd import optimizer as O
     Xd = torch.from_numpy(X).to("cuda:0")
-    log(f"plain run: {G} generations")
-    lp, op, _ = O.run(gp, Xd, G, sigma=1.0, seed=5, log_every=10, graph=True)
-    target = 0.99 * lp.hypervolume[-1]
-    log(f"screened run: {train_generations} plain generations, then screened, until hv >= {target:.6g} or {G}")
-    ls, os_, sur = O.run(gp, Xd, G, sigma=1.0, seed=5, train_generations=train_generations, target_hv=target,
-                         log_every=10, graph=True)
-    reach = next((i for i, h in enumerate(ls.hypervolume) if h >= target), None)
+    runs = []
+    first = None
+    for seed in seeds:
+        log(f"seed {seed}: plain run, {G} generations")
+        lp, op, _ = O.run(gp, Xd, G, sigma=1.0, seed=seed, log_every=10, graph=True)
+        target = 0.99 * lp.hypervolume[-1]
+        plain_reach = next(i for i, h in enumerate(lp.hypervolume) if h >= target)
+        log(f"seed {seed}: screened run, {train_generations} plain generations, then screened, "
+            f"until hv >= {target:.6g} or {G}")
+        ls, os_, sur = O.run(gp, Xd, G, sigma=1.0, seed=seed, train_generations=train_generations, target_hv=target,
+                             log_every=10, graph=True)
+        reach = next((i for i, h in enumerate(ls.hypervolume) if h >= target), None)
+        r = {"seed": seed, "target_hv": target,
+             "plain": {"final_hv": lp.hypervolume[-1], "seconds": lp.seconds[-1],
+                       "generations_to_target": plain_reach + 1, "seconds_to_target": lp.seconds[plain_reach],
+                       "exact_to_target": int(sum(lp.exact_evals[:plain_reach + 1]))},
+             "screened": {"final_hv": ls.hypervolume[-1], "seconds": ls.seconds[-1],
+                          "generations_to_target": None if reach is None else reach + 1,
+                          "seconds_to_target": None if reach is None else ls.seconds[reach],
+                          "exact_to_target": None if reach is None else int(sum(ls.exact_evals[:reach + 1])),
+                          "hv": ls.hypervolume, "t": ls.seconds, "exact": ls.exact_evals, "accepted": ls.accepted}}
+        if reach is not None:
+            r["speedup_to_target"] = lp.seconds[-1] / ls.seconds[reach]
+            r["speedup_vs_plain_reaching_target"] = lp.seconds[plain_reach] / ls.seconds[reach]
+        log(f"seed {seed}: plain {lp.seconds[-1]:.1f} s (target at {lp.seconds[plain_reach]:.1f} s), "
+            f"screened {r['screened']['seconds_to_target']} s")
+        runs.append(r)
+        if first is None:
+            first = (os_, sur)
+    os_, sur = first
     quality = surrogate_report(gp, os_, sur)
-    log(f"surrogate held-out quality: {quality}")
-    res = {"workload": name, "generations": G, "train_generations": train_generations,
-           "plain": {"final_hv": lp.hypervolume[-1], "seconds": lp.seconds[-1],
-                     "hv": lp.hypervolume, "t": lp.seconds, "exact": lp.exact_evals, "accepted": lp.accepted},
-           "screened": {"final_hv": ls.hypervolume[-1], "seconds": ls.seconds[-1],
-                        "reached_generation": None if reach is None else reach + 1,
-                        "seconds_to_target": None if reach is None else ls.seconds[reach],
-                        "hv": ls.hypervolume, "t": ls.seconds, "exact": ls.exact_evals, "accepted": ls.accepted},
-           "target_hv": target, "surrogate_quality": quality}
+    log(f"surrogate held-out quality (GPU exact deltas): {quality}")
+    oracle_quality = surrogate_oracle_report(w, gp, os_, sur)
+    log(f"surrogate held-out quality (FP64 oracle deltas): {oracle_quality}")
+    med = lambda xs: float(np.median([x for x in xs if x is not None])) if any(x is not None for x in xs) else None
+    res = {"workload": name, "generations": G, "train_generations": train_generations, "seeds": list(seeds),
+           "median": {"plain_seconds": med([r["plain"]["seconds"] for r in runs]),
+                      "plain_seconds_to_target": med([r["plain"]["seconds_to_target"] for r in runs]),
+                      "screened_seconds_to_target": med([r["screened"]["seconds_to_target"] for r in runs]),
+                      "speedup_to_target": med([r.get("speedup_to_target") for r in runs]),
+                      "speedup_vs_plain_reaching_target": med([r.get("speedup_vs_plain_reaching_target")
+                                                               for r in runs])},
+           "runs": runs, "surrogate_quality": quality, "surrogate_quality_oracle": oracle_quality}
     print(json.dumps(res), flush=True)
 
 
@@ -435,7 +542,10 @@ def uneven_batch(steps=3, warmup=1):
     pyramid level: the 12 problems of workloads.UNEVEN_PROBLEMS at the 2x
     box-averaged level and at full resolution (population handed off by
     x -> 2x + 0.5); per level, all single-point FOS elements of every
-    solution.  Each problem's image row pitch is autotuned first."""
+    solution.  Each problem's image row pitch is autotuned first.  Timed three
+    ways: one dsm_eval_partial_batch call per level (job table uploaded per
+    call), one dsm_batch_run per level (stored configuration), and one HIP
+    graph holding both levels' runs (a whole two-level generation)."""
     import torch
     from paper_2202_11001_amd import dsm
     from paper_2202_11001_amd import workloads as W
@@ -443,10 +553,25 @@ def uneven_batch(steps=3, warmup=1):
     n = len(W.UNEVEN_PROBLEMS)
     res = {"problems": n, "levels": []}
     handoff = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+
+    keep = []
     for level in (0, 1):
         t0 = time.perf_counter()
         ws = W.uneven(level=level)
-        jobs, probs, samples = [], [], 0
+        jobs = []
         for i, w in enumerate(ws):
             gp = dsm.Problem.from_workload(w)
 
@@ -463,7 +588,6 @@ def uneven_batch(steps=3, warmup=1):
             cache = torch.empty((X.shape[0], gp.T, 3), dtype=torch.float64, device=dev)
             gp.eval_full(Xd, tet_terms=cache)
             gp.autotune_pitch(Xd, offd, ptsd, cd, tet_terms_in=cache)
-            probs.append(gp)
             jobs.append(dict(problem=gp, X=Xd, fos_off=offd, fos_pts=ptsd, cand=cd, tet_terms_in=cache))
         log(f"uneven level {level}: {n} problems set up in {time.perf_counter() - t0:.1f} s")
         batch = dsm.Batch(max_jobs=n)
@@ -472,27 +596,33 @@ def uneven_batch(steps=3, warmup=1):
         samples = int(sum(int(o[3].to(torch.int64).sum().item()) for o in outs))
         evals = sum(j["X"].shape[0] * (j["fos_off"].shape[0] - 1) for j in jobs)
         flagged = int(sum(int((o[2] != 0).sum().item()) for o in outs))
-        for _ in range(warmup):
-            batch.eval_partial(jobs)
-        torch.cuda.synchronize()
-        stream = torch.cuda.current_stream()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-        ev[0].record(stream)
-        for k in range(steps):
-            batch.eval_partial(jobs)
-            ev[k + 1].record(stream)
-        torch.cuda.synchronize()
-        ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+        ms = timed(lambda: batch.eval_partial(jobs))
+        stored = dsm.Batch(max_jobs=n)
+        stored.set_jobs(jobs)
+        ms_run = timed(stored.run)
         log(f"uneven level {level}: {evals} partial evaluations, {samples} samples, {flagged} flagged, {ms:.2f} ms "
-            f"per fused launch")
+            f"per fused launch ({ms_run:.2f} ms from the stored configuration)")
         res["levels"].append({"level": level, "partial_evals": evals, "voxel_samples": samples, "ms": ms,
+                              "ms_stored": ms_run,
                               "partial_evals_per_s": evals / (ms / 1e3), "voxel_samples_per_s": samples / (ms / 1e3),
-                              "algorithmic_GBps": samples * BYTES_PER_SAMPLE / (ms / 1e3) / 1e9})
-        del batch, jobs, probs
+                              "algorithmic_GBps": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9,
+                              "roofline_frac": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9 / HBM_PEAK_GBS})
+        keep.append((batch, stored, jobs))
+    # both levels in one captured graph
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _, stored, _ in keep:
+            stored.run()
+    torch.cuda.synchronize()
+    ms_graph = timed(graph.replay)
+    log(f"uneven: both levels replayed from one HIP graph in {ms_graph:.2f} ms")
     tot_e = sum(l["partial_evals"] for l in res["levels"])
     tot_ms = sum(l["ms"] for l in res["levels"])
     res["total"] = {"partial_evals": tot_e, "voxel_samples": sum(l["voxel_samples"] for l in res["levels"]),
-                    "ms": tot_ms, "partial_evals_per_s": tot_e / (tot_ms / 1e3)}
+                    "ms": tot_ms, "ms_graph_both_levels": ms_graph, "partial_evals_per_s": tot_e / (tot_ms / 1e3),
+                    "partial_evals_per_s_graph": tot_e / (ms_graph / 1e3)}
     print(json.dumps(res), flush=True)
 
 
@@ -676,7 +806,7 @@ def main():
         sampler_run(gp, X, args.sampler_run, w.name, w)
         return
     if args.surrogate_run:
-        surrogate_run(gp, X, args.surrogate_run, args.train_generations, w.name)
+        surrogate_run(gp, X, args.surrogate_run, args.train_generations, w.name, w)
         return
     off, pts = w.fos()
     F = len(off) - 1

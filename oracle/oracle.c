@@ -29,6 +29,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define LAT 128.0
 
@@ -947,4 +950,21 @@ void ref_literal_fold_check(const ref_problem *p, int S, const float *X, int *vi
           }
       violations[s * 2 + g] = bad;
     }
+}
+
+/* threads the oracle's parallel loops use (timing legs); 0 leaves the default */
+void ref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int ref_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

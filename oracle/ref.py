@@ -75,6 +75,10 @@ def lib():
         L.ref_transform.argtypes = [P, C.c_int, P, P, P]
         L.ref_literal_fold_check.restype = None
         L.ref_literal_fold_check.argtypes = [P, C.c_int, P, P]
+        L.ref_set_threads.restype = None
+        L.ref_set_threads.argtypes = [C.c_int]
+        L.ref_max_threads.restype = C.c_int
+        L.ref_max_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -98,6 +102,14 @@ def refine(mesh_coarse, Xc):
 def orient3d(a, b, c, d) -> float:
     arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, c, d)]
     return lib().ref_orient3d(*[_p(x) for x in arrs])
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (OpenMP); returns the previous maximum."""
+    L = lib()
+    prev = L.ref_max_threads()
+    L.ref_set_threads(int(n))
+    return prev
 
 
 class Problem:
