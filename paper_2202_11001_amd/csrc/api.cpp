@@ -578,7 +578,7 @@ dsm_status batch_tables(const dsm_batch* b, int n_jobs, const dsm_partial_job* j
     a.cflags = p->d_cflags;
     a.ccount = p->d_ccount;
     off[j + 1] = off[j] + (q.S * q.F * a.nchunk + 7) / 8;
-    foff[j + 1] = foff[j] + q.S * q.F;
+    foff[j + 1] = foff[j] + (q.S * q.F + kFinishPairs - 1) / kFinishPairs;
     lds = std::max(lds, eval_lds_bytes(kMaxChunk, a.nver));
   }
   return DSM_OK;

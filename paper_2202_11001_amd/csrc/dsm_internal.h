@@ -19,6 +19,10 @@ constexpr int kClusterMax = 16, kClusterSelMax = 1024, kClusterRounds = 50;
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
 constexpr int kPartChunk = 8;     // affected tetrahedra per workgroup in partial evaluation
 constexpr int kMaxChunk = kFullChunk > kPartChunk ? kFullChunk : kPartChunk;
+// The finishing kernel gives each (group, solution) pair kFinishLanes lanes
+// (one per affected tetrahedron at a time), kFinishPairs pairs per 64-lane wave.
+constexpr int kFinishLanes = 16;
+constexpr int kFinishPairs = 64 / kFinishLanes;
 
 // Sampled images are stored z-pair interleaved with a replicated one-voxel
 // border: element (x', y', z') of the (Dx+2) x (Dy+2) x (Dz+1) element grid
@@ -121,7 +125,8 @@ constexpr int kOrderMax = 4096;
 hipError_t launch_order(int G, const int* aff_cnt, int* order, hipStream_t stream);
 // wg_off_dev [2][n_jobs + 1]: the jobs' per-XCD slot offsets in the sweep (a
 // job of n workgroups takes ceil(n / 8) slots on each XCD; per_xcd slots in
-// all), then their workgroup offsets in the finishing kernel (total_finish)
+// all), then their workgroup offsets in the finishing kernel (a job of n
+// pairs takes ceil(n / kFinishPairs) workgroups; total_finish in all)
 hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int per_xcd, int total_finish,
                              size_t lds, hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);

@@ -138,6 +138,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over the 16 lanes of a lane group, in a fixed butterfly order (every
+// lane of the group ends with the same sum).
+__device__ __forceinline__ double group16_sum(double v) {
+  for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);
+  return v;
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
   for (int off = 1; off < 64; off <<= 1) {
     const int o = __shfl_up(v, off, 64);
@@ -923,11 +930,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
 
 // Adds the deformation and guidance terms (FP64, per tetrahedron) to the swept
 // dissimilarity, writes per-tetrahedron terms, and in partial mode the
-// normalised sums over each group in ascending tetrahedron order.
-__device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
+// normalised sums over each group in ascending tetrahedron order.  One group
+// of kFinishLanes lanes per (group, solution) pair, one lane per affected
+// tetrahedron (kFinishLanes at a time): a star averages 16 tetrahedra, so
+// 16-lane groups keep most FP64 lanes busy.
+__device__ __forceinline__ void finish_body(const EvalArgs& a, int logical, int lane) {
   const double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
-  const int lane = threadIdx.x;
   const int g = logical / a.S, s = logical - g * a.S;
   const int na = group_size(a, g);
   const size_t oi = (size_t)s * a.G + g;
@@ -952,10 +961,10 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
     if (a.vcount) a.vcount[oi] = cnt;
   }
   // one lane per affected tetrahedron; the per-tetrahedron terms are summed
-  // over the wave in a fixed butterfly order (every lane ends with the same sum)
+  // over the lane group in a fixed butterfly order
   const double* sims = simws + oi * a.nver * a.maxA;
   double accn[3] = {0, 0, 0}, acco[3] = {0, 0, 0};
-  for (int base = 0; base < na; base += 64) {
+  for (int base = 0; base < na; base += kFinishLanes) {
     const int i = base + lane;
     double tn[3] = {0, 0, 0}, to[3] = {0, 0, 0};
     for (int v = 0; v < a.nver; ++v) {
@@ -995,8 +1004,8 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
         for (int c = 0; c < 3; ++c) to[c] = src[c];
       }
       for (int c = 0; c < 3; ++c) {
-        accn[c] += wave_sum(tn[c]);
-        acco[c] += wave_sum(to[c]);
+        accn[c] += group16_sum(tn[c]);
+        acco[c] += group16_sum(to[c]);
       }
     }
   }
@@ -1011,15 +1020,21 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical) {
 
 // FP64 geometry per lane: the 3-wave target (at most 168 VGPRs, a few 8-byte
 // spills) ran the finish kernels 20 % faster than 2 waves without spills.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_finish(EvalArgs a) {
-  finish_body(a, blockIdx.x);
+// Each 64-lane workgroup takes kFinishPairs consecutive pairs.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_finish(EvalArgs a, int n_pairs) {
+  const int pair = blockIdx.x * kFinishPairs + (threadIdx.x / kFinishLanes);
+  if (pair < n_pairs) finish_body(a, pair, threadIdx.x % kFinishLanes);
 }
 
+// Several problems: wg_off [n_jobs + 1] are the jobs' first workgroups, a job
+// of n pairs taking ceil(n / kFinishPairs) of them.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_finish_batch(const EvalArgs* __restrict__ jobs, const int* __restrict__ wg_off,
                                                      int n_jobs) {
   int j = 0;
   while (j + 1 < n_jobs && wg_off[j + 1] <= (int)blockIdx.x) ++j;
-  finish_body(jobs[j], (int)blockIdx.x - wg_off[j]);
+  const EvalArgs& a = jobs[j];
+  const int pair = ((int)blockIdx.x - wg_off[j]) * kFinishPairs + (int)(threadIdx.x / kFinishLanes);
+  if (pair < a.S * a.G) finish_body(a, pair, threadIdx.x % kFinishLanes);
 }
 
 // ------------------------------------------------------------ small kernels
@@ -1454,7 +1469,7 @@ hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end) (void)hipEventRecord(ev_end, stream);
-  k_finish<<<(unsigned)nwg, 64, 0, stream>>>(a);
+  k_finish<<<(unsigned)((nwg + kFinishPairs - 1) / kFinishPairs), 64, 0, stream>>>(a, (int)nwg);
   return hipGetLastError();
 }
 
