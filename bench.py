@@ -588,6 +588,7 @@ def uneven_batch(steps=3, warmup=1):
             cache = torch.empty((X.shape[0], gp.T, 3), dtype=torch.float64, device=dev)
             gp.eval_full(Xd, tet_terms=cache)
             gp.autotune_pitch(Xd, offd, ptsd, cd, tet_terms_in=cache)
+            gp.autotune_chunk(Xd, offd, ptsd, cd, tet_terms_in=cache)
             jobs.append(dict(problem=gp, X=Xd, fos_off=offd, fos_pts=ptsd, cand=cd, tet_terms_in=cache))
         log(f"uneven level {level}: {n} problems set up in {time.perf_counter() - t0:.1f} s")
         batch = dsm.Batch(max_jobs=n)
@@ -606,7 +607,9 @@ def uneven_batch(steps=3, warmup=1):
                               "ms_stored": ms_run,
                               "partial_evals_per_s": evals / (ms / 1e3), "voxel_samples_per_s": samples / (ms / 1e3),
                               "algorithmic_GBps": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9,
-                              "roofline_frac": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9 / HBM_PEAK_GBS})
+                              "roofline_frac": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9 / HBM_PEAK_GBS,
+                              "part_chunks": [j["problem"].part_chunk for j in jobs],
+                              "row_pitches": [j["problem"].pitch for j in jobs]})
         keep.append((batch, stored, jobs))
     # both levels in one captured graph
     side = torch.cuda.Stream()
@@ -739,7 +742,9 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: 2 steps, no warmup, no CPU leg")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
     ap.add_argument("--no-screen", action="store_true", help="skip the surrogate-screened step")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch and chunk")
+    ap.add_argument("--part-chunk", type=int, default=0,
+                    help="affected tetrahedra per workgroup (4..8) instead of autotuning it")
     ap.add_argument("--multires", type=int, nargs=2, default=None, metavar=("G1", "G2"),
                     help="multi-resolution run: G1 coarse then G2 fine generations (reported separately)")
     ap.add_argument("--tet-fos", action="store_true",
@@ -818,6 +823,11 @@ def main():
     if not args.no_autotune and not args.profile:
         best, table = gp.autotune_pitch(Xd, offd, ptsd, candd, tet_terms_in=cache)
         log(f"image row pitch autotune (ms per step): {table} -> {best}")
+        if not args.part_chunk:
+            best, table = gp.autotune_chunk(Xd, offd, ptsd, candd, tet_terms_in=cache)
+            log(f"affected tetrahedra per workgroup autotune (ms per step): {table} -> {best}")
+    if args.part_chunk:
+        gp.set_part_chunk(args.part_chunk)
     out = (torch.empty((S, F, 3), dtype=torch.float64, device=dev), torch.empty((S, F, 3), dtype=torch.float64, device=dev),
            torch.empty((S, F), dtype=torch.int32, device=dev), torch.empty((S, F), dtype=torch.int32, device=dev))
     gp.eval_partial(Xd, offd, ptsd, candd, tet_terms_in=cache, out=out)
@@ -873,6 +883,7 @@ def main():
         "config": {"workload": w.name + f", meshes {w.mesh}, population {S}, {F} single-point FOS elements per step",
                    "partial_evals_per_step": S * F, "voxel_samples_per_step": samples},
         "voxel_samples_per_s": samples_per_s,
+        "tuning": {"image_row_pitch": gp.pitch, "part_chunk": gp.part_chunk},
         # "bound" names the roofline the fraction is taken against (HBM, on
         # algorithmic bytes); "limiter" is what the kernel's counters show
         # limits it: the vector-memory (texture) address and data path, with

@@ -269,6 +269,31 @@ dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t
                               const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_pitch,
                               const int32_t* pitches, float* ms_out, int32_t* best);
 
+/* Work split of the partial evaluation.  Each workgroup of a partial
+ * evaluation sweeps one chunk of `chunk` affected tetrahedra of one (element,
+ * solution) pair, both directions; the chunk changes no voxel set, flag or
+ * count, only the speed (smaller chunks give more, shorter workgroups) and
+ * the rounding of the dissimilarity: the waves' per-lane compensated FP32
+ * sums follow the work split (relative differences of order 1e-9).
+ * dsm_set_part_chunk sets it for later partial evaluations of p (default 8);
+ * it neither allocates nor synchronises, but a stored batch configuration
+ * keeps the chunk it was stored with.  Errors: DSM_ERR_ARG for a chunk
+ * outside [4, 8].  dsm_get_part_chunk returns the current chunk (0 for a null
+ * problem). */
+dsm_status dsm_set_part_chunk(dsm_problem* p, int32_t chunk);
+int32_t dsm_get_part_chunk(const dsm_problem* p);
+
+/* Autotuning of the chunk for one partial-evaluation workload, like
+ * dsm_autotune_pitch: for each of the n_chunk host candidates `chunks`
+ * (n_chunk 0: 4, 5, 6, 7, 8) runs the partial evaluation twice on the null
+ * stream and records the second run's time in ms_out host [n_chunk] (or [5];
+ * may be NULL); the fastest chunk is kept and returned in *best (may be NULL).
+ * Setup-time call: allocates temporary outputs and synchronises.  Errors as
+ * dsm_set_part_chunk for a candidate, as dsm_eval_partial for the rest. */
+dsm_status dsm_autotune_chunk(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                              const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_chunk,
+                              const int32_t* chunks, float* ms_out, int32_t* best);
+
 /* Test hook for Sec. 2.3.1 rasterisation: owner dev [Dz][Dy][Dx] int32 receives
  * the id of the tetrahedron of grid coordinates Xgrid dev [P][3] whose exact
  * voxel set contains each voxel (-1 if none); overlap dev [1] int32 counts

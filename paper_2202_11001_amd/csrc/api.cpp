@@ -236,9 +236,9 @@ dsm_status dsm_problem_create(const dsm_problem_desc* d, dsm_problem** out) {
                             (size_t)p->max_S * full_groups * kFullChunk);
   }
   DSM_TRY(dev_alloc(&p->d_simws, p->simws_len), "hipMalloc sweep workspace");
-  p->nchunk = (p->maxA + kPartChunk - 1) / kPartChunk;
+  p->nchunk = (p->maxA + p->part_chunk - 1) / p->part_chunk;
   {
-    const size_t nc = (size_t)p->max_S * std::max(1, p->max_F) * p->nchunk;
+    const size_t nc = (size_t)p->max_S * std::max(1, p->max_F) * ((p->maxA + kMinPartChunk - 1) / kMinPartChunk);
     DSM_TRY(dev_alloc(&p->d_cflags, nc), "hipMalloc chunk flags");
     DSM_TRY(dev_alloc(&p->d_ccount, nc), "hipMalloc chunk counts");
   }
@@ -426,6 +426,7 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
   a.vcount = voxel_count;
   a.mask = mask;
   a.simws = p->d_simws;
+  a.pchunk = p->part_chunk;
   a.nchunk = p->nchunk;
   a.cflags = p->d_cflags;
   a.ccount = p->d_ccount;
@@ -443,6 +444,59 @@ dsm_status dsm_eval_partial(dsm_problem* p, int32_t S, const float* X, int32_t F
                                  tet_terms_new, voxel_count, stream);
 }
 
+}  // extern "C"
+
+namespace {
+// Shared driver of the setup-time autotuners: for each candidate k, apply(k)
+// changes one setting of p, then the partial evaluation runs twice on the null
+// stream and the second run is timed; the fastest candidate is applied again
+// at the end and returned in *best_k (an index into the candidates).
+template <class Apply>
+dsm_status autotune(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                    const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int n, Apply apply,
+                    float* ms_out, int* best_k) {
+  double *old = nullptr, *nw = nullptr;
+  uint32_t* fl = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  dsm_status st = DSM_OK;
+  float best_ms = INFINITY;
+  int best = -1;
+  if ((e = dev_alloc(&old, (size_t)S * F * 3)) != hipSuccess || (e = dev_alloc(&nw, (size_t)S * F * 3)) != hipSuccess ||
+      (e = dev_alloc(&fl, (size_t)S * F)) != hipSuccess || (e = hipEventCreate(&e0)) != hipSuccess ||
+      (e = hipEventCreate(&e1)) != hipSuccess) {
+    st = hip_fail(e, "autotune buffers");
+  }
+  for (int k = 0; st == DSM_OK && k < n; ++k) {
+    if ((st = apply(k)) != DSM_OK) break;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && st == DSM_OK; ++rep) {  // the first run warms caches and code
+      (void)hipEventRecord(e0, nullptr);
+      st = dsm_eval_partial(p, S, X, F, fos_off, fos_pts, cand, tet_terms_in, old, nw, fl, nullptr, nullptr, nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      if (st == DSM_OK && (e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "autotune run");
+      if (st == DSM_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (st != DSM_OK) break;
+    if (ms_out) ms_out[k] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = k;
+    }
+  }
+  if (st == DSM_OK && best >= 0) st = apply(best);
+  if (st == DSM_OK) *best_k = best;
+  if (old) (void)hipFree(old);
+  if (nw) (void)hipFree(nw);
+  if (fl) (void)hipFree(fl);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+}  // namespace
+
+extern "C" {
+
 dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
                               const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_pitch,
                               const int32_t* pitches, float* ms_out, int32_t* best) {
@@ -458,46 +512,44 @@ dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t
   }
   for (int c : cands)
     if (c != 0 && !pitch_ok(p->dims[0], p->dims[1], p->dims[2], c)) return fail(DSM_ERR_ARG, "pitch %d not accepted", c);
-  // temporary outputs (setup-time call: allocation allowed here)
-  double *old = nullptr, *nw = nullptr;
-  uint32_t* fl = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e;
-  dsm_status st = DSM_OK;
-  float best_ms = INFINITY;
-  int best_pitch = p->pitch;
-  if ((e = dev_alloc(&old, (size_t)S * F * 3)) != hipSuccess || (e = dev_alloc(&nw, (size_t)S * F * 3)) != hipSuccess ||
-      (e = dev_alloc(&fl, (size_t)S * F)) != hipSuccess || (e = hipEventCreate(&e0)) != hipSuccess ||
-      (e = hipEventCreate(&e1)) != hipSuccess) {
-    st = hip_fail(e, "autotune buffers");
-  }
-  for (size_t k = 0; st == DSM_OK && k < cands.size(); ++k) {
-    if ((e = repack(p, cands[k])) != hipSuccess) {
-      st = hip_fail(e, "re-pack images");
-      break;
-    }
-    float ms = 0.f;
-    for (int rep = 0; rep < 2 && st == DSM_OK; ++rep) {  // the first run warms caches and code
-      (void)hipEventRecord(e0, nullptr);
-      st = dsm_eval_partial(p, S, X, F, fos_off, fos_pts, cand, tet_terms_in, old, nw, fl, nullptr, nullptr, nullptr);
-      (void)hipEventRecord(e1, nullptr);
-      if (st == DSM_OK && (e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "autotune run");
-      if (st == DSM_OK) (void)hipEventElapsedTime(&ms, e0, e1);
-    }
-    if (st != DSM_OK) break;
-    if (ms_out) ms_out[k] = ms;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best_pitch = p->pitch;
-    }
-  }
-  if (st == DSM_OK && (e = repack(p, best_pitch)) != hipSuccess) st = hip_fail(e, "re-pack images");
-  if (st == DSM_OK && best) *best = best_pitch;
-  if (old) (void)hipFree(old);
-  if (nw) (void)hipFree(nw);
-  if (fl) (void)hipFree(fl);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  int k = -1;
+  const dsm_status st = autotune(p, S, X, F, fos_off, fos_pts, cand, tet_terms_in, (int)cands.size(), [&](int i) {
+    const hipError_t e = repack(p, cands[i]);
+    return e == hipSuccess ? DSM_OK : hip_fail(e, "re-pack images");
+  }, ms_out, &k);
+  if (st == DSM_OK && best) *best = p->pitch;
+  return st;
+}
+
+dsm_status dsm_set_part_chunk(dsm_problem* p, int32_t chunk) {
+  g_err.clear();
+  if (!p) return fail(DSM_ERR_ARG, "null argument");
+  if (chunk < kMinPartChunk || chunk > kMaxPartChunk)
+    return fail(DSM_ERR_ARG, "chunk %d outside [%d, %d]", chunk, kMinPartChunk, kMaxPartChunk);
+  p->part_chunk = chunk;
+  p->nchunk = (p->maxA + chunk - 1) / chunk;
+  return DSM_OK;
+}
+
+int32_t dsm_get_part_chunk(const dsm_problem* p) { return p ? p->part_chunk : 0; }
+
+dsm_status dsm_autotune_chunk(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                              const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_chunk,
+                              const int32_t* chunks, float* ms_out, int32_t* best) {
+  g_err.clear();
+  if (!p || !X || !fos_off || !fos_pts || !cand || n_chunk < 0 || (n_chunk > 0 && !chunks)) return fail(DSM_ERR_ARG, "null argument");
+  if (S <= 0 || F <= 0) return fail(DSM_ERR_ARG, "S and F must be positive");
+  std::vector<int> cands;
+  if (n_chunk > 0)
+    cands.assign(chunks, chunks + n_chunk);
+  else
+    for (int c = kMinPartChunk; c <= kMaxPartChunk; ++c) cands.push_back(c);
+  for (int c : cands)
+    if (c < kMinPartChunk || c > kMaxPartChunk) return fail(DSM_ERR_ARG, "chunk %d outside [%d, %d]", c, kMinPartChunk, kMaxPartChunk);
+  int k = -1;
+  const dsm_status st = autotune(p, S, X, F, fos_off, fos_pts, cand, tet_terms_in, (int)cands.size(),
+                                 [&](int i) { return dsm_set_part_chunk(p, cands[i]); }, ms_out, &k);
+  if (st == DSM_OK && best) *best = p->part_chunk;
   return st;
 }
 
@@ -574,6 +626,7 @@ dsm_status batch_tables(const dsm_batch* b, int n_jobs, const dsm_partial_job* j
     a.vcount = q.voxel_count;
     a.mask = q.mask;
     a.simws = p->d_simws;
+    a.pchunk = p->part_chunk;
     a.nchunk = p->nchunk;
     a.cflags = p->d_cflags;
     a.ccount = p->d_ccount;

@@ -17,8 +17,11 @@ constexpr double kLat = 128.0;    // lattice steps per voxel
 // kClusterSelMax selected solutions, at most kClusterRounds k-means rounds.
 constexpr int kClusterMax = 16, kClusterSelMax = 1024, kClusterRounds = 50;
 constexpr int kFullChunk = 8;     // tetrahedra per workgroup in full evaluation
-constexpr int kPartChunk = 8;     // affected tetrahedra per workgroup in partial evaluation
-constexpr int kMaxChunk = kFullChunk > kPartChunk ? kFullChunk : kPartChunk;
+// Affected tetrahedra per workgroup in partial evaluation: a per-problem
+// setting in [kMinPartChunk, kMaxPartChunk] (dsm_set_part_chunk), default
+// kPartChunk; the LDS layout is sized for kMaxChunk.
+constexpr int kPartChunk = 8, kMinPartChunk = 4, kMaxPartChunk = 8;
+constexpr int kMaxChunk = kFullChunk > kMaxPartChunk ? kFullChunk : kMaxPartChunk;
 // The finishing kernel gives each (group, solution) pair kFinishLanes lanes
 // (one per affected tetrahedron at a time), kFinishPairs pairs per 64-lane wave.
 constexpr int kFinishLanes = 16;
@@ -94,7 +97,8 @@ struct EvalArgs {
   uint32_t* vcount;      // [S][G] or null
   const uint8_t* mask;   // [S][G] or null: evaluate only where non-zero (partial)
   double* simws;         // swept dissimilarity workspace of the problem
-  int nchunk;            // partial: workgroups (chunks of kFullChunk affected tetrahedra) per group
+  int pchunk;            // partial: affected tetrahedra per workgroup
+  int nchunk;            // partial: workgroups (chunks of pchunk affected tetrahedra) per group
   uint32_t* cflags;      // partial: [S][G][nchunk] constraint flags per chunk
   uint32_t* ccount;      // partial: [S][G][nchunk] candidate voxel count per chunk
 };
@@ -173,7 +177,8 @@ struct dsm_problem {
   size_t simws_len = 0;
   uint32_t* d_cflags = nullptr; // [max_S][max_F][nchunk] per-chunk flags of a partial evaluation
   uint32_t* d_ccount = nullptr; // [max_S][max_F][nchunk] per-chunk voxel counts
-  int nchunk = 1;               // ceil(maxA / kFullChunk)
+  int part_chunk = dsm::kPartChunk;  // affected tetrahedra per workgroup in partial evaluation
+  int nchunk = 1;               // ceil(maxA / part_chunk); the chunk arrays hold ceil(maxA / kMinPartChunk)
   std::vector<float> identity;  // [P][3]
   float* d_ident = nullptr;     // device copy of the undeformed grid [P][3]
   std::vector<hipEvent_t> ev;   // timing event pairs (begin, end)

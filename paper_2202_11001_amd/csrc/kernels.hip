@@ -712,10 +712,10 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
 
   // this chunk's tetrahedra: slots [i0, i0 + na) of the group
   const int na_all = PARTIAL ? a.aff_cnt[g] : min(kFullChunk, pr.T - g * kFullChunk);
-  const int i0 = c * (PARTIAL ? kPartChunk : kFullChunk);
+  const int i0 = c * (PARTIAL ? a.pchunk : kFullChunk);
   if (na_all <= i0) return;  // malformed element (count -1) or no tetrahedra in this chunk: k_finish sets the flags
   if (PARTIAL && a.mask && a.mask[(size_t)s * a.G + g] == 0) return;  // not requested
-  const int na = min(PARTIAL ? kPartChunk : kFullChunk, na_all - i0);
+  const int na = min(PARTIAL ? a.pchunk : kFullChunk, na_all - i0);
   if (tid == 0) s_flags = 0u;
   if (tid < kWaves) s_count[tid] = 0u;
   for (int i = tid; i < na; i += kWG) s_tet[i] = group_tet(a, g, i0 + i);
@@ -953,7 +953,7 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical, int 
   }
   if (a.partial && lane == 0) {  // combine the chunks' flags and voxel counts in chunk order
     unsigned fl = 0u, cnt = 0u;
-    for (int c = 0; c * kPartChunk < na; ++c) {
+    for (int c = 0; c * a.pchunk < na; ++c) {
       fl |= a.cflags[oi * a.nchunk + c];
       cnt += a.ccount[oi * a.nchunk + c];
     }

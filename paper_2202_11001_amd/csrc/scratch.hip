@@ -88,7 +88,7 @@ dsm_status dsm_eval_partial_noalloc(dsm_problem* p, int32_t S, const float* X, i
   }
   if (device < 0 || device >= kMaxDevices) return set_error(DSM_ERR_UNSUPPORTED, "device index above 63");
   const int nver = tet_terms_in ? 1 : 2;
-  const int nchunk = (p->maxA + kPartChunk - 1) / kPartChunk;
+  const int nchunk = p->nchunk;
   const ScratchLayout L = scratch_layout(S, F, p->maxA, nver, nchunk);
   if (L.total > kScratchBytes) {
     snprintf(msg, sizeof msg,
@@ -127,6 +127,7 @@ dsm_status dsm_eval_partial_noalloc(dsm_problem* p, int32_t S, const float* X, i
   a.vcount = voxel_count;
   a.mask = nullptr;
   a.simws = (double*)(base + L.simws);
+  a.pchunk = p->part_chunk;
   a.nchunk = nchunk;
   a.cflags = (uint32_t*)(base + L.cflags);
   a.ccount = (uint32_t*)(base + L.ccount);

@@ -110,6 +110,9 @@ def lib():
             "dsm_problem_set_pitch": ([V, I], I),
             "dsm_refine_population": ([V, I, V, V, V], I),
             "dsm_autotune_pitch": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
+            "dsm_set_part_chunk": ([V, I], I),
+            "dsm_get_part_chunk": ([V], I),
+            "dsm_autotune_chunk": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
             "dsm_surrogate_create": ([V, V], I),
             "dsm_surrogate_destroy": ([V], I),
             "dsm_surrogate_last_error": ([], C.c_char_p),
@@ -619,6 +622,30 @@ class Problem:
         if pitches is None:
             pl = self._default_pitch_candidates()
         return int(best.value), {int(p): float(t) for p, t in zip(pl, ms)}
+
+    @property
+    def part_chunk(self):
+        """Affected tetrahedra per workgroup of a partial evaluation."""
+        return int(lib().dsm_get_part_chunk(self._h))
+
+    def set_part_chunk(self, chunk):
+        """Sets the affected tetrahedra per workgroup of later partial evaluations (4..8)."""
+        _check(lib().dsm_set_part_chunk(self._h, int(chunk)))
+
+    def autotune_chunk(self, X, fos_off, fos_pts, cand, tet_terms_in=None, chunks=None):
+        """Times the partial evaluation for each candidate chunk and keeps the
+        fastest; returns (best chunk, {chunk: ms})."""
+        S, F = X.shape[0], fos_off.shape[0] - 1
+        cl = np.ascontiguousarray(chunks if chunks is not None else [], dtype=np.int32)
+        n = len(cl) if chunks is not None else 5
+        ms = np.zeros(n, np.float32)
+        best = C.c_int32()
+        _check(lib().dsm_autotune_chunk(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                        _dptr(tet_terms_in), len(cl) if chunks is not None else 0,
+                                        _np_ptr(cl), _np_ptr(ms), C.byref(best)))
+        if chunks is None:
+            cl = list(range(4, 9))
+        return int(best.value), {int(c): float(t) for c, t in zip(cl, ms)}
 
     def _default_pitch_candidates(self):
         Dx = self.dims[0]

@@ -380,6 +380,7 @@ def test_uneven_batch_one_launch(level):
         off, pts = w.fos()
         cand = w.candidates(X, off, pts)
         gp = _gpu_problem(w, len(X))
+        gp.set_part_chunk(4 + len(probs) % 5)  # every problem its own work split
         probs.append((w, rp, X, off, pts, cand, gp))
         Xd = _t(X)
         cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
@@ -435,6 +436,50 @@ def test_layout_pitch_changes_nothing():
         np.testing.assert_array_equal(a, b)
     with pytest.raises(dsm.DsmError):
         gp.set_pitch(Dx + 1)
+
+
+def test_part_chunk_changes_no_voxel_set():
+    """The affected tetrahedra per workgroup (4..8) change no flag and no voxel
+    count, and the terms only by rounding: the voxels a wave sums in its
+    per-lane compensated FP32 sums follow the work split (measured differences
+    below 4e-9 relative); the chunk autotuner keeps one of its candidates; the
+    allocation-free entry point follows the problem's chunk bit for bit."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)[:48]
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    gp = _gpu_problem(w, len(X))
+    assert gp.part_chunk == 8
+    Xd, offd, ptsd, cd = _t(X), _t(off), _t(pts), _t(cand)
+    cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+    gp.eval_full(Xd, tet_terms=cache)
+
+    def run(noalloc=False):
+        f = gp.eval_partial_noalloc if noalloc else gp.eval_partial
+        res = f(Xd, offd, ptsd, cd, tet_terms_in=cache, voxel_count=True)
+        torch.cuda.synchronize()
+        return [r.cpu().numpy() for r in res]
+
+    ref8 = run()
+    assert gp.max_star > 8  # several chunks per element at every chunk size tried
+    for chunk in (4, 5, 6, 7, 8):
+        gp.set_part_chunk(chunk)
+        assert gp.part_chunk == chunk
+        got = run()
+        _say(f"part chunk {chunk}")
+        np.testing.assert_array_equal(got[2], ref8[2])
+        np.testing.assert_array_equal(got[3], ref8[3])
+        for a, b in zip(got[:2], ref8[:2]):
+            np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
+        for a, b in zip(run(noalloc=True), got):
+            np.testing.assert_array_equal(a, b)
+    for bad in (3, 9):
+        with pytest.raises(dsm.DsmError):
+            gp.set_part_chunk(bad)
+    assert gp.part_chunk == 8
+    best, table = gp.autotune_chunk(Xd, offd, ptsd, cd, tet_terms_in=cache, chunks=[5, 8])
+    assert best in (5, 8) and gp.part_chunk == best and sorted(table) == [5, 8] and all(t > 0 for t in table.values())
 
 
 def ref_pitch_default(Dx):
