@@ -145,11 +145,16 @@ __device__ __forceinline__ double group16_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_up(v, off, 64);
-    if (lane >= off) v += o;
-  }
+// Inclusive prefix sum over the 64 lanes of a wave, all lanes active: DPP
+// shifts within rows of 16 lanes, then the row totals carried by the
+// broadcasts of lanes 15 and 31.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
   return v;
 }
 
@@ -288,7 +293,7 @@ __device__ void setup_slices(const float* xo, const float* xt, const int D[3], i
       slice_rows(L, rt.zlo + lane, D[1], ya, yb);
       cnt = max(0, yb - ya + 1);
     }
-    const int incl = wave_incl_scan(cnt, lane);
+    const int incl = wave_incl_scan(cnt);
     if (lane < nz) {
       rt.rs[lane] = (unsigned short)(incl - cnt);
       rt.y0[lane] = (unsigned short)ya;
@@ -368,23 +373,35 @@ struct WaveRows {
 // lane's row, or a large negative value if it is empty.
 __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int sy, int sz,
                                           int base, float shift, WaveRows& wr, int* my_start) {
-  const int r = b * 64 + lane;
+  const int r0 = b * 64, r = r0 + lane;
   int len = 0, lin = 0;
   float bx = 0.f, by = 0.f, bz = 0.f;
-  if (r < rt.nrows) {
-    int y, z;
-    if (rt.sliced) {
-      int j = 0;  // last slice whose first candidate row is <= r
-      const int nz = rt.nz;
-#pragma unroll
-      for (int step = 32; step >= 1; step >>= 1)
-        if (j + step < nz && rt.rs[j + step] <= r) j += step;
-      y = rt.y0[j] + (r - rt.rs[j]);
-      z = rt.zlo + j;
-    } else {
-      y = rt.ylo + r % rt.ny;
-      z = rt.zlo + r / rt.ny;
+  int y, z;
+  if (rt.sliced) {
+    // lane k holds slice k's first candidate row and its y; row r lies in the
+    // last slice that starts at or before r: the slice of the unit's first
+    // row, advanced over the slices that start inside the unit (in order)
+    const int nz = rt.nz;
+    const int rsk = lane < nz ? (int)rt.rs[lane] : 0x7fffffff;
+    const int y0k = lane < nz ? (int)rt.y0[lane] : 0;
+    const int jb = __popcll(__ballot(rsk <= r0)) - 1;  // rs[0] = 0
+    y = __builtin_amdgcn_readlane(y0k, jb) + (r - __builtin_amdgcn_readlane(rsk, jb));
+    z = rt.zlo + jb;
+    unsigned long long inside = __ballot(rsk > r0 && rsk < r0 + 64);
+    while (inside) {
+      const int k = __builtin_ctzll(inside);
+      inside &= inside - 1;
+      const int s = __builtin_amdgcn_readlane(rsk, k);
+      if (r >= s) {
+        y = __builtin_amdgcn_readlane(y0k, k) + (r - s);
+        z = rt.zlo + k;
+      }
     }
+  } else {
+    y = rt.ylo + r % rt.ny;
+    z = rt.zlo + r / rt.ny;
+  }
+  if (r < rt.nrows) {
     int x0, x1;
     row_span(rt, y, z, D[0], x0, x1);
     if (x1 >= x0) {
@@ -396,7 +413,7 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
       bz = (float)(rt.P0[2] + rt.J[2][0] * v[0] + rt.J[2][1] * v[1] + rt.J[2][2] * v[2] + shift);
     }
   }
-  const int incl = wave_incl_scan(len, lane);
+  const int incl = wave_incl_scan(len);
   const int start = incl - len;
   const unsigned long long ne = __ballot(len > 0);
   const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(ne >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ne, 0u));
@@ -407,7 +424,7 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
   }
   wave_sync();
   *my_start = len > 0 ? start : -(1 << 30);
-  return __shfl(incl, 63, 64);
+  return __builtin_amdgcn_readlane(incl, 63);
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const float* p, int bytes) {
@@ -645,9 +662,9 @@ __device__ void lds_exclusive_scan(int* v, int n, int tid) {
     int carry = 0;
     for (int base = 0; base < n; base += 64) {
       const int x = base + tid < n ? v[base + tid] : 0;
-      const int incl = wave_incl_scan(x, tid);
+      const int incl = wave_incl_scan(x);
       if (base + tid < n) v[base + tid] = carry + incl - x;
-      carry += __shfl(incl, 63, 64);
+      carry += __builtin_amdgcn_readlane(incl, 63);
     }
     if (tid == 0) v[n] = carry;
   }
@@ -1170,8 +1187,8 @@ __global__ __launch_bounds__(64) void k_affected(DevProblem pr, int F, const int
   const int lo = min(lane * chunk, total), hi = min(lo + chunk, total);
   int cnt = 0;
   for (int i = lo; i < hi; ++i) cnt += i == 0 || s_c[i] != s_c[i - 1];
-  const int incl = wave_incl_scan(cnt, lane);
-  const int n_unique = __shfl(incl, 63, 64);
+  const int incl = wave_incl_scan(cnt);
+  const int n_unique = __builtin_amdgcn_readlane(incl, 63);
   if (n_unique > maxA) {
     if (lane == 0) aff_cnt[f] = -1;
     return;
