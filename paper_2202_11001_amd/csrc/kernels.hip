@@ -158,6 +158,15 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
+// Inclusive prefix sum within each row of 16 lanes (the lanes of a row active).
+__device__ __forceinline__ int row16_incl_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);  // row_shr:8
+  return v;
+}
+
 // Parameters of one (tetrahedron, direction) for rasterising the own grid's
 // voxels and mapping them into the other grid.  Lives in LDS.
 constexpr int kMaxSlices = 64;  // slice-table capacity; taller tetrahedra enumerate bounding-box rows
@@ -312,6 +321,53 @@ __device__ void setup_slices(const float* xo, const float* xt, const int D[3], i
     rt.P0[r] = (double)xt[r] - (rt.J[r][0] * (double)xo[0] + rt.J[r][1] * (double)xo[1] + rt.J[r][2] * (double)xo[2]);
   }
   wave_sync();
+}
+
+// setup_slices on a group of 16 lanes (one DPP row, `sub` = lane within the
+// group; all 16 lanes call it) for tetrahedra of few slices: slices in rounds of
+// 16, the candidate-row prefix carried from round to round.  Returns the number
+// of rows (on every lane of the group).
+__device__ int setup_slices16(const float* xo, const float* xt, const int D[3], int lane, int sub, RasterTet& rt) {
+  const int nz = rt.nz;
+  int nrows;
+  if (nz <= kMaxSlices) {
+    float L[4][3];
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 3; ++c) L[q][c] = (xo[3 * q + c] + 0.5f) * 128.f;
+    int carry = 0;
+    for (int base = 0; base < nz; base += 16) {
+      const int k = base + sub;
+      int cnt = 0, ya = 0;
+      if (k < nz) {
+        int yb;
+        slice_rows(L, rt.zlo + k, D[1], ya, yb);
+        cnt = max(0, yb - ya + 1);
+      }
+      const int incl = row16_incl_scan(cnt);
+      if (k < nz) {
+        rt.rs[k] = (unsigned short)(carry + incl - cnt);
+        rt.y0[k] = (unsigned short)ya;
+      }
+      carry += __shfl(incl, lane | 15, 64);
+    }
+    nrows = carry;
+    if (sub == 0) {
+      rt.rs[nz] = (unsigned short)carry;
+      rt.nrows = carry;
+      rt.sliced = 1;
+    }
+  } else {
+    nrows = nz * rt.ny;
+    if (sub == 0) {
+      rt.nrows = nrows;
+      rt.sliced = 0;
+    }
+  }
+  if (sub < 3) {
+    const int r = sub;
+    rt.P0[r] = (double)xt[r] - (rt.J[r][0] * (double)xo[0] + rt.J[r][1] * (double)xo[1] + rt.J[r][2] * (double)xo[2]);
+  }
+  return nrows;
 }
 
 // Both parts on one wave.
@@ -805,17 +861,17 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     }
   }
   __syncthreads();
-  // slice tables, one wave per entry, and the units
-  for (int e = wave; e < nent; e += kWaves) {
+  // slice tables, 16 lanes per entry, and the units
+  for (int e0 = wave * 4; e0 < nent; e0 += kWaves * 4) {
+    const int e = e0 + (lane >> 4), sub = lane & 15;
     int nunits = 0;
-    if (uniform(s_units[e])) {
+    if (e < nent && s_units[e]) {
       int own;
       const float* xyz = entry_xyz(e, own);
-      setup_slices(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, s_rts[e]);
-      nunits = (s_rts[e].nrows + 63) >> 6;
+      nunits = (setup_slices16(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, sub, s_rts[e]) + 63) >> 6;
     }
     wave_sync();
-    if (lane == 0) s_units[e] = nunits;
+    if (e < nent && sub == 0) s_units[e] = nunits;
   }
   for (int e = tid; e < nent * kWaves; e += kWG) s_part[e] = 0.0;
   __syncthreads();
