@@ -788,8 +788,9 @@ def main():
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_screen = 2, 0, True, True
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} not supported: this evaluator runs on one GPU "
-              f"(solutions shard across GPUs without exchange, see the design notes)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} not supported: this evaluator runs on one GPU; a population "
+              f"would shard by solutions across GPUs with no exchange during evaluation, which is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
