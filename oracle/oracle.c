@@ -13,8 +13,7 @@
  * barycentric mapping, FP64 trilinear sampling, FP64 sums.  No blocking, no spans,
  * no incremental evaluation.
  *
- * Conventions (readings of passages where the paper is silent; each is also
- * listed in the design notes):
+ * Conventions (readings of passages where the paper is silent):
  *   - grid 0 = source ("moving") grid on the source image, grid 1 = target
  *     ("fixed") grid on the target image (Sec. 2.1: a source image is registered
  *     onto a target image; forward = transformed source compared to target,
