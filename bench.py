@@ -132,7 +132,7 @@ def screened_step(gp, Xd, offd, ptsd, candd, cache, out, w, S, F, K=4, train_ste
     ok = (flags == 0).reshape(-1)
     f_ok, o_ok, n_ok = feats[ok], old.reshape(-1, 3)[ok].contiguous(), new.reshape(-1, 3)[ok].contiguous()
     sur = dsm.Surrogate(seed=11, max_rows=S * F * K, max_batch=4096)
-    sur.fit_scaling(f_ok, (n_ok - o_ok).to(torch.float32).contiguous())
+    sur.fit_scaling(f_ok, sur.pack(part_old=o_ok, part_new=n_ok)[2])  # raw deltas new - old
     fb, tg, _ = sur.pack(f_ok, o_ok, n_ok)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -686,6 +686,35 @@ size_t dsm_forced_work_bytes(const dsm_problem* p, int32_t S);
 dsm_status dsm_forced_replace(dsm_problem* p, int32_t S, float* X, double* obj, double* cache, const int32_t* donor,
                               const uint8_t* improved, int32_t* nis, void* work, int32_t* n_replaced, void* stream);
 
+/* RV-GOMEA's anticipated mean shift (Sec. 2.2 builds on RV-GOMEA; the
+ * samplers add 2 c times it for half of the population): shift dev [n]
+ * float64 = mean - prev, then prev dev [n] = mean (mean dev [n], e.g. the
+ * selection's point means [P][6] of dsm_estimate_distributions); with
+ * has_prev = 0 (first generation) only prev = mean, and shift may be NULL.
+ * Errors: DSM_ERR_ARG, DSM_ERR_DEVICE. */
+dsm_status dsm_ams_shift(int32_t n, const double* mean, double* prev, double* shift, int32_t has_prev, void* stream);
+
+/* MO-RV-GOMEA's single-objective clusters (the optimiser Sec. 2.2 builds
+ * on): of k clusters with objective means means dev [k][3] float64 (as
+ * dsm_cluster_objectives writes them), objective o = 0, 1, 2 (while o < k)
+ * takes the cluster, not yet taken, with the lowest mean in o (the lowest
+ * index among equal means; a NaN mean is never lower).  so dev [S] int32
+ * receives the objective of solution s's cluster assign dev [S] int32, or -1.
+ * Errors: DSM_ERR_ARG (k outside [1, 16]), DSM_ERR_DEVICE. */
+dsm_status dsm_single_objective_clusters(int32_t k, const double* means, int32_t S, const int32_t* assign, int32_t* so,
+                                         void* stream);
+
+/* RV-GOMEA's forced-improvement donors: every solution whose no-improvement
+ * stretch nis dev [S] int32 exceeds nis_max gets donor dev [S] int32 = the
+ * entry at min(floor(u[s] n), n - 1) of the ascending list of the n solutions
+ * that no member dominates (dominated_by == 0, dominated_by dev [S] int32 as
+ * dsm_select writes it), u dev [S] float32 uniform draws in [0, 1) made by the
+ * caller (computed in float32); all other solutions get -1.  n_forced dev [1]
+ * int32 or NULL is increased by the number of donors given.  Errors:
+ * DSM_ERR_ARG, DSM_ERR_CAPACITY (S > 8192), DSM_ERR_DEVICE. */
+dsm_status dsm_draw_donors(int32_t S, const int32_t* nis, int32_t nis_max, const int32_t* dominated_by, const float* u,
+                           int32_t* donor, int32_t* n_forced, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

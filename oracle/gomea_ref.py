@@ -345,3 +345,42 @@ def multiplier_step(accepted, mult, cluster=None, eta=0.9, lo=0.05, hi=10.0):
             out[j, f] = min(np.float32(c / np.float32(eta)), np.float32(hi)) if hit else \
                 max(np.float32(c * np.float32(eta)), np.float32(lo))
     return out
+
+
+def ams_shift(mean, prev):
+    """RV-GOMEA's anticipated mean shift: the change of the selection's mean of
+    every variable since the previous generation (mean - prev)."""
+    return np.asarray(mean, np.float64) - np.asarray(prev, np.float64)
+
+
+def single_objective_clusters(means, assign):
+    """MO-RV-GOMEA's single-objective clusters: objective o = 0, 1, 2 (while
+    o < k) takes, of the k clusters not yet taken, the one whose mean in o is
+    lowest (the lowest index among equal means); returns, for every solution,
+    the objective of its cluster assign[s], or -1 if that cluster has none."""
+    means = np.asarray(means, np.float64)
+    k = len(means)
+    of_cluster = [-1] * k
+    for o in range(min(3, k)):
+        best = None
+        for j in range(k):
+            if of_cluster[j] < 0 and (best is None or means[j, o] < means[best, o]):
+                best = j
+        of_cluster[best] = o
+    return np.array([of_cluster[a] if 0 <= a < k else -1 for a in assign], np.int32)
+
+
+def draw_donors(nis, nis_max, dominated_by, u):
+    """RV-GOMEA's forced-improvement donors: a solution whose no-improvement
+    stretch exceeds nis_max gets a donor drawn from the solutions no member
+    dominates, taken in ascending order: entry min(floor(u[s] n), n - 1) of the
+    n of them, with the caller's uniform draw u[s] in [0, 1) (the product in
+    float32); the others get -1."""
+    nd = np.nonzero(np.asarray(dominated_by) == 0)[0]
+    n = len(nd)
+    donor = np.full(len(nis), -1, np.int32)
+    for s in range(len(nis)):
+        if nis[s] > nis_max and n > 0:
+            i = int(np.floor(np.float32(u[s]) * np.float32(n)))
+            donor[s] = nd[min(max(i, 0), n - 1)]
+    return donor

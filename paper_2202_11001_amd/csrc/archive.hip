@@ -266,6 +266,87 @@ __global__ __launch_bounds__(kSelWG) void k_select(int S, const double* __restri
   }
 }
 
+// RV-GOMEA's anticipated mean shift: the change of the selection's point means
+// since the previous generation; prev keeps the current means.
+__global__ void k_ams_shift(int n, const double* __restrict__ mean, double* __restrict__ prev, double* __restrict__ shift,
+                            int has_prev) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double m = mean[i];
+    if (has_prev) shift[i] = m - prev[i];
+    prev[i] = m;
+  }
+}
+
+// MO-RV-GOMEA's single-objective clusters: objective o = 0, 1, 2 (while o < k)
+// takes, of the clusters not yet taken, the one with the lowest mean in o (the
+// lowest index among equal means); every solution gets its cluster's objective.
+// Each workgroup derives the (at most kClusterMax) assignments itself.
+__global__ void k_so_clusters(int k, const double* __restrict__ means, int S, const int* __restrict__ assign,
+                              int* __restrict__ so) {
+  __shared__ int of_cluster[kClusterMax];
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < k; ++j) of_cluster[j] = -1;
+    for (int o = 0; o < 3 && o < k; ++o) {
+      int best = -1;
+      double bv = 0.0;
+      for (int j = 0; j < k; ++j)
+        if (of_cluster[j] < 0 && (best < 0 || means[3 * j + o] < bv)) {
+          best = j;
+          bv = means[3 * j + o];
+        }
+      of_cluster[best] = o;  // o < k clusters are taken, so one is free
+    }
+  }
+  __syncthreads();
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+    const int a = assign[s];
+    so[s] = a >= 0 && a < k ? of_cluster[a] : -1;
+  }
+}
+
+// RV-GOMEA's forced-improvement donors, one workgroup: the solutions no member
+// dominates, in ascending order (block-wide prefix), and every solution whose
+// no-improvement stretch exceeds nis_max takes the list's entry at
+// min(floor(u[s] n), n - 1).
+__global__ __launch_bounds__(1024) void k_draw_donors(int S, const int* __restrict__ nis, int nis_max,
+                                                      const int* __restrict__ dominated_by, const float* __restrict__ u,
+                                                      int* __restrict__ donor, int* __restrict__ n_forced) {
+  extern __shared__ int s_nd[];  // [S]
+  __shared__ int part[1024];
+  __shared__ int s_forced;
+  const int t = threadIdx.x;
+  const int per = (S + 1023) / 1024;
+  const int b = min(S, t * per), e = min(S, b + per);
+  int c = 0;
+  for (int i = b; i < e; ++i) c += dominated_by[i] == 0;
+  part[t] = c;
+  if (t == 0) s_forced = 0;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - c;
+  for (int i = b; i < e; ++i)
+    if (dominated_by[i] == 0) s_nd[run++] = i;
+  const int n = part[1023];
+  __syncthreads();
+  int forced = 0;
+  for (int s = t; s < S; s += 1024) {
+    int d = -1;
+    if (nis[s] > nis_max && n > 0) {
+      d = s_nd[min(max((int)(u[s] * (float)n), 0), n - 1)];
+      ++forced;
+    }
+    donor[s] = d;
+  }
+  if (forced) atomicAdd(&s_forced, forced);
+  __syncthreads();
+  if (t == 0 && n_forced) n_forced[0] += s_forced;
+}
+
 // AMaLGaM's adaptive variance scaling, one thread per distribution (float32).
 __global__ void k_avs(int n, float* __restrict__ mult, int* __restrict__ nis, const double* __restrict__ sdr,
                       int nis_max, float eta, float lo, float hi) {
@@ -434,6 +515,33 @@ dsm_status dsm_mark_improved(int32_t S, int32_t F, const uint8_t* accepted, uint
   if (S == 0 || F == 0) return DSM_OK;
   if (!accepted || !improved) return DSM_ERR_ARG;
   k_mark_improved<<<(S + 255) / 256, 256, 0, (hipStream_t)stream>>>(S, F, accepted, improved);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_ams_shift(int32_t n, const double* mean, double* prev, double* shift, int32_t has_prev, void* stream) {
+  if (n < 0) return DSM_ERR_ARG;
+  if (n == 0) return DSM_OK;
+  if (!mean || !prev || (has_prev && !shift)) return DSM_ERR_ARG;
+  k_ams_shift<<<std::min(1024, (n + 255) / 256), 256, 0, (hipStream_t)stream>>>(n, mean, prev, shift, has_prev ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_single_objective_clusters(int32_t k, const double* means, int32_t S, const int32_t* assign, int32_t* so,
+                                         void* stream) {
+  if (k < 1 || k > kClusterMax || S < 0) return DSM_ERR_ARG;
+  if (S == 0) return DSM_OK;
+  if (!means || !assign || !so) return DSM_ERR_ARG;
+  k_so_clusters<<<std::min(64, (S + 255) / 256), 256, 0, (hipStream_t)stream>>>(k, means, S, assign, so);
+  return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
+}
+
+dsm_status dsm_draw_donors(int32_t S, const int32_t* nis, int32_t nis_max, const int32_t* dominated_by, const float* u,
+                           int32_t* donor, int32_t* n_forced, void* stream) {
+  if (S < 0) return DSM_ERR_ARG;
+  if (S > 8192) return DSM_ERR_CAPACITY;
+  if (S == 0) return DSM_OK;
+  if (!nis || !dominated_by || !u || !donor) return DSM_ERR_ARG;
+  k_draw_donors<<<1, 1024, sizeof(int) * S, (hipStream_t)stream>>>(S, nis, nis_max, dominated_by, u, donor, n_forced);
   return hipGetLastError() == hipSuccess ? DSM_OK : DSM_ERR_DEVICE;
 }
 

@@ -110,6 +110,9 @@ def lib():
             "dsm_problem_set_pitch": ([V, I], I),
             "dsm_refine_population": ([V, I, V, V, V], I),
             "dsm_autotune_pitch": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
+            "dsm_ams_shift": ([I, V, V, V, I, V], I),
+            "dsm_single_objective_clusters": ([I, V, I, V, V, V], I),
+            "dsm_draw_donors": ([I, V, I, V, V, V, V, V], I),
             "dsm_set_part_chunk": ([V, I], I),
             "dsm_get_part_chunk": ([V], I),
             "dsm_autotune_chunk": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
@@ -290,6 +293,49 @@ def mark_improved(accepted, improved, stream=None):
         raise ValueError("mark_improved: accepted uint8 [S][F], improved uint8 [S] expected")
     F = accepted.numel() // max(1, S)
     _check(lib().dsm_mark_improved(S, F, _dptr(accepted), _dptr(improved), _stream(stream)))
+
+
+def ams_shift(mean, prev, shift=None, has_prev=True, stream=None):
+    """Anticipated mean shift (``dsm_ams_shift``): shift = mean - prev, then
+    prev = mean, all float64 of equal size (prev, shift contiguous, updated in
+    place); with has_prev False only prev = mean.  Returns shift."""
+    torch = _torch()
+    n = mean.numel()
+    if (mean.dtype != torch.float64 or prev.dtype != torch.float64 or prev.numel() != n or not mean.is_contiguous()
+            or not prev.is_contiguous() or (has_prev and (shift is None or shift.dtype != torch.float64
+                                                          or shift.numel() != n or not shift.is_contiguous()))):
+        raise ValueError("ams_shift: contiguous float64 mean, prev (and shift) of equal size expected")
+    _check(lib().dsm_ams_shift(n, _dptr(mean), _dptr(prev), _dptr(shift) if has_prev else None, int(bool(has_prev)),
+                               _stream(stream)))
+    return shift
+
+
+def single_objective_clusters(means, assign, stream=None):
+    """Objective of every solution's cluster, or -1 (``dsm_single_objective_clusters``):
+    means float64 [k][3], assign int32 [S]; returns int32 [S]."""
+    torch = _torch()
+    k, S = means.shape[0], assign.numel()
+    if means.dtype != torch.float64 or means.dim() != 2 or means.shape[1] != 3 or assign.dtype != torch.int32:
+        raise ValueError("single_objective_clusters: means float64 [k][3], assign int32 [S] expected")
+    so = torch.empty(S, dtype=torch.int32, device=assign.device)
+    _check(lib().dsm_single_objective_clusters(k, _dptr(means.contiguous()), S, _dptr(assign), _dptr(so),
+                                               _stream(stream)))
+    return so
+
+
+def draw_donors(nis, nis_max, dominated_by, u, n_forced=None, stream=None):
+    """Forced-improvement donors (``dsm_draw_donors``): nis and dominated_by
+    int32 [S], u float32 [S] uniform draws in [0, 1); returns donor int32 [S]
+    (-1 = none); n_forced int32 [1] is increased by the number of donors."""
+    torch = _torch()
+    S = nis.numel()
+    if (nis.dtype != torch.int32 or dominated_by.dtype != torch.int32 or dominated_by.numel() != S
+            or u.dtype != torch.float32 or u.numel() != S):
+        raise ValueError("draw_donors: nis, dominated_by int32 [S] and u float32 [S] expected")
+    donor = torch.empty(S, dtype=torch.int32, device=nis.device)
+    _check(lib().dsm_draw_donors(S, _dptr(nis), int(nis_max), _dptr(dominated_by), _dptr(u), _dptr(donor),
+                                 _dptr(n_forced), _stream(stream)))
+    return donor
 
 
 def mesh_topology(mesh, dims=None):

@@ -214,16 +214,16 @@ class Optimiser:
         # more than nis_max generations copies element values from a donor
         self.use_fi = bool(forced_improvements)
         if self.use_fi and graph:
-            raise ValueError("forced improvements run eagerly (donors are drawn on the host)")
+            raise ValueError("forced improvements run eagerly (the donors' uniform draws come from the host)")
         self.nis_max = int(1 + np.floor(np.log10(self.S))) if nis_max is None else int(nis_max)
         self.nis = torch.zeros(self.S, dtype=torch.int32, device=dev)
         self._donor = None
-        self._fi = None
-        self.fi_forced = 0    # solutions given a donor, summed over generations
+        self._n_forced = torch.zeros(1, dtype=torch.int32, device=dev)    # solutions given a donor
         self._n_replaced = torch.zeros(1, dtype=torch.int32, device=dev)  # of which replaced by their donor
         self._fi_work = None
         self._gen = 0
-        self._point_mean = None
+        self._point_mean = None  # previous generation's point means (device float64 [P][6])
+        self._shift_buf = None
         self._shift = None
         self._ams = None
         if sampler == "estimated":
@@ -375,22 +375,21 @@ class Optimiser:
         if self.use_ams:
             all_pts = self.torch.arange(self.p.P, dtype=self.torch.int32, device=self.X.device)
             mean = self.p.estimate_distributions(self.X, sel, all_pts)[0]
-            self._shift = None if self._point_mean is None else (mean - self._point_mean).contiguous()
-            self._point_mean = mean
+            has_prev = self._point_mean is not None
+            if not has_prev:
+                self._point_mean = self.torch.empty_like(mean)
+                self._shift_buf = self.torch.empty_like(mean)
+            dsm.ams_shift(mean, self._point_mean, self._shift_buf, has_prev=has_prev)
+            self._shift = self._shift_buf if has_prev else None
             half = np.random.default_rng([self.seed, self._gen, 7]).permutation(self.S) < self.S // 2
             self._ams = self.torch.from_numpy(half.astype(np.uint8)).to(self.X.device)
         if self.k == 1:
             return [sel]
         members, self._assign, means = dsm.cluster_objectives(self.obj, sel, self.k)
         if self.use_so:
-            torch = self.torch
             # objective o takes the cluster with the lowest mean in o among those
             # not yet taken (in objective order), so each gets its own while k >= 3
-            of_cluster = torch.full((self.k,), -1, dtype=torch.int32, device=self.X.device)
-            for o in range(min(3, self.k)):
-                m = torch.where(of_cluster < 0, means[:, o], torch.full_like(means[:, o], float("inf")))
-                of_cluster[m.argmin()] = o
-            self._so = of_cluster[self._assign.long()].contiguous()
+            self._so = dsm.single_objective_clusters(means, self._assign)
         return [members[j] for j in range(self.k)]
 
     def _dominated_by(self):
@@ -407,18 +406,17 @@ class Optimiser:
 
     def _draw_donors(self):
         """Solutions whose no-improvement stretch exceeds nis_max get a donor: a
-        random non-dominated member of the population."""
+        random member of the population that no member dominates
+        (dsm_draw_donors, with uniform draws from the optimiser's generator)."""
         torch = self.torch
-        fl = (self.nis > self.nis_max).cpu().numpy()
-        self._fi = fl
-        if not fl.any():
-            self._donor = None
-            return
-        self.fi_forced += int(fl.sum())
-        nd = torch.nonzero(self._dominated_by() == 0).reshape(-1).cpu().numpy()
-        donor = np.full(self.S, -1, np.int32)
-        donor[fl] = np.random.default_rng([self.seed, self._gen, 11]).choice(nd, size=int(fl.sum()))
-        self._donor = torch.from_numpy(donor).to(self.X.device)
+        u = np.random.default_rng([self.seed, self._gen, 11]).random(self.S, dtype=np.float32)
+        self._donor = dsm.draw_donors(self.nis, self.nis_max, self._dominated_by(),
+                                      torch.from_numpy(u).to(self.X.device), n_forced=self._n_forced)
+
+    @property
+    def fi_forced(self):
+        """Solutions given a donor, summed over generations."""
+        return int(self._n_forced.item())
 
     def _after_forcing(self, outs):
         """Updates the no-improvement stretches; a forced solution that accepted
@@ -507,7 +505,7 @@ def train_surrogate(collected, seed=7, steps=2000, batch=4096, max_rows=1 << 20)
     old = torch.cat([c[1] for c in collected]).contiguous()
     new = torch.cat([c[2] for c in collected]).contiguous()
     sur = dsm.Surrogate(seed=seed, max_rows=max_rows, max_batch=batch)
-    sur.fit_scaling(feats, (new - old).to(torch.float32).contiguous())
+    sur.fit_scaling(feats, sur.pack(part_old=old, part_new=new)[2])  # raw deltas new - old
     fb, tg, _ = sur.pack(feats, old, new)
     losses = sur.train(fb, tg, steps=steps, batch=batch)
     return sur, losses, feats.shape[0]

@@ -163,3 +163,42 @@ def test_multiplier_step_matches_oracle(k):
     torch.cuda.synchronize()
     want = G.multiplier_step(acc, mult, cluster if k > 1 else None)
     np.testing.assert_array_equal(md.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("has_prev", [True, False])
+def test_ams_shift_matches_oracle(has_prev):
+    rng = np.random.default_rng(21)
+    mean = rng.normal(size=(600, 6)) * 50
+    prev = rng.normal(size=(600, 6)) * 50
+    shift0 = rng.normal(size=(600, 6))
+    m, p, sh = _t(mean), _t(prev), _t(shift0)
+    dsm.ams_shift(m, p, sh, has_prev=has_prev)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(p.cpu().numpy(), mean)
+    np.testing.assert_array_equal(sh.cpu().numpy(), G.ams_shift(mean, prev) if has_prev else shift0)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 16])
+def test_single_objective_clusters_matches_oracle(k):
+    rng = np.random.default_rng(30 + k)
+    means = rng.integers(0, 4, (k, 3)).astype(np.float64) / 4.0  # many ties
+    assign = rng.integers(-1, k, 700).astype(np.int32)
+    so = dsm.single_objective_clusters(_t(means), _t(assign))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(so.cpu().numpy(), G.single_objective_clusters(means, assign))
+
+
+@pytest.mark.parametrize("S", [7, 512, 3000])
+def test_draw_donors_matches_oracle(S):
+    rng = np.random.default_rng(S)
+    obj = rng.integers(0, 6, (S, 3)).astype(np.float64)
+    cnt = torch.empty(S, dtype=torch.int32, device=DEV)
+    dsm.select(_t(obj), 0, dominated_by=cnt)
+    nis = rng.integers(0, 8, S).astype(np.int32)
+    u = rng.random(S).astype(np.float32)
+    n_forced = torch.full((1,), 5, dtype=torch.int32, device=DEV)
+    donor = dsm.draw_donors(_t(nis), 4, cnt, _t(u), n_forced=n_forced)
+    torch.cuda.synchronize()
+    want = G.draw_donors(nis, 4, cnt.cpu().numpy(), u)
+    np.testing.assert_array_equal(donor.cpu().numpy(), want)
+    assert int(n_forced.item()) == 5 + int((want >= 0).sum()) and (want >= 0).sum() > 0

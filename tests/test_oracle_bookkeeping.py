@@ -122,3 +122,47 @@ def test_multiplier_step_hand_case():
     # without clusters a hit anywhere counts; the bounds hold
     out1 = G.multiplier_step(acc, np.array([[9.5, 0.05, 0.5]], np.float32))
     np.testing.assert_array_equal(out1, np.array([[10.0, 0.05, f(0.5) / f(0.9)]], np.float32))
+
+
+def test_ams_shift_hand_case():
+    np.testing.assert_array_equal(G.ams_shift([1.5, 2.0, -1.0], [1.0, 3.0, -1.0]), [0.5, -1.0, 0.0])
+
+
+def test_single_objective_clusters_hand_case():
+    means = np.array([[0.5, 0.2, 0.9],
+                      [0.1, 0.8, 0.3],
+                      [0.1, 0.1, 0.1],   # ties cluster 1 in objective 0: the lower index wins
+                      [0.7, 0.7, 0.0]])
+    # objective 0 -> cluster 1; objective 1 -> cluster 2 (0.1 < 0.2 < 0.7); objective 2 -> cluster 3 (0.0 < 0.9)
+    np.testing.assert_array_equal(G.single_objective_clusters(means, [0, 1, 2, 3, 1, -1]), [-1, 0, 1, 2, 0, -1])
+    # two clusters: objective 0 takes cluster 1, objective 1 the remaining cluster 0, objective 2 none
+    np.testing.assert_array_equal(G.single_objective_clusters(means[:2], [0, 1, 1]), [1, 0, 0])
+    # one cluster: it optimises objective 0
+    np.testing.assert_array_equal(G.single_objective_clusters(means[:1], [0, 0]), [0, 0])
+
+
+def test_draw_donors_hand_case():
+    dominated_by = np.array([0, 2, 0, 1, 0])          # non-dominated: 0, 2, 4
+    nis = np.array([5, 0, 7, 9, 1])                   # stretches above 4: solutions 0, 2, 3
+    u = np.array([0.0, 0.5, 0.34, 0.999, 0.2], np.float32)
+    # floor(0 * 3) = 0, floor(1.02) = 1, floor(2.997) = 2
+    np.testing.assert_array_equal(G.draw_donors(nis, 4, dominated_by, u), [0, -1, 2, 4, -1])
+    # nobody flagged
+    np.testing.assert_array_equal(G.draw_donors(nis, 9, dominated_by, u), [-1] * 5)
+
+
+def test_draw_donors_are_uniform_over_the_non_dominated():
+    """Every flagged solution gets a non-dominated member, and draws spread
+    evenly over [0, 1) give every such member the same share."""
+    rng = np.random.default_rng(4)
+    S = 40
+    dominated_by = rng.integers(0, 3, S)
+    nd = np.nonzero(dominated_by == 0)[0]
+    hits = np.zeros(S, int)
+    for r in range(500):
+        u = ((np.arange(S) + r * S) / (500.0 * S)).astype(np.float32)  # 20,000 draws on an even grid of [0, 1)
+        d = G.draw_donors(np.ones(S, int), 0, dominated_by, u)
+        assert np.all(np.isin(d, nd))
+        np.add.at(hits, d, 1)
+    share = hits[nd]
+    assert share.sum() == 500 * S and share.max() - share.min() <= 1
