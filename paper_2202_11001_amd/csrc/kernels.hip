@@ -2,14 +2,15 @@
 //
 // Work decomposition (Sec. 2.2: the affected tetrahedra of a partial change
 // are re-evaluated; Sec. 2.3: every objective is a sum of per-cell terms):
-//   one workgroup per (FOS element, solution) in partial evaluation, or per
-//   (chunk of tetrahedra, solution) in full evaluation.  Its work units are
-//   (version, direction, tetrahedron, batch of 64 voxel rows); the 4 waves take
-//   the units round robin.  A wave computes the exact x-span of 64 rows (one
-//   row per lane), prefix-sums the span lengths, and then sweeps the voxels of
-//   those rows 64 at a time, adjacent lanes on adjacent voxels, so that both
-//   the streamed own-image reads and the trilinear gathers from the other
-//   image are coalesced.
+//   one workgroup per (FOS element, chunk of its affected tetrahedra,
+//   solution) in partial evaluation, or per (chunk of tetrahedra, solution) in
+//   full evaluation.  Its work units are (version, direction, tetrahedron,
+//   batch of 64 voxel rows); each of the 4 waves takes a contiguous range of
+//   units.  A wave computes the exact x-span of 64 rows (one row per lane),
+//   prefix-sums the span lengths, and then sweeps the voxels of those rows 64
+//   at a time, adjacent lanes on adjacent voxels, so that both the streamed
+//   own-image reads and the trilinear gathers from the other image are
+//   coalesced.
 //
 // Exactness: coordinates are lattice integers (1/128 voxel, |u| <= 2^16), so
 // every orientation value and every face function evaluated at a voxel centre
@@ -754,7 +755,7 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 // ------------------------------------------------------------ voxel sweep kernel
 
 // Dissimilarity of every (version, tetrahedron) of one chunk of at most
-// kPartChunk affected tetrahedra (partial evaluation) or of one group of
+// a.pchunk affected tetrahedra (partial evaluation) or of one group of
 // kFullChunk tetrahedra (full evaluation) of one solution: writes
 // simws[((s*G + g)*nver + v)*maxA + i].  Workgroups are numbered (group, chunk,
 // solution) with the solution fastest, so the workgroups resident on an XCD
