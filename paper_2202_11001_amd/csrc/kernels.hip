@@ -984,8 +984,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // unevenly), and within a part the workgroups of one element's solutions stay
 // together.  Elements follow interleaved_group's order within a job.
 // Arguments read through the job table take more registers than kernel
-// arguments; the 7-wave target (at most 72 VGPRs, one 8-byte spill in the
-// set-up) runs small problems 5 % faster than 6 waves without spills.
+// arguments; the 7-wave target (at most 72 VGPRs) ran small problems 5 %
+// faster than 6 waves.
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_batch(
     const EvalArgs* __restrict__ jobs, const int* __restrict__ xcd_off, int n_jobs) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1093,8 +1093,9 @@ __device__ __forceinline__ void finish_body(const EvalArgs& a, int logical, int 
   }
 }
 
-// FP64 geometry per lane: the 3-wave target (at most 168 VGPRs, a few 8-byte
-// spills) ran the finish kernels 20 % faster than 2 waves without spills.
+// FP64 geometry per lane: the 3-wave target (at most 168 VGPRs, with some
+// registers spilled) ran the finish kernels 20 % faster than 2 waves without
+// spills.
 // Each 64-lane workgroup takes kFinishPairs consecutive pairs.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_finish(EvalArgs a, int n_pairs) {
   const int pair = blockIdx.x * kFinishPairs + (threadIdx.x / kFinishLanes);
