@@ -145,9 +145,20 @@ def test_identity_closed_forms_gpu():
 # ---------------------------------------------------------------- partial evaluation
 
 @pytest.mark.parametrize("use_cache", [True, False])
-@pytest.mark.parametrize("which", ["tiny", "random"])
+@pytest.mark.parametrize("which", ["tiny", "random", "tall", "very_tall"])
 def test_partial_single_point(which, use_cache):
-    w = W.tiny() if which == "tiny" else _small_workload()
+    """Every (solution, single-point element) pair against the oracle.  The
+    tall workloads have tetrahedra spanning up to about 60 slices (slice tables
+    built in four rounds of 16 lanes) and about 75 slices (more than the
+    64-slice table: rows enumerated over the bounding box)."""
+    if which == "tiny":
+        w = W.tiny()
+    elif which == "random":
+        w = _small_workload()
+    elif which == "tall":
+        w = _small_workload(dims=(22, 18, 118), mesh=(3, 3, 3), seed=6)
+    else:
+        w = _small_workload(dims=(18, 16, 150), mesh=(3, 3, 3), seed=7)
     rp = oracle_problem(w)
     X = feasible_population(w, rp)
     off, pts = w.fos()
