@@ -671,3 +671,35 @@ def test_uneven_batch_graph_both_levels():
             np.testing.assert_array_equal(o[3][s, elems][None][g_fl == 0], rnv[g_fl == 0])
             assert_objectives_close(o[1][s, elems][None], rnew, flags=g_fl, what=f"level {lv} {w.name} part_new")
             assert_objectives_close(o[0][s, elems][None], rold, what=f"level {lv} {w.name} part_old")
+
+
+def test_stored_batch_keeps_its_chunk():
+    """A stored multi-problem configuration keeps the work split it was stored
+    with: changing a problem's chunk afterwards changes neither what
+    dsm_batch_run computes nor its bits, while a new dsm_eval_partial follows
+    the new chunk."""
+    probs = _uneven_level(0, [0, 4])
+    for *_, job in probs:
+        job["problem"].set_part_chunk(5)
+    batch = dsm.Batch(max_jobs=2)
+    outs = batch.set_jobs([p[-1] for p in probs])
+    batch.run()
+    torch.cuda.synchronize()
+    stored5 = [[t.cpu().numpy().copy() for t in o] for o in outs]
+    single5 = [p[-1]["problem"].eval_partial(p[-1]["X"], p[-1]["fos_off"], p[-1]["fos_pts"], p[-1]["cand"],
+                                             tet_terms_in=p[-1]["tet_terms_in"], voxel_count=True) for p in probs]
+    for *_, job in probs:
+        job["problem"].set_part_chunk(8)
+    batch.run()
+    single8 = [p[-1]["problem"].eval_partial(p[-1]["X"], p[-1]["fos_off"], p[-1]["fos_pts"], p[-1]["cand"],
+                                             tet_terms_in=p[-1]["tet_terms_in"], voxel_count=True) for p in probs]
+    torch.cuda.synchronize()
+    for o, s5, s8, st5 in zip(outs, single5, single8, stored5):
+        for a, b, c, d in zip(o, s5, s8, st5):
+            a, b, c = a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+            np.testing.assert_array_equal(a, d)      # the stored run repeats itself bit for bit
+            np.testing.assert_array_equal(a, b)      # and equals a launch at the stored chunk
+            if a.dtype.kind == "f":
+                np.testing.assert_allclose(c, a, rtol=1e-7, atol=1e-12)
+            else:
+                np.testing.assert_array_equal(c, a)  # flags and counts do not depend on the chunk
