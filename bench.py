@@ -542,7 +542,8 @@ def uneven_batch(steps=3, warmup=1):
     pyramid level: the 12 problems of workloads.UNEVEN_PROBLEMS at the 2x
     box-averaged level and at full resolution (population handed off by
     x -> 2x + 0.5); per level, all single-point FOS elements of every
-    solution.  Each problem's image row pitch is autotuned first.  Timed three
+    solution.  Each problem's image row pitch, chunk and row order are
+    autotuned first (the row order also on the whole batch).  Timed three
     ways: one dsm_eval_partial_batch call per level (job table uploaded per
     call), one dsm_batch_run per level (stored configuration), and one HIP
     graph holding both levels' runs (a whole two-level generation)."""
@@ -589,8 +590,26 @@ def uneven_batch(steps=3, warmup=1):
             gp.eval_full(Xd, tet_terms=cache)
             gp.autotune_pitch(Xd, offd, ptsd, cd, tet_terms_in=cache)
             gp.autotune_chunk(Xd, offd, ptsd, cd, tet_terms_in=cache)
+            gp.autotune_row_order(Xd, offd, ptsd, cd, tet_terms_in=cache)
             jobs.append(dict(problem=gp, X=Xd, fos_off=offd, fos_pts=ptsd, cand=cd, tet_terms_in=cache))
         log(f"uneven level {level}: {n} problems set up in {time.perf_counter() - t0:.1f} s")
+        # A problem timed alone fills the GPU less than the fused launch does, so
+        # the row orders are also compared on the whole stored batch: as tuned
+        # per problem, all by slice, all by slice pair; the fastest is kept.
+        tuned = [j["problem"].row_order for j in jobs]
+        choice = {}
+        for name, orders in (("per problem", tuned), ("by slice", [0] * n), ("by slice pair", [1] * n)):
+            for j, o in zip(jobs, orders):
+                j["problem"].set_row_order(o)
+            trial = dsm.Batch(max_jobs=n)
+            trial.set_jobs(jobs)
+            choice[name] = (timed(trial.run), orders)
+            del trial
+        best_name = min(choice, key=lambda k: choice[k][0])
+        for j, o in zip(jobs, choice[best_name][1]):
+            j["problem"].set_row_order(o)
+        log(f"uneven level {level}: row orders on the stored batch (ms) "
+            f"{ {k: round(v[0], 3) for k, v in choice.items()} } -> {best_name}")
         batch = dsm.Batch(max_jobs=n)
         outs = batch.eval_partial(jobs)
         torch.cuda.synchronize()
@@ -609,6 +628,7 @@ def uneven_batch(steps=3, warmup=1):
                               "algorithmic_GBps": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9,
                               "roofline_frac": samples * BYTES_PER_SAMPLE / (ms_run / 1e3) / 1e9 / HBM_PEAK_GBS,
                               "part_chunks": [j["problem"].part_chunk for j in jobs],
+                              "row_orders": [j["problem"].row_order for j in jobs],
                               "row_pitches": [j["problem"].pitch for j in jobs]})
         keep.append((batch, stored, jobs))
     # both levels in one captured graph
@@ -742,9 +762,11 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: 2 steps, no warmup, no CPU leg")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the copy kernel of known size")
     ap.add_argument("--no-screen", action="store_true", help="skip the surrogate-screened step")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch and chunk")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default image row pitch, chunk and row order")
     ap.add_argument("--part-chunk", type=int, default=0,
                     help="affected tetrahedra per workgroup (4..8) instead of autotuning it")
+    ap.add_argument("--row-order", type=int, default=-1, choices=(-1, 0, 1),
+                    help="row order of the sweep (0 by slice, 1 by slice pair; -1: autotuned)")
     ap.add_argument("--multires", type=int, nargs=2, default=None, metavar=("G1", "G2"),
                     help="multi-resolution run: G1 coarse then G2 fine generations (reported separately)")
     ap.add_argument("--tet-fos", action="store_true",
@@ -827,8 +849,13 @@ def main():
         if not args.part_chunk:
             best, table = gp.autotune_chunk(Xd, offd, ptsd, candd, tet_terms_in=cache)
             log(f"affected tetrahedra per workgroup autotune (ms per step): {table} -> {best}")
+        if args.row_order < 0:
+            best, table = gp.autotune_row_order(Xd, offd, ptsd, candd, tet_terms_in=cache)
+            log(f"row order autotune (0 by slice, 1 by slice pair; ms per step): {table} -> {best}")
     if args.part_chunk:
         gp.set_part_chunk(args.part_chunk)
+    if args.row_order >= 0:
+        gp.set_row_order(args.row_order)
     out = (torch.empty((S, F, 3), dtype=torch.float64, device=dev), torch.empty((S, F, 3), dtype=torch.float64, device=dev),
            torch.empty((S, F), dtype=torch.int32, device=dev), torch.empty((S, F), dtype=torch.int32, device=dev))
     gp.eval_partial(Xd, offd, ptsd, candd, tet_terms_in=cache, out=out)
@@ -884,7 +911,7 @@ def main():
         "config": {"workload": w.name + f", meshes {w.mesh}, population {S}, {F} single-point FOS elements per step",
                    "partial_evals_per_step": S * F, "voxel_samples_per_step": samples},
         "voxel_samples_per_s": samples_per_s,
-        "tuning": {"image_row_pitch": gp.pitch, "part_chunk": gp.part_chunk},
+        "tuning": {"image_row_pitch": gp.pitch, "part_chunk": gp.part_chunk, "row_order": gp.row_order},
         # "bound" names the roofline the fraction is taken against (HBM, on
         # algorithmic bytes); "limiter" is what the kernel's counters show
         # limits it: the vector-memory (texture) address and data path, with

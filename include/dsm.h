@@ -274,7 +274,8 @@ dsm_status dsm_autotune_pitch(dsm_problem* p, int32_t S, const float* X, int32_t
  * solution) pair, both directions; the chunk changes no voxel set, flag or
  * count, only the speed (smaller chunks give more, shorter workgroups) and
  * the rounding of the dissimilarity: the waves' per-lane compensated FP32
- * sums follow the work split (relative differences of order 1e-9).
+ * sums follow the work split (relative differences of order 1e-9 for element
+ * sums, up to about 1e-7 for single tetrahedra; at most 4 x 2^-24).
  * dsm_set_part_chunk sets it for later partial evaluations of p (default 8);
  * it neither allocates nor synchronises, but a stored batch configuration
  * keeps the chunk it was stored with.  Errors: DSM_ERR_ARG for a chunk
@@ -293,6 +294,34 @@ int32_t dsm_get_part_chunk(const dsm_problem* p);
 dsm_status dsm_autotune_chunk(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
                               const int32_t* fos_pts, const float* cand, const double* tet_terms_in, int32_t n_chunk,
                               const int32_t* chunks, float* ms_out, int32_t* best);
+
+/* Order of the voxel rows that the sweep of the objectives' dissimilarity
+ * term (Sec. 2.3.1) visits within a tetrahedron.  DSM_ROWS_BY_SLICE (the
+ * default): y-major within each voxel slice z.  DSM_ROWS_BY_SLICE_PAIR: slices
+ * taken in pairs (z, z + 1) whose rows alternate, (y, z), (y, z + 1),
+ * (y + 1, z), ..., so the two rows of one y read the same elements of the own
+ * image (which holds the values at z and z + 1 side by side): fewer cache
+ * lines per sample on tetrahedra with long rows, more candidate rows to build
+ * on small ones.  The order changes no voxel set, flag or count, only the speed
+ * and the rounding of the dissimilarity (as for the chunk); it applies to full and partial evaluations of p, and a
+ * stored batch configuration keeps the order it was stored with.
+ * dsm_set_row_order neither allocates nor synchronises.  Errors: DSM_ERR_ARG
+ * for another value.  dsm_get_row_order returns the current order (-1 for a
+ * null problem). */
+#define DSM_ROWS_BY_SLICE 0
+#define DSM_ROWS_BY_SLICE_PAIR 1
+dsm_status dsm_set_row_order(dsm_problem* p, int32_t order);
+int32_t dsm_get_row_order(const dsm_problem* p);
+
+/* Autotuning of the row order for one partial-evaluation workload, like
+ * dsm_autotune_chunk: runs the partial evaluation twice on the null stream
+ * with each order (DSM_ROWS_BY_SLICE, then DSM_ROWS_BY_SLICE_PAIR) and records
+ * the second run's time in ms_out host [2] (may be NULL); the faster order is
+ * kept and returned in *best (may be NULL).  Setup-time call: allocates
+ * temporary outputs and synchronises.  Errors as dsm_eval_partial. */
+dsm_status dsm_autotune_row_order(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                                  const int32_t* fos_pts, const float* cand, const double* tet_terms_in,
+                                  float* ms_out, int32_t* best);
 
 /* Test hook for Sec. 2.3.1 rasterisation: owner dev [Dz][Dy][Dx] int32 receives
  * the id of the tetrahedron of grid coordinates Xgrid dev [P][3] whose exact

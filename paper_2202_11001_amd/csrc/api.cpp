@@ -380,6 +380,7 @@ dsm_status dsm_eval_full(dsm_problem* p, int32_t S, const float* X, double* obj,
   a.nver = 1;
   a.terms_out = tet_terms ? tet_terms : p->d_terms;
   a.simws = p->d_simws;
+  a.row_pairs = p->row_order;
   hipEvent_t eb, ee;
   timing_pair(p, eb, ee);
   if ((e = launch_eval(a, eb, ee, st)) != hipSuccess) return hip_fail(e, "evaluation launch");
@@ -427,6 +428,7 @@ dsm_status dsm_eval_partial_masked(dsm_problem* p, int32_t S, const float* X, in
   a.mask = mask;
   a.simws = p->d_simws;
   a.pchunk = p->part_chunk;
+  a.row_pairs = p->row_order;
   a.nchunk = p->nchunk;
   a.cflags = p->d_cflags;
   a.ccount = p->d_ccount;
@@ -553,6 +555,30 @@ dsm_status dsm_autotune_chunk(dsm_problem* p, int32_t S, const float* X, int32_t
   return st;
 }
 
+dsm_status dsm_set_row_order(dsm_problem* p, int32_t order) {
+  g_err.clear();
+  if (!p) return fail(DSM_ERR_ARG, "null argument");
+  if (order != DSM_ROWS_BY_SLICE && order != DSM_ROWS_BY_SLICE_PAIR) return fail(DSM_ERR_ARG, "row order %d unknown", order);
+  p->row_order = order;
+  return DSM_OK;
+}
+
+int32_t dsm_get_row_order(const dsm_problem* p) { return p ? p->row_order : -1; }
+
+dsm_status dsm_autotune_row_order(dsm_problem* p, int32_t S, const float* X, int32_t F, const int32_t* fos_off,
+                                  const int32_t* fos_pts, const float* cand, const double* tet_terms_in,
+                                  float* ms_out, int32_t* best) {
+  g_err.clear();
+  if (!p || !X || !fos_off || !fos_pts || !cand) return fail(DSM_ERR_ARG, "null argument");
+  if (S <= 0 || F <= 0) return fail(DSM_ERR_ARG, "S and F must be positive");
+  const int orders[2] = {DSM_ROWS_BY_SLICE, DSM_ROWS_BY_SLICE_PAIR};
+  int k = -1;
+  const dsm_status st = autotune(p, S, X, F, fos_off, fos_pts, cand, tet_terms_in, 2,
+                                 [&](int i) { return dsm_set_row_order(p, orders[i]); }, ms_out, &k);
+  if (st == DSM_OK && best) *best = p->row_order;
+  return st;
+}
+
 }  // extern "C"
 
 // What the affected-set and ordering launches of one stored job need.
@@ -627,6 +653,7 @@ dsm_status batch_tables(const dsm_batch* b, int n_jobs, const dsm_partial_job* j
     a.mask = q.mask;
     a.simws = p->d_simws;
     a.pchunk = p->part_chunk;
+    a.row_pairs = p->row_order;
     a.nchunk = p->nchunk;
     a.cflags = p->d_cflags;
     a.ccount = p->d_ccount;

@@ -99,6 +99,7 @@ struct EvalArgs {
   double* simws;         // swept dissimilarity workspace of the problem
   int pchunk;            // partial: affected tetrahedra per workgroup
   int nchunk;            // partial: workgroups (chunks of pchunk affected tetrahedra) per group
+  int row_pairs;         // 1: the sweep's rows alternate between the slices of a pair (dsm_set_row_order)
   uint32_t* cflags;      // partial: [S][G][nchunk] constraint flags per chunk
   uint32_t* ccount;      // partial: [S][G][nchunk] candidate voxel count per chunk
 };
@@ -179,6 +180,7 @@ struct dsm_problem {
   uint32_t* d_ccount = nullptr; // [max_S][max_F][nchunk] per-chunk voxel counts
   int part_chunk = dsm::kPartChunk;  // affected tetrahedra per workgroup in partial evaluation
   int nchunk = 1;               // ceil(maxA / part_chunk); the chunk arrays hold ceil(maxA / kMinPartChunk)
+  int row_order = DSM_ROWS_BY_SLICE;  // or DSM_ROWS_BY_SLICE_PAIR (dsm_set_row_order)
   std::vector<float> identity;  // [P][3]
   float* d_ident = nullptr;     // device copy of the undeformed grid [P][3]
   std::vector<hipEvent_t> ev;   // timing event pairs (begin, end)

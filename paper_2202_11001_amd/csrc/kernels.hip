@@ -180,8 +180,9 @@ struct RasterTet {
   int zlo, nz, ylo, ny;  // bounding box (slices, rows)
   int nrows;             // candidate rows
   int sliced;            // 1: candidate rows from the slice table, 0: every bounding-box row
-  unsigned short y0[kMaxSlices];      // first candidate row of each slice
-  unsigned short rs[kMaxSlices + 1];  // exclusive prefix of candidate rows per slice (<= 64 * 512)
+  int pairs;             // slice table: 0 one row group per slice, 1 one per pair of slices
+  unsigned short y0[kMaxSlices];      // first candidate row (its y) of each row group
+  unsigned short rs[kMaxSlices + 1];  // exclusive prefix of candidate rows per row group (<= 64 * 512)
 };
 
 // Conservative row range [ya, yb] of the cross-section of the tetrahedron
@@ -290,32 +291,57 @@ __device__ void setup_task(const float* xo, const float* xt, const int D[3], int
   }
 }
 
-__device__ void setup_slices(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
+// Candidate rows of the row group that starts at slice k: slice k alone
+// (pairs = 0), or slices k and k + 1 for even k (pairs = 1), whose candidate
+// rows alternate between the two slices over the union of their row ranges.
+// [ya, yb] is slice k's row range; with pairs, lane ^ 1 holds slice k + 1's
+// (called on both lanes).  Returns the group's first y in gya and its number of
+// candidate rows in cnt (0 on lanes that start no group).
+__device__ __forceinline__ void group_rows(int ya, int yb, int k, int nz, int pairs, int& gya, int& cnt) {
+  int lo = ya, hi = yb, m = 1;
+  if (pairs) {
+    const int oya = __shfl_xor(ya, 1, 64), oyb = __shfl_xor(yb, 1, 64);
+    if (k + 1 < nz) {
+      m = 2;
+      if (oyb >= oya) {
+        lo = yb >= ya ? min(ya, oya) : oya;
+        hi = yb >= ya ? max(yb, oyb) : oyb;
+      }
+    }
+  }
+  gya = hi >= lo ? lo : 0;
+  cnt = (k & pairs) || k >= nz ? 0 : m * max(0, hi - lo + 1);
+}
+
+__device__ void setup_slices(const float* xo, const float* xt, const int D[3], int lane, int pairs, RasterTet& rt) {
   const int nz = rt.nz;
   if (nz <= kMaxSlices) {
-    // candidate rows of slice zlo + lane, prefix-summed over the slices
-    int cnt = 0, ya = 0;
+    // candidate rows of the row group starting at slice zlo + lane,
+    // prefix-summed over the groups
+    int ya = 0, yb = -1;
     if (lane < nz) {
       float L[4][3];
       for (int q = 0; q < 4; ++q)
         for (int c = 0; c < 3; ++c) L[q][c] = (xo[3 * q + c] + 0.5f) * 128.f;
-      int yb;
       slice_rows(L, rt.zlo + lane, D[1], ya, yb);
-      cnt = max(0, yb - ya + 1);
     }
+    int gya, cnt;
+    group_rows(ya, yb, lane, nz, pairs, gya, cnt);
     const int incl = wave_incl_scan(cnt);
-    if (lane < nz) {
-      rt.rs[lane] = (unsigned short)(incl - cnt);
-      rt.y0[lane] = (unsigned short)ya;
+    if (lane < nz && !(lane & pairs)) {
+      rt.rs[lane >> pairs] = (unsigned short)(incl - cnt);
+      rt.y0[lane >> pairs] = (unsigned short)gya;
     }
     if (lane == 63) {
-      rt.rs[min(nz, kMaxSlices)] = (unsigned short)incl;
+      rt.rs[(nz + pairs) >> pairs] = (unsigned short)incl;
       rt.nrows = incl;
       rt.sliced = 1;
+      rt.pairs = pairs;
     }
   } else if (lane == 0) {
     rt.nrows = nz * rt.ny;
     rt.sliced = 0;
+    rt.pairs = 0;
   }
   if (lane < 3) {
     const int r = lane;
@@ -328,7 +354,8 @@ __device__ void setup_slices(const float* xo, const float* xt, const int D[3], i
 // group; all 16 lanes call it) for tetrahedra of few slices: slices in rounds of
 // 16, the candidate-row prefix carried from round to round.  Returns the number
 // of rows (on every lane of the group).
-__device__ int setup_slices16(const float* xo, const float* xt, const int D[3], int lane, int sub, RasterTet& rt) {
+__device__ int setup_slices16(const float* xo, const float* xt, const int D[3], int lane, int sub, int pairs,
+                              RasterTet& rt) {
   const int nz = rt.nz;
   int nrows;
   if (nz <= kMaxSlices) {
@@ -338,30 +365,30 @@ __device__ int setup_slices16(const float* xo, const float* xt, const int D[3], 
     int carry = 0;
     for (int base = 0; base < nz; base += 16) {
       const int k = base + sub;
-      int cnt = 0, ya = 0;
-      if (k < nz) {
-        int yb;
-        slice_rows(L, rt.zlo + k, D[1], ya, yb);
-        cnt = max(0, yb - ya + 1);
-      }
+      int ya = 0, yb = -1;
+      if (k < nz) slice_rows(L, rt.zlo + k, D[1], ya, yb);
+      int gya, cnt;
+      group_rows(ya, yb, k, nz, pairs, gya, cnt);
       const int incl = row16_incl_scan(cnt);
-      if (k < nz) {
-        rt.rs[k] = (unsigned short)(carry + incl - cnt);
-        rt.y0[k] = (unsigned short)ya;
+      if (k < nz && !(k & pairs)) {
+        rt.rs[k >> pairs] = (unsigned short)(carry + incl - cnt);
+        rt.y0[k >> pairs] = (unsigned short)gya;
       }
       carry += __shfl(incl, lane | 15, 64);
     }
     nrows = carry;
     if (sub == 0) {
-      rt.rs[nz] = (unsigned short)carry;
+      rt.rs[(nz + pairs) >> pairs] = (unsigned short)carry;
       rt.nrows = carry;
       rt.sliced = 1;
+      rt.pairs = pairs;
     }
   } else {
     nrows = nz * rt.ny;
     if (sub == 0) {
       rt.nrows = nrows;
       rt.sliced = 0;
+      rt.pairs = 0;
     }
   }
   if (sub < 3) {
@@ -375,7 +402,7 @@ __device__ int setup_slices16(const float* xo, const float* xt, const int D[3], 
 __device__ void setup_raster(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
   if (lane < kSetupTasks) setup_task(xo, xt, D, lane, rt);
   wave_sync();
-  setup_slices(xo, xt, D, lane, rt);
+  setup_slices(xo, xt, D, lane, 0, rt);
 }
 
 // Exact x-span [x0, x1] (inclusive; empty if x0 > x1) of voxel row (y, z).
@@ -423,37 +450,50 @@ struct WaveRows {
 };
 
 // Computes the spans of rows [64 b, 64 b + 64) of rt, stores the non-empty
-// ones compacted (in row order) in wr, and returns the number of voxels.  Row r
-// is y-major within a slice: y = ylo + r % ny.  The linear index stored for a
-// span's first voxel (x0, y, z) is base + z sz + y sy + x0, its mapped position
+// ones compacted (in row order) in wr, and returns the number of voxels.  With
+// a slice table, row r is y-major within its row group: y = y0 + (r - rs) of
+// the group's slice, or, for a pair of slices, rows alternate between them,
+// (y0, z), (y0, z + 1), (y0 + 1, z), ...; every bounding-box row otherwise,
+// y = ylo + r % ny.  The linear index of a span's first voxel (x0, y, z) is
+// lin = base + z sz + y sy + x0; wr stores lin minus the row's start, or with
+// kOwnBytes the byte offset of its value in the bordered z-pair image minus 8
+// times the start (the second row of a pair reads the second value of the
+// element that holds the first row's voxel, so the two rows share the own
+// image's cache lines).  The mapped position of the first voxel is
 // P0 + J (x0, y, z) + shift.  *my_start receives the first voxel index of this
 // lane's row, or a large negative value if it is empty.
+template <bool kOwnBytes>
 __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int sy, int sz,
                                           int base, float shift, WaveRows& wr, int* my_start) {
   const int r0 = b * 64, r = r0 + lane;
   int len = 0, lin = 0;
   float bx = 0.f, by = 0.f, bz = 0.f;
-  int y, z;
+  int y, z, h = 0;
   if (rt.sliced) {
-    // lane k holds slice k's first candidate row and its y; row r lies in the
-    // last slice that starts at or before r: the slice of the unit's first
-    // row, advanced over the slices that start inside the unit (in order)
-    const int nz = rt.nz;
-    const int rsk = lane < nz ? (int)rt.rs[lane] : 0x7fffffff;
-    const int y0k = lane < nz ? (int)rt.y0[lane] : 0;
-    const int jb = __popcll(__ballot(rsk <= r0)) - 1;  // rs[0] = 0
-    y = __builtin_amdgcn_readlane(y0k, jb) + (r - __builtin_amdgcn_readlane(rsk, jb));
-    z = rt.zlo + jb;
+    // lane k holds row group k's first candidate row and first y; row r lies
+    // in the last group that starts at or before r: the group of the unit's
+    // first row, advanced over the groups that start inside the unit (in order)
+    const int nz = rt.nz, pairs = rt.pairs, ng = (nz + pairs) >> pairs;
+    const int rsk = lane < ng ? (int)rt.rs[lane] : 0x7fffffff;
+    const int y0k = lane < ng ? (int)rt.y0[lane] : 0;
+    int k = __popcll(__ballot(rsk <= r0)) - 1;  // rs[0] = 0
+    int s = __builtin_amdgcn_readlane(rsk, k), ys = __builtin_amdgcn_readlane(y0k, k);
     unsigned long long inside = __ballot(rsk > r0 && rsk < r0 + 64);
     while (inside) {
-      const int k = __builtin_ctzll(inside);
+      const int kk = __builtin_ctzll(inside);
       inside &= inside - 1;
-      const int s = __builtin_amdgcn_readlane(rsk, k);
-      if (r >= s) {
-        y = __builtin_amdgcn_readlane(y0k, k) + (r - s);
-        z = rt.zlo + k;
+      const int ss = __builtin_amdgcn_readlane(rsk, kk);
+      if (r >= ss) {
+        s = ss;
+        ys = __builtin_amdgcn_readlane(y0k, kk);
+        k = kk;
       }
     }
+    const int two = pairs && 2 * k + 1 < nz ? 1 : 0;  // the group is a pair of slices
+    const int rr = r - s;
+    h = rr & two;
+    y = ys + (rr >> two);
+    z = rt.zlo + (k << pairs) + h;
   } else {
     y = rt.ylo + r % rt.ny;
     z = rt.zlo + r / rt.ny;
@@ -464,6 +504,7 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
     if (x1 >= x0) {
       len = x1 - x0 + 1;
       lin = base + z * sz + y * sy + x0;
+      if (kOwnBytes) lin = (lin - h * sz) * 8 + 4 * h;
       const double v[3] = {(double)x0, (double)y, (double)z};
       bx = (float)(rt.P0[0] + rt.J[0][0] * v[0] + rt.J[0][1] * v[1] + rt.J[0][2] * v[2] + shift);
       by = (float)(rt.P0[1] + rt.J[1][0] * v[0] + rt.J[1][1] * v[1] + rt.J[1][2] * v[2] + shift);
@@ -477,7 +518,7 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
   wave_sync();
   if (len > 0) {
     wr.row[slot].start = start;
-    wr.row[slot].rec = make_float4(__int_as_float(lin - start), bx, by, bz);
+    wr.row[slot].rec = make_float4(__int_as_float(kOwnBytes ? lin - 8 * start : lin - start), bx, by, bz);
   }
   wave_sync();
   *my_start = len > 0 ? start : -(1 << 30);
@@ -583,9 +624,9 @@ __device__ __forceinline__ void sweep_pair(const WaveRows& wr, const SampleCtx& 
   const int ea = TAIL ? min(qa, nvox - 1) : qa, eb = TAIL ? min(qb, nvox - 1) : qb;
   const RowRec ra = wr.row[r0], rb = wr.row[r1];
   const float foa = (float)(ea - ra.start), fob = (float)(eb - rb.start);
-  const float ava = load1(sc.own, (__float_as_int(ra.rec.x) + ea) << 3);
+  const float ava = load1(sc.own, __float_as_int(ra.rec.x) + (ea << 3));
   const Taps ta = load_taps(sc, fmaf(jx, foa, ra.rec.y), fmaf(jy, foa, ra.rec.z), fmaf(jz, foa, ra.rec.w));
-  const float avb = load1(sc.own, (__float_as_int(rb.rec.x) + eb) << 3);
+  const float avb = load1(sc.own, __float_as_int(rb.rec.x) + (eb << 3));
   const Taps tb = load_taps(sc, fmaf(jx, fob, rb.rec.y), fmaf(jy, fob, rb.rec.z), fmaf(jz, fob, rb.rec.w));
   const float ca = contrib_of(sc, ava, ta);
   const float cb = contrib_of(sc, avb, tb);
@@ -604,7 +645,7 @@ __device__ __forceinline__ void sweep_one(const WaveRows& wr, const SampleCtx& s
   const int ea = min(qa, nvox - 1);
   const RowRec ra = wr.row[r0];
   const float foa = (float)(ea - ra.start);
-  const float ava = load1(sc.own, (__float_as_int(ra.rec.x) + ea) << 3);
+  const float ava = load1(sc.own, __float_as_int(ra.rec.x) + (ea << 3));
   const Taps ta = load_taps(sc, fmaf(jx, foa, ra.rec.y), fmaf(jy, foa, ra.rec.z), fmaf(jz, foa, ra.rec.w));
   const float ca = contrib_of(sc, ava, ta);
   const float c = qa < nvox ? ca : 0.f;
@@ -869,7 +910,7 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     if (e < nent && s_units[e]) {
       int own;
       const float* xyz = entry_xyz(e, own);
-      nunits = (setup_slices16(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, sub, s_rts[e]) + 63) >> 6;
+      nunits = (setup_slices16(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, sub, a.row_pairs, s_rts[e]) + 63) >> 6;
     }
     wave_sync();
     if (e < nent && sub == 0) s_units[e] = nunits;
@@ -917,7 +958,7 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     }
     const int b = u - uniform(s_units[cur]);
     int my_start;
-    const int nvox = uniform(build_rows(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
+    const int nvox = uniform(build_rows<true>(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
     int carry = 0;  // non-empty rows that start before the current chunk
     for (int q0 = 0; q0 < nvox; q0 += 128) {
       // voxels q0 + lane and q0 + 64 + lane: rows starting in this pair of
@@ -1297,7 +1338,7 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
   for (int b = wave; b < nb; b += kWaves) {
     WaveRows& wr = rows[wave];
     int my_start;
-    const int nvox = build_rows(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
+    const int nvox = build_rows<false>(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
     int carry = 0;
     for (int q0 = 0; q0 < nvox; q0 += 64) {
       wr.marker[lane] = 0;
@@ -1387,7 +1428,7 @@ __global__ __launch_bounds__(kWG) void k_transform(DevProblem pr, int own, const
   for (int b = wave; b < nb; b += kWaves) {
     WaveRows& wr = rows[wave];
     int my_start;
-    const int nvox = build_rows(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
+    const int nvox = build_rows<false>(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
     int carry = 0;
     for (int q0 = 0; q0 < nvox; q0 += 64) {
       wr.marker[lane] = 0;

@@ -128,6 +128,7 @@ dsm_status dsm_eval_partial_noalloc(dsm_problem* p, int32_t S, const float* X, i
   a.mask = nullptr;
   a.simws = (double*)(base + L.simws);
   a.pchunk = p->part_chunk;
+  a.row_pairs = p->row_order;
   a.nchunk = nchunk;
   a.cflags = (uint32_t*)(base + L.cflags);
   a.ccount = (uint32_t*)(base + L.ccount);

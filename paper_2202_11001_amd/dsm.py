@@ -116,6 +116,9 @@ def lib():
             "dsm_set_part_chunk": ([V, I], I),
             "dsm_get_part_chunk": ([V], I),
             "dsm_autotune_chunk": ([V, I, V, I, V, V, V, V, I, V, V, V], I),
+            "dsm_set_row_order": ([V, I], I),
+            "dsm_get_row_order": ([V], I),
+            "dsm_autotune_row_order": ([V, I, V, I, V, V, V, V, V, V], I),
             "dsm_surrogate_create": ([V, V], I),
             "dsm_surrogate_destroy": ([V], I),
             "dsm_surrogate_last_error": ([], C.c_char_p),
@@ -692,6 +695,27 @@ class Problem:
         if chunks is None:
             cl = list(range(4, 9))
         return int(best.value), {int(c): float(t) for c, t in zip(cl, ms)}
+
+    ROWS_BY_SLICE, ROWS_BY_SLICE_PAIR = 0, 1
+
+    @property
+    def row_order(self):
+        """Row order of the sweep: ROWS_BY_SLICE (0) or ROWS_BY_SLICE_PAIR (1)."""
+        return int(lib().dsm_get_row_order(self._h))
+
+    def set_row_order(self, order):
+        """Sets the row order of later evaluations (0 by slice, 1 by slice pair)."""
+        _check(lib().dsm_set_row_order(self._h, int(order)))
+
+    def autotune_row_order(self, X, fos_off, fos_pts, cand, tet_terms_in=None):
+        """Times the partial evaluation with each row order and keeps the
+        faster; returns (best order, {order: ms})."""
+        S, F = X.shape[0], fos_off.shape[0] - 1
+        ms = np.zeros(2, np.float32)
+        best = C.c_int32()
+        _check(lib().dsm_autotune_row_order(self._h, S, _dptr(X), F, _dptr(fos_off), _dptr(fos_pts), _dptr(cand),
+                                            _dptr(tet_terms_in), _np_ptr(ms), C.byref(best)))
+        return int(best.value), {0: float(ms[0]), 1: float(ms[1])}
 
     def _default_pitch_candidates(self):
         Dx = self.dims[0]

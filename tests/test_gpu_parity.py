@@ -106,8 +106,11 @@ def test_fold_flags_bitexact():
 
 # ---------------------------------------------------------------- full evaluation
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("which", ["tiny", "random", "random_aniso"])
-def test_full_eval(which):
+def test_full_eval(which, order):
+    """Full evaluation against the oracle, with rows swept slice by slice and
+    in slice pairs."""
     if which == "tiny":
         w = W.tiny()
     elif which == "random":
@@ -117,8 +120,9 @@ def test_full_eval(which):
     rp = oracle_problem(w)
     X = feasible_population(w, rp)
     X[0] = np.stack([rp.identity(), rp.identity()])
-    _say(f"full eval {w.name} S={len(X)}")
+    _say(f"full eval {w.name} S={len(X)} row order {order}")
     gp = _gpu_problem(w, len(X))
+    gp.set_row_order(order)
     terms = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
     obj, flags = gp.eval_full(_t(X), tet_terms=terms)
     torch.cuda.synchronize()
@@ -144,13 +148,17 @@ def test_identity_closed_forms_gpu():
 
 # ---------------------------------------------------------------- partial evaluation
 
-@pytest.mark.parametrize("use_cache", [True, False])
-@pytest.mark.parametrize("which", ["tiny", "random", "tall", "very_tall"])
-def test_partial_single_point(which, use_cache):
+_SINGLE_POINT_CASES = ([(w, c, 0) for w in ("tiny", "random", "tall", "very_tall") for c in (True, False)] +
+                       [(w, True, 1) for w in ("tiny", "random", "tall", "very_tall")])
+
+
+@pytest.mark.parametrize("which,use_cache,order", _SINGLE_POINT_CASES)
+def test_partial_single_point(which, use_cache, order):
     """Every (solution, single-point element) pair against the oracle.  The
     tall workloads have tetrahedra spanning up to about 60 slices (slice tables
-    built in four rounds of 16 lanes) and about 75 slices (more than the
-    64-slice table: rows enumerated over the bounding box)."""
+    built in four rounds of 16 lanes, and with order 1 slice pairs within each
+    round, the last pair of an odd count a single slice) and about 75 slices
+    (more than the 64-slice table: rows enumerated over the bounding box)."""
     if which == "tiny":
         w = W.tiny()
     elif which == "random":
@@ -163,10 +171,11 @@ def test_partial_single_point(which, use_cache):
     X = feasible_population(w, rp)
     off, pts = w.fos()
     cand = w.candidates(X, off, pts)
-    _say(f"partial {w.name} S={len(X)} F={len(off) - 1} cache={use_cache}")
+    _say(f"partial {w.name} S={len(X)} F={len(off) - 1} cache={use_cache} row order {order}")
     robj, rflags, rterms, _ = rp.eval_full(X, want_terms=True)
     rold, rnew, rfl, rnv = rp.eval_partial(X, off, pts, cand, tet_terms=rterms if use_cache else None)
     gp = _gpu_problem(w, len(X))
+    gp.set_row_order(order)
     Xd = _t(X)
     cache = None
     if use_cache:
@@ -392,6 +401,7 @@ def test_uneven_batch_one_launch(level):
         cand = w.candidates(X, off, pts)
         gp = _gpu_problem(w, len(X))
         gp.set_part_chunk(4 + len(probs) % 5)  # every problem its own work split
+        gp.set_row_order(len(probs) % 2)        # and rows by slice or by slice pair
         probs.append((w, rp, X, off, pts, cand, gp))
         Xd = _t(X)
         cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
@@ -449,11 +459,22 @@ def test_layout_pitch_changes_nothing():
         gp.set_pitch(Dx + 1)
 
 
+# Two work splits or row orders sum the same FP32 contributions in different
+# orders.  Each per-lane compensated FP32 sum is within 2u|S| of the exact sum
+# of its (positive) contributions, u = 2^-24, and the lanes' sums are combined
+# in FP64, so each result is within 2u relative of the exact sum of the same
+# contributions and two splits differ by at most 4u = 2.4e-7 relative (plus
+# the second-order terms of compensated summation and the FP64 combination:
+# the 25 % margin).
+_SPLIT_RTOL = 4 * 2.0 ** -24 * 1.25
+
+
 def test_part_chunk_changes_no_voxel_set():
     """The affected tetrahedra per workgroup (4..8) change no flag and no voxel
     count, and the terms only by rounding: the voxels a wave sums in its
     per-lane compensated FP32 sums follow the work split (measured differences
-    below 4e-9 relative); the chunk autotuner keeps one of its candidates; the
+    below 4e-9 relative for the element sums, 1e-7 for single tetrahedra;
+    bound _SPLIT_RTOL); the chunk autotuner keeps one of its candidates; the
     allocation-free entry point follows the problem's chunk bit for bit."""
     w = W.batched()
     rp = oracle_problem(w)
@@ -482,7 +503,7 @@ def test_part_chunk_changes_no_voxel_set():
         np.testing.assert_array_equal(got[2], ref8[2])
         np.testing.assert_array_equal(got[3], ref8[3])
         for a, b in zip(got[:2], ref8[:2]):
-            np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
+            np.testing.assert_allclose(a, b, rtol=_SPLIT_RTOL, atol=1e-12)
         for a, b in zip(run(noalloc=True), got):
             np.testing.assert_array_equal(a, b)
     for bad in (3, 9):
@@ -491,6 +512,48 @@ def test_part_chunk_changes_no_voxel_set():
     assert gp.part_chunk == 8
     best, table = gp.autotune_chunk(Xd, offd, ptsd, cd, tet_terms_in=cache, chunks=[5, 8])
     assert best in (5, 8) and gp.part_chunk == best and sorted(table) == [5, 8] and all(t > 0 for t in table.values())
+
+
+def test_row_order_changes_no_voxel_set():
+    """Sweeping rows in slice pairs instead of slice by slice changes no flag
+    and no voxel count, full or partial, and the terms only by rounding (the
+    per-lane FP32 sums follow the order); the allocation-free entry point
+    follows the problem's order bit for bit; the autotuner keeps one order."""
+    w = W.batched()
+    rp = oracle_problem(w)
+    X = feasible_population(w, rp)[:48]
+    off, pts = w.fos()
+    cand = w.candidates(X, off, pts)
+    gp = _gpu_problem(w, len(X))
+    assert gp.row_order == 0
+    Xd, offd, ptsd, cd = _t(X), _t(off), _t(pts), _t(cand)
+    cache = torch.empty((len(X), gp.T, 3), dtype=torch.float64, device=DEV)
+
+    def run(noalloc=False):
+        obj, fl = gp.eval_full(Xd, tet_terms=cache)
+        f = gp.eval_partial_noalloc if noalloc else gp.eval_partial
+        res = f(Xd, offd, ptsd, cd, tet_terms_in=cache, voxel_count=True)
+        torch.cuda.synchronize()
+        return [obj.cpu().numpy(), fl.cpu().numpy(), cache.cpu().numpy()] + [r.cpu().numpy() for r in res]
+
+    ref = run()
+    for order in (1, 0, 1):
+        gp.set_row_order(order)
+        assert gp.row_order == order
+        _say(f"row order {order}")
+        got = run()
+        for i in (1, 5, 6):  # full flags, partial flags, voxel counts
+            np.testing.assert_array_equal(got[i], ref[i])
+        for i in (0, 2, 3, 4):  # full objectives, terms, part_old, part_new
+            np.testing.assert_allclose(got[i], ref[i], rtol=_SPLIT_RTOL, atol=1e-12)
+        for a, b in zip(run(noalloc=True), got):
+            np.testing.assert_array_equal(a, b)
+    for bad in (-1, 2):
+        with pytest.raises(dsm.DsmError):
+            gp.set_row_order(bad)
+    assert gp.row_order == 1
+    best, table = gp.autotune_row_order(Xd, offd, ptsd, cd, tet_terms_in=cache)
+    assert best in (0, 1) and gp.row_order == best and sorted(table) == [0, 1] and all(t > 0 for t in table.values())
 
 
 def ref_pitch_default(Dx):
@@ -674,13 +737,14 @@ def test_uneven_batch_graph_both_levels():
 
 
 def test_stored_batch_keeps_its_chunk():
-    """A stored multi-problem configuration keeps the work split it was stored
-    with: changing a problem's chunk afterwards changes neither what
-    dsm_batch_run computes nor its bits, while a new dsm_eval_partial follows
-    the new chunk."""
+    """A stored multi-problem configuration keeps the work split and row order
+    it was stored with: changing a problem's chunk and row order afterwards
+    changes neither what dsm_batch_run computes nor its bits, while a new
+    dsm_eval_partial follows the new settings."""
     probs = _uneven_level(0, [0, 4])
     for *_, job in probs:
         job["problem"].set_part_chunk(5)
+        job["problem"].set_row_order(1)
     batch = dsm.Batch(max_jobs=2)
     outs = batch.set_jobs([p[-1] for p in probs])
     batch.run()
@@ -690,6 +754,7 @@ def test_stored_batch_keeps_its_chunk():
                                              tet_terms_in=p[-1]["tet_terms_in"], voxel_count=True) for p in probs]
     for *_, job in probs:
         job["problem"].set_part_chunk(8)
+        job["problem"].set_row_order(0)
     batch.run()
     single8 = [p[-1]["problem"].eval_partial(p[-1]["X"], p[-1]["fos_off"], p[-1]["fos_pts"], p[-1]["cand"],
                                              tet_terms_in=p[-1]["tet_terms_in"], voxel_count=True) for p in probs]
@@ -700,6 +765,6 @@ def test_stored_batch_keeps_its_chunk():
             np.testing.assert_array_equal(a, d)      # the stored run repeats itself bit for bit
             np.testing.assert_array_equal(a, b)      # and equals a launch at the stored chunk
             if a.dtype.kind == "f":
-                np.testing.assert_allclose(c, a, rtol=1e-7, atol=1e-12)
+                np.testing.assert_allclose(c, a, rtol=_SPLIT_RTOL, atol=1e-12)
             else:
                 np.testing.assert_array_equal(c, a)  # flags and counts do not depend on the chunk
