@@ -925,7 +925,7 @@ def main():
                      "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source, scaled by a copy "
                                        "kernel (profiles/k_sweep_partial_clinical_traffic.txt); not re-measured "
                                        "in this run" if traffic else None,
-                     "kernel": "k_sweep<1> (partial-evaluation voxel sweep)", "kernel_ms": kms,
+                     "kernel": f"k_sweep<1, {gp.row_order}> (partial-evaluation voxel sweep)", "kernel_ms": kms,
                      "algorithmic_bytes_per_launch": samples * BYTES_PER_SAMPLE,
                      "kernel_source_sha256_16": kernel_source_hash()},
     }

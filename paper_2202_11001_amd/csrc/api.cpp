@@ -604,11 +604,20 @@ struct dsm_batch {
   EvalArgs* d_set_jobs = nullptr;
   int* d_set_off = nullptr;
   std::vector<BatchSetJob> set;
-  int set_n = 0, set_per_xcd = 0, set_total_finish = 0;
+  int set_n = 0, set_per_xcd = 0, set_total_finish = 0, set_rows = 0;
   size_t set_lds = 0;
 };
 
 namespace {
+
+// Row orders of a batch's jobs for launch_eval_batch: 0 all by slice, 1 all
+// by slice pair, 2 both.
+int batch_rows(const std::vector<EvalArgs>& args) {
+  bool by_slice = false, by_pair = false;
+  for (const EvalArgs& a : args)
+    if (a.S > 0 && a.G > 0) (a.row_pairs ? by_pair : by_slice) = true;
+  return by_slice && by_pair ? 2 : (by_pair ? 1 : 0);
+}
 
 // Validates the jobs and fills their evaluation arguments, the per-XCD slot
 // offsets of the sweep (a job of n workgroups takes ceil(n / 8) slots on each
@@ -729,7 +738,8 @@ dsm_status dsm_eval_partial_batch(dsm_batch* b, int32_t n_jobs, const dsm_partia
   if (e == hipSuccess) e = hipEventRecord(b->copied, st);
   if (e != hipSuccess) return hip_fail(e, "job table copy");
   b->pending = true;
-  if ((e = launch_eval_batch(b->d_jobs, b->d_off, n_jobs, off[n_jobs], foff[n_jobs], lds, st)) != hipSuccess)
+  if ((e = launch_eval_batch(b->d_jobs, b->d_off, n_jobs, off[n_jobs], foff[n_jobs], lds, batch_rows(args), st)) !=
+      hipSuccess)
     return hip_fail(e, "batched evaluation launch");
   return DSM_OK;
 }
@@ -767,6 +777,7 @@ dsm_status dsm_batch_set_jobs(dsm_batch* b, int32_t n_jobs, const dsm_partial_jo
   b->set_per_xcd = n_jobs > 0 ? off[n_jobs] : 0;
   b->set_total_finish = n_jobs > 0 ? foff[n_jobs] : 0;
   b->set_lds = lds;
+  b->set_rows = batch_rows(args);
   b->set_n = n_jobs;
   return DSM_OK;
 }
@@ -782,7 +793,8 @@ dsm_status dsm_batch_run(dsm_batch* b, void* stream) {
     if (e == hipSuccess && q.order) e = launch_order(q.F, q.aff_cnt, q.order, st);
     if (e != hipSuccess) return hip_fail(e, "affected-set launch");
   }
-  e = launch_eval_batch(b->d_set_jobs, b->d_set_off, b->set_n, b->set_per_xcd, b->set_total_finish, b->set_lds, st);
+  e = launch_eval_batch(b->d_set_jobs, b->d_set_off, b->set_n, b->set_per_xcd, b->set_total_finish, b->set_lds,
+                        b->set_rows, st);
   return e == hipSuccess ? DSM_OK : hip_fail(e, "batched evaluation launch");
 }
 

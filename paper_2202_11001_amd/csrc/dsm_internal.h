@@ -80,6 +80,8 @@ struct EvalArgs {
   int S;                 // solutions
   int G;                 // groups: FOS elements (partial) or tetrahedron chunks (full)
   int partial;           // 1: partial evaluation, 0: full evaluation
+  int row_pairs;         // 1: the sweep's rows alternate between the slices of a pair (dsm_set_row_order);
+                         // placed in the padding before X, so the fields after it keep their offsets
   const float* X;        // [S][2][P][3]
   const int* fos_off;    // partial only
   const int* fos_pts;
@@ -99,7 +101,6 @@ struct EvalArgs {
   double* simws;         // swept dissimilarity workspace of the problem
   int pchunk;            // partial: affected tetrahedra per workgroup
   int nchunk;            // partial: workgroups (chunks of pchunk affected tetrahedra) per group
-  int row_pairs;         // 1: the sweep's rows alternate between the slices of a pair (dsm_set_row_order)
   uint32_t* cflags;      // partial: [S][G][nchunk] constraint flags per chunk
   uint32_t* ccount;      // partial: [S][G][nchunk] candidate voxel count per chunk
 };
@@ -131,9 +132,10 @@ hipError_t launch_order(int G, const int* aff_cnt, int* order, hipStream_t strea
 // wg_off_dev [2][n_jobs + 1]: the jobs' per-XCD slot offsets in the sweep (a
 // job of n workgroups takes ceil(n / 8) slots on each XCD; per_xcd slots in
 // all), then their workgroup offsets in the finishing kernel (a job of n
-// pairs takes ceil(n / kFinishPairs) workgroups; total_finish in all)
+// pairs takes ceil(n / kFinishPairs) workgroups; total_finish in all).  rows:
+// 0 every job's rows by slice, 1 every job's by slice pair, 2 both occur.
 hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int per_xcd, int total_finish,
-                             size_t lds, hipStream_t stream);
+                             size_t lds, int rows, hipStream_t stream);
 hipError_t launch_full_reduce(const DevProblem& pr, int S, const double* terms, double* obj, hipStream_t stream);
 hipError_t launch_owner(const DevProblem& pr, const float* Xg, int* owner, int* overlap, hipStream_t stream);
 // Piecewise-affine map of one solution X2 [2][P][3] at every voxel of image own:

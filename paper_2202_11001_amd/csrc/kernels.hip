@@ -297,9 +297,10 @@ __device__ void setup_task(const float* xo, const float* xt, const int D[3], int
 // [ya, yb] is slice k's row range; with pairs, lane ^ 1 holds slice k + 1's
 // (called on both lanes).  Returns the group's first y in gya and its number of
 // candidate rows in cnt (0 on lanes that start no group).
-__device__ __forceinline__ void group_rows(int ya, int yb, int k, int nz, int pairs, int& gya, int& cnt) {
+template <int kPairs>
+__device__ __forceinline__ void group_rows(int ya, int yb, int k, int nz, int& gya, int& cnt) {
   int lo = ya, hi = yb, m = 1;
-  if (pairs) {
+  if (kPairs) {
     const int oya = __shfl_xor(ya, 1, 64), oyb = __shfl_xor(yb, 1, 64);
     if (k + 1 < nz) {
       m = 2;
@@ -310,33 +311,32 @@ __device__ __forceinline__ void group_rows(int ya, int yb, int k, int nz, int pa
     }
   }
   gya = hi >= lo ? lo : 0;
-  cnt = (k & pairs) || k >= nz ? 0 : m * max(0, hi - lo + 1);
+  cnt = (k & kPairs) || k >= nz ? 0 : m * max(0, hi - lo + 1);
 }
 
-__device__ void setup_slices(const float* xo, const float* xt, const int D[3], int lane, int pairs, RasterTet& rt) {
+__device__ void setup_slices(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
   const int nz = rt.nz;
   if (nz <= kMaxSlices) {
-    // candidate rows of the row group starting at slice zlo + lane,
-    // prefix-summed over the groups
-    int ya = 0, yb = -1;
+    // candidate rows of slice zlo + lane, prefix-summed over the slices
+    int cnt = 0, ya = 0;
     if (lane < nz) {
       float L[4][3];
       for (int q = 0; q < 4; ++q)
         for (int c = 0; c < 3; ++c) L[q][c] = (xo[3 * q + c] + 0.5f) * 128.f;
+      int yb;
       slice_rows(L, rt.zlo + lane, D[1], ya, yb);
+      cnt = max(0, yb - ya + 1);
     }
-    int gya, cnt;
-    group_rows(ya, yb, lane, nz, pairs, gya, cnt);
     const int incl = wave_incl_scan(cnt);
-    if (lane < nz && !(lane & pairs)) {
-      rt.rs[lane >> pairs] = (unsigned short)(incl - cnt);
-      rt.y0[lane >> pairs] = (unsigned short)gya;
+    if (lane < nz) {
+      rt.rs[lane] = (unsigned short)(incl - cnt);
+      rt.y0[lane] = (unsigned short)ya;
     }
     if (lane == 63) {
-      rt.rs[(nz + pairs) >> pairs] = (unsigned short)incl;
+      rt.rs[min(nz, kMaxSlices)] = (unsigned short)incl;
       rt.nrows = incl;
       rt.sliced = 1;
-      rt.pairs = pairs;
+      rt.pairs = 0;
     }
   } else if (lane == 0) {
     rt.nrows = nz * rt.ny;
@@ -353,9 +353,11 @@ __device__ void setup_slices(const float* xo, const float* xt, const int D[3], i
 // setup_slices on a group of 16 lanes (one DPP row, `sub` = lane within the
 // group; all 16 lanes call it) for tetrahedra of few slices: slices in rounds of
 // 16, the candidate-row prefix carried from round to round.  Returns the number
-// of rows (on every lane of the group).
-__device__ int setup_slices16(const float* xo, const float* xt, const int D[3], int lane, int sub, int pairs,
-                              RasterTet& rt) {
+// of rows (on every lane of the group).  kPairs: row groups of slice pairs
+// (group_rows).
+template <int kPairs>
+__device__ int setup_slices16(const float* xo, const float* xt, const int D[3], int lane, int sub, RasterTet& rt) {
+  constexpr int pairs = kPairs;
   const int nz = rt.nz;
   int nrows;
   if (nz <= kMaxSlices) {
@@ -368,7 +370,7 @@ __device__ int setup_slices16(const float* xo, const float* xt, const int D[3], 
       int ya = 0, yb = -1;
       if (k < nz) slice_rows(L, rt.zlo + k, D[1], ya, yb);
       int gya, cnt;
-      group_rows(ya, yb, k, nz, pairs, gya, cnt);
+      group_rows<kPairs>(ya, yb, k, nz, gya, cnt);
       const int incl = row16_incl_scan(cnt);
       if (k < nz && !(k & pairs)) {
         rt.rs[k >> pairs] = (unsigned short)(carry + incl - cnt);
@@ -402,7 +404,7 @@ __device__ int setup_slices16(const float* xo, const float* xt, const int D[3], 
 __device__ void setup_raster(const float* xo, const float* xt, const int D[3], int lane, RasterTet& rt) {
   if (lane < kSetupTasks) setup_task(xo, xt, D, lane, rt);
   wave_sync();
-  setup_slices(xo, xt, D, lane, 0, rt);
+  setup_slices(xo, xt, D, lane, rt);
 }
 
 // Exact x-span [x0, x1] (inclusive; empty if x0 > x1) of voxel row (y, z).
@@ -461,8 +463,10 @@ struct WaveRows {
 // element that holds the first row's voxel, so the two rows share the own
 // image's cache lines).  The mapped position of the first voxel is
 // P0 + J (x0, y, z) + shift.  *my_start receives the first voxel index of this
-// lane's row, or a large negative value if it is empty.
-template <bool kOwnBytes>
+// lane's row, or a large negative value if it is empty.  kPairs must equal
+// rt.pairs (a compile-time copy, so that the slice-by-slice order pays
+// nothing for the other).
+template <bool kOwnBytes, int kPairs>
 __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, const int D[3], int sy, int sz,
                                           int base, float shift, WaveRows& wr, int* my_start) {
   const int r0 = b * 64, r = r0 + lane;
@@ -473,27 +477,31 @@ __device__ __forceinline__ int build_rows(const RasterTet& rt, int b, int lane, 
     // lane k holds row group k's first candidate row and first y; row r lies
     // in the last group that starts at or before r: the group of the unit's
     // first row, advanced over the groups that start inside the unit (in order)
-    const int nz = rt.nz, pairs = rt.pairs, ng = (nz + pairs) >> pairs;
+    const int nz = rt.nz, ng = (nz + kPairs) >> kPairs;
     const int rsk = lane < ng ? (int)rt.rs[lane] : 0x7fffffff;
     const int y0k = lane < ng ? (int)rt.y0[lane] : 0;
-    int k = __popcll(__ballot(rsk <= r0)) - 1;  // rs[0] = 0
-    int s = __builtin_amdgcn_readlane(rsk, k), ys = __builtin_amdgcn_readlane(y0k, k);
+    // row r of group k (uniform), which starts at row s with y = ys
+    auto place = [&](int k, int s, int ys) {
+      const int rr = r - s;
+      if (kPairs) {
+        const int two = 2 * k + 1 < nz ? 1 : 0;  // the group is a pair of slices
+        h = rr & two;
+        y = ys + (rr >> two);
+        z = rt.zlo + 2 * k + h;
+      } else {
+        y = ys + rr;
+        z = rt.zlo + k;
+      }
+    };
+    const int jb = __popcll(__ballot(rsk <= r0)) - 1;  // rs[0] = 0
+    place(jb, __builtin_amdgcn_readlane(rsk, jb), __builtin_amdgcn_readlane(y0k, jb));
     unsigned long long inside = __ballot(rsk > r0 && rsk < r0 + 64);
     while (inside) {
-      const int kk = __builtin_ctzll(inside);
+      const int k = __builtin_ctzll(inside);
       inside &= inside - 1;
-      const int ss = __builtin_amdgcn_readlane(rsk, kk);
-      if (r >= ss) {
-        s = ss;
-        ys = __builtin_amdgcn_readlane(y0k, kk);
-        k = kk;
-      }
+      const int s = __builtin_amdgcn_readlane(rsk, k);
+      if (r >= s) place(k, s, __builtin_amdgcn_readlane(y0k, k));
     }
-    const int two = pairs && 2 * k + 1 < nz ? 1 : 0;  // the group is a pair of slices
-    const int rr = r - s;
-    h = rr & two;
-    y = ys + (rr >> two);
-    z = rt.zlo + (k << pairs) + h;
   } else {
     y = rt.ylo + r % rt.ny;
     z = rt.zlo + r / rt.ny;
@@ -804,15 +812,20 @@ __device__ __forceinline__ int group_tet(const EvalArgs& a, int g, int i) {
 // region in L2; with `interleave` the groups follow interleaved_group's order.
 // Partial mode also writes the chunk's constraint flags and
 // candidate voxel count to cflags / ccount [S][G][nchunk]; k_finish combines
-// them.
-template <int PARTIAL>
+// them.  ROWS: the row order, 0 slice by slice, 1 in slice pairs (both fixed
+// at compile time), 2 a.row_pairs read at run time (a batch of problems with
+// both orders).
+template <int PARTIAL, int ROWS>
 __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsigned char* smem, bool interleave) {
   double* __restrict__ simws = a.simws;
   const DevProblem& pr = a.pr;
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   const int nchunk = PARTIAL ? a.nchunk : 1;
   const int gl = logical / (a.S * nchunk), rem = logical - gl * (a.S * nchunk);
-  const int g = PARTIAL && a.order ? a.order[gl] : (interleave ? interleaved_group(gl, a.G) : gl);
+  // g and the counts below are the same on every lane; saying so keeps the
+  // values derived from them (the direction of an entry, hence the image
+  // buffer a load reads) in scalar registers
+  const int g = uniform(PARTIAL && a.order ? a.order[gl] : (interleave ? interleaved_group(gl, a.G) : gl));
   const int c = rem / a.S, s = rem - c * a.S;
   const int nver = a.nver;
   const EvalLayout Lay = eval_layout(kMaxChunk, nver);
@@ -826,7 +839,7 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   __shared__ unsigned s_count[kWaves];
 
   // this chunk's tetrahedra: slots [i0, i0 + na) of the group
-  const int na_all = PARTIAL ? a.aff_cnt[g] : min(kFullChunk, pr.T - g * kFullChunk);
+  const int na_all = uniform(PARTIAL ? a.aff_cnt[g] : min(kFullChunk, pr.T - g * kFullChunk));
   const int i0 = c * (PARTIAL ? a.pchunk : kFullChunk);
   if (na_all <= i0) return;  // malformed element (count -1) or no tetrahedra in this chunk: k_finish sets the flags
   if (PARTIAL && a.mask && a.mask[(size_t)s * a.G + g] == 0) return;  // not requested
@@ -910,7 +923,11 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     if (e < nent && s_units[e]) {
       int own;
       const float* xyz = entry_xyz(e, own);
-      nunits = (setup_slices16(xyz + own * 12, xyz + (1 - own) * 12, pr.D, lane, sub, a.row_pairs, s_rts[e]) + 63) >> 6;
+      const float *xo = xyz + own * 12, *xt = xyz + (1 - own) * 12;
+      const int nrows = ROWS == 2 ? (a.row_pairs ? setup_slices16<1>(xo, xt, pr.D, lane, sub, s_rts[e])
+                                                 : setup_slices16<0>(xo, xt, pr.D, lane, sub, s_rts[e]))
+                                  : setup_slices16<ROWS>(xo, xt, pr.D, lane, sub, s_rts[e]);
+      nunits = (nrows + 63) >> 6;
     }
     wave_sync();
     if (e < nent && sub == 0) s_units[e] = nunits;
@@ -958,7 +975,9 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
     }
     const int b = u - uniform(s_units[cur]);
     int my_start;
-    const int nvox = uniform(build_rows<true>(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
+    const int nvox = uniform(ROWS == 2 ? (rtp->pairs ? build_rows<true, 1>(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start)
+                                                     : build_rows<true, 0>(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start))
+                                        : build_rows<true, ROWS>(*rtp, b, lane, pr.D, pr.ex, pr.exy, own_base, 1.0f, wr, &my_start));
     int carry = 0;  // non-empty rows that start before the current chunk
     for (int q0 = 0; q0 < nvox; q0 += 128) {
       // voxels q0 + lane and q0 + 64 + lane: rows starting in this pair of
@@ -1010,10 +1029,10 @@ __device__ __forceinline__ void sweep_body(const EvalArgs& a, int logical, unsig
   }
 }
 
-template <int PARTIAL>
+template <int PARTIAL, int ROWS>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_sweep(EvalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sweep_body<PARTIAL>(a, xcd_logical(blockIdx.x, a.S * a.G * (PARTIAL ? a.nchunk : 1)), smem, PARTIAL != 0);
+  sweep_body<PARTIAL, ROWS>(a, xcd_logical(blockIdx.x, a.S * a.G * (PARTIAL ? a.nchunk : 1)), smem, PARTIAL != 0);
 }
 
 // Several problems in one launch.  Each job's workgroup range is split into 8
@@ -1026,7 +1045,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // together.  Elements follow interleaved_group's order within a job.
 // Arguments read through the job table take more registers than kernel
 // arguments; the 7-wave target (at most 72 VGPRs) ran small problems 5 %
-// faster than 6 waves.
+// faster than 6 waves.  ROWS as for sweep_body.
+template <int ROWS>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_batch(
     const EvalArgs* __restrict__ jobs, const int* __restrict__ xcd_off, int n_jobs) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1038,7 +1058,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
   const int n8 = uniform(xcd_off[j + 1] - xcd_off[j]);
   const int logical = x * n8 + (k - uniform(xcd_off[j]));
   if (logical >= a.S * a.G * a.nchunk) return;
-  sweep_body<1>(a, logical, smem, true);
+  sweep_body<1, ROWS>(a, logical, smem, true);
 }
 
 // ------------------------------------------------------------ finishing kernel
@@ -1338,7 +1358,7 @@ __global__ __launch_bounds__(kWG) void k_owner(DevProblem pr, const float* __res
   for (int b = wave; b < nb; b += kWaves) {
     WaveRows& wr = rows[wave];
     int my_start;
-    const int nvox = build_rows<false>(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
+    const int nvox = build_rows<false, 0>(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
     int carry = 0;
     for (int q0 = 0; q0 < nvox; q0 += 64) {
       wr.marker[lane] = 0;
@@ -1428,7 +1448,7 @@ __global__ __launch_bounds__(kWG) void k_transform(DevProblem pr, int own, const
   for (int b = wave; b < nb; b += kWaves) {
     WaveRows& wr = rows[wave];
     int my_start;
-    const int nvox = build_rows<false>(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
+    const int nvox = build_rows<false, 0>(rt, b, lane, pr.D, pr.D[0], pr.DxDy, 0, 0.0f, wr, &my_start);
     int carry = 0;
     for (int q0 = 0; q0 < nvox; q0 += 64) {
       wr.marker[lane] = 0;
@@ -1579,10 +1599,14 @@ hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end
   if (nwg <= 0) return hipSuccess;
   const size_t lds = eval_lds_bytes(kMaxChunk, a.nver);
   if (ev_begin) (void)hipEventRecord(ev_begin, stream);
-  if (a.partial)
-    k_sweep<1><<<(unsigned)(nwg * a.nchunk), kWG, lds, stream>>>(a);
+  if (a.partial && a.row_pairs)
+    k_sweep<1, 1><<<(unsigned)(nwg * a.nchunk), kWG, lds, stream>>>(a);
+  else if (a.partial)
+    k_sweep<1, 0><<<(unsigned)(nwg * a.nchunk), kWG, lds, stream>>>(a);
+  else if (a.row_pairs)
+    k_sweep<0, 1><<<(unsigned)nwg, kWG, lds, stream>>>(a);
   else
-    k_sweep<0><<<(unsigned)nwg, kWG, lds, stream>>>(a);
+    k_sweep<0, 0><<<(unsigned)nwg, kWG, lds, stream>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end) (void)hipEventRecord(ev_end, stream);
@@ -1591,9 +1615,15 @@ hipError_t launch_eval(const EvalArgs& a, hipEvent_t ev_begin, hipEvent_t ev_end
 }
 
 hipError_t launch_eval_batch(const EvalArgs* jobs_dev, const int* wg_off_dev, int n_jobs, int per_xcd, int total_finish,
-                             size_t lds, hipStream_t stream) {
+                             size_t lds, int rows, hipStream_t stream) {
   if (per_xcd <= 0) return hipSuccess;
-  k_sweep_batch<<<(unsigned)(8 * per_xcd), kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs);
+  const unsigned nwg = (unsigned)(8 * per_xcd);
+  if (rows == 0)
+    k_sweep_batch<0><<<nwg, kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs);
+  else if (rows == 1)
+    k_sweep_batch<1><<<nwg, kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs);
+  else
+    k_sweep_batch<2><<<nwg, kWG, lds, stream>>>(jobs_dev, wg_off_dev, n_jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_finish_batch<<<(unsigned)total_finish, 64, 0, stream>>>(jobs_dev, wg_off_dev + (n_jobs + 1), n_jobs);
