@@ -279,7 +279,8 @@ def test_determinism():
 def test_batched_all_pairs():
     """64^3 blurred-ellipsoid pair, 5^3 meshes, 96 solutions x 125 single-point
     elements in one launch; the oracle recomputes every full evaluation and
-    every one of the 12,000 (solution, element) pairs."""
+    every one of the 12,000 (solution, element) pairs, against which both
+    row orders of the sweep are checked."""
     w = W.batched()
     rp = oracle_problem(w)
     X = feasible_population(w, rp)
@@ -308,13 +309,27 @@ def test_batched_all_pairs():
     vcs = vc.cpu().numpy().astype(np.int64)
     allok = (flg == 0).all(axis=1)
     assert np.all(vcs[allok].sum(axis=1) == 8 * gp.V)
+    _say("batched: rows in slice pairs")
+    gp.set_row_order(1)
+    obj, flags = gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(flags.cpu().numpy().astype(np.uint32), rflags)
+    assert_objectives_close(obj.cpu().numpy(), robj, what="full objectives, slice pairs")
+    np.testing.assert_array_equal(fl.cpu().numpy().astype(np.uint32), rfl)
+    np.testing.assert_array_equal(vc.cpu().numpy()[flg == 0], rnv[flg == 0])
+    assert_objectives_close(new.cpu().numpy(), rnew, flags=flg, what="part_new, slice pairs")
+    assert_objectives_close(old.cpu().numpy(), rold, what="part_old, slice pairs")
 
 
 def test_clinical_full_size_all_elements():
     """512x512x100 clinical-shaped workload in the benchmark's launch
     configuration (512 solutions x 600 single-point elements in one launch,
     cached old terms); the oracle recomputes the full evaluation and all 600
-    elements (every star size, 2 to 48 tetrahedra) of 4 solutions."""
+    elements (every star size, 2 to 48 tetrahedra) of 4 solutions.  Checked
+    with the defaults (8 tetrahedra per workgroup, rows by slice) and with the
+    setting the benchmark's autotuners keep on this workload (4, slice
+    pairs)."""
     w = W.clinical()
     _say(f"clinical full size {w.name}")
     gp = _gpu_problem(w, w.S)
@@ -346,6 +361,18 @@ def test_clinical_full_size_all_elements():
     np.testing.assert_array_equal(vcs[sols][g_fl == 0], rnv[g_fl == 0])
     assert_objectives_close(new.cpu().numpy()[sols], rnew, flags=g_fl, what="part_new")
     assert_objectives_close(old.cpu().numpy()[sols], rold, what="part_old")
+    assert_delta_close(old.cpu().numpy()[sols], new.cpu().numpy()[sols], rold, rnew, g_fl)
+    _say("clinical: chunk 4, rows in slice pairs")
+    gp.set_part_chunk(4)
+    gp.set_row_order(1)
+    obj, flags = gp.eval_full(Xd, tet_terms=cache)
+    old, new, fl, vc = gp.eval_partial(Xd, _t(off), _t(pts), _t(cand), tet_terms_in=cache, voxel_count=True)
+    torch.cuda.synchronize()
+    assert_objectives_close(obj.cpu().numpy()[sols], robj, what="full objectives, slice pairs")
+    np.testing.assert_array_equal(fl.cpu().numpy().astype(np.uint32), fln)
+    np.testing.assert_array_equal(vc.cpu().numpy().astype(np.int64), vcs)
+    assert_objectives_close(new.cpu().numpy()[sols], rnew, flags=g_fl, what="part_new, chunk 4, slice pairs")
+    assert_objectives_close(old.cpu().numpy()[sols], rold, what="part_old, chunk 4, slice pairs")
     assert_delta_close(old.cpu().numpy()[sols], new.cpu().numpy()[sols], rold, rnew, g_fl)
 
 
