@@ -2,6 +2,7 @@
 symbol, validates host arguments before touching a device, and its host-side
 topology equals the oracle's (Sec. 2.1 split, Sec. 2.2 stars)."""
 import ctypes as C
+import os
 
 import numpy as np
 import pytest
@@ -137,3 +138,20 @@ def test_new_entry_points_validate_on_the_host():
                                  None, None, None) == dsm.ERR_ARG
     assert L.dsm_sample_estimated(None, 4, None, 1, None, 1, None, None, None, 1, None, None, None, 2.0, 0, 0,
                                   None, None, None) == dsm.ERR_ARG
+
+
+def test_tuning_settings_validate_on_the_host():
+    """The work-split and row-order settings and their autotuners reject a null
+    problem (and the getters report it) before any device work."""
+    L = dsm.lib()
+    assert L.dsm_set_part_chunk(None, 4) == dsm.ERR_ARG
+    assert L.dsm_get_part_chunk(None) == 0
+    assert L.dsm_set_row_order(None, 0) == dsm.ERR_ARG
+    assert L.dsm_get_row_order(None) == -1
+    assert L.dsm_autotune_chunk(None, 1, None, 1, None, None, None, None, 0, None, None, None) == dsm.ERR_ARG
+    assert L.dsm_autotune_row_order(None, 1, None, 1, None, None, None, None, None, None) == dsm.ERR_ARG
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "dsm.h")).read()
+    defs = dict(re.findall(r"#define (DSM_ROWS_\w+) (\d+)", hdr))
+    assert int(defs["DSM_ROWS_BY_SLICE"]) == dsm.Problem.ROWS_BY_SLICE == 0
+    assert int(defs["DSM_ROWS_BY_SLICE_PAIR"]) == dsm.Problem.ROWS_BY_SLICE_PAIR == 1
