@@ -702,11 +702,14 @@ def test_uneven_batch_graph_both_levels():
     configurations, enqueued by dsm_batch_run and captured together in one HIP
     graph: every replay (with eager work in between) equals the eager run bit
     for bit, the eager run equals one launch per problem, and every problem is
-    checked against the oracle on sampled pairs."""
+    checked against the oracle on sampled pairs.  Rows by slice at level 0 and
+    by slice pair at level 1, the orders the benchmark keeps."""
     idx = list(range(12))
     levels = []
     for level in (0, 1):
         probs = _uneven_level(level, idx)
+        for p in probs:
+            p[-1]["problem"].set_row_order(level)
         batch = dsm.Batch(max_jobs=len(probs))
         outs = batch.set_jobs([p[-1] for p in probs])
         levels.append((probs, batch, outs))
